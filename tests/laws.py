@@ -1,0 +1,403 @@
+"""Laws that pin the oracle: each check runs the oracle (or a variant build of
+it) on a small seeded system whose answer the paper and the mathematics fix,
+and returns (passed, statistic). The expected values never come from the
+oracle itself: they come from matrix exponentials of the chain's generator,
+binomial / hypergeometric / Poisson laws, mpmath closed forms, and integer
+bookkeeping of the event list.
+"""
+from __future__ import annotations
+
+import math
+from collections import defaultdict
+from fractions import Fraction
+
+import mpmath as mp
+import numpy as np
+from scipy import linalg, stats
+
+from farmnet import EXIT, ENTER, EXTERNAL, INTERNAL, synth
+from oracle import oracle as O
+
+P_MIN = 1e-4   # acceptance level of the goodness-of-fit tests (inputs are seeded)
+
+
+def gof(observed_counts, probs, min_expected=5.0):
+    """Pearson chi-square goodness of fit with sparse bins pooled. Returns p."""
+    obs = np.asarray(observed_counts, float)
+    p = np.asarray(probs, float)
+    n = obs.sum()
+    exp = n * p
+    big = exp >= min_expected
+    o = np.r_[obs[big], obs[~big].sum()]
+    e = np.r_[exp[big], exp[~big].sum()]
+    if e[-1] < min_expected:            # fold the pooled tail into the largest bin
+        j = np.argmax(e[:-1])
+        o[j] += o[-1]; e[j] += e[-1]
+        o, e = o[:-1], e[:-1]
+    stat = ((o - e) ** 2 / e).sum()
+    return float(stats.chi2.sf(stat, len(e) - 1))
+
+
+# ---------------------------------------------------------------------------
+# SSA law: pure recovery is a binomial thinning (each infected animal recovers
+# independently at rate gamma), so I(t) ~ Bin(I0, exp(-gamma t)).
+# ---------------------------------------------------------------------------
+
+def check_sis_decay(lib_path=None):
+    p = synth.sis_decay(n_nodes=4000, I0=20, gamma=0.3, n_days=3)
+    r = O.run(p, record_days=[0, 1, 2], lib_path=lib_path)
+    pv = []
+    for d in range(3):
+        I = r["snap_u"][d, 0, :, 1]
+        q = math.exp(-0.3 * (d + 1))
+        pv.append(gof(np.bincount(I, minlength=21), stats.binom.pmf(np.arange(21), 20, q)))
+    return min(pv) > P_MIN, min(pv)
+
+
+# ---------------------------------------------------------------------------
+# The paper's synthetic benchmark model (Sec. 4.2): S->I and I->S at rate 1 per
+# individual with S = I = 1000. lambda = S + I = 2000 never changes, so the
+# transitions of a node-day are Poisson(2000); each individual is a two-state
+# chain, so I(t) = Bin(1000, (1+e^-2t)/2) + Bin(1000, (1-e^-2t)/2).
+# ---------------------------------------------------------------------------
+
+def _flip_pmf(t, n=1000):
+    a = stats.binom.pmf(np.arange(n + 1), n, (1 + math.exp(-2 * t)) / 2)
+    b = stats.binom.pmf(np.arange(n + 1), n, (1 - math.exp(-2 * t)) / 2)
+    return np.convolve(a, b)
+
+
+def check_flip_state(lib_path=None):
+    p = synth.flip_model(n_nodes=3000, n_days=2)
+    r = O.run(p, record_days=[0, 1], lib_path=lib_path)
+    pv = []
+    for d in range(2):
+        I = r["snap_u"][d, 0, :, 1]
+        pmf = _flip_pmf(d + 1)
+        edges = np.arange(850, 1151, 10)
+        cdf = np.cumsum(pmf)
+        probs = np.diff(np.r_[0.0, cdf[edges[1:] - 1], 1.0])
+        counts = np.histogram(I, bins=np.r_[-1, edges[1:] - 0.5, 3000])[0]
+        pv.append(gof(counts, probs))
+    return min(pv) > P_MIN, min(pv)
+
+
+def check_flip_clock(lib_path=None):
+    p = synth.flip_model(n_nodes=1, n_days=2).with_replicates(3000)
+    r = O.run(p, lib_path=lib_path)
+    k = r["transitions"].ravel()
+    edges = np.arange(1850, 2151, 10)
+    probs = np.diff(np.r_[0.0, stats.poisson.cdf(edges[1:] - 1, 2000), 1.0])
+    counts = np.histogram(k, bins=np.r_[-1, edges[1:] - 0.5, 10**9])[0]
+    pv = gof(counts, probs)
+    return pv > P_MIN, pv
+
+
+# ---------------------------------------------------------------------------
+# Exact master equation of a two-node system over whole days: the per-node
+# chain over [d, d+1) with phi frozen (eq:numstep3) is exp(Q), the events are
+# exact hypergeometric draws in list order (eq:numstep4), and phi follows the
+# Euler step (eq:numstep5) from the post-event state (two_node_exact) or, for
+# the alternative reading, from the pre-event state (two_node_exact_pre).
+# ---------------------------------------------------------------------------
+
+def _sis_day_matrix(n, inf_rate_per_s, gamma):
+    Q = np.zeros((n + 1, n + 1))
+    for I in range(n + 1):
+        S = n - I
+        a, b = inf_rate_per_s * S, gamma * I
+        if I < n:
+            Q[I, I + 1] = a
+        if I > 0:
+            Q[I, I - 1] = b
+        Q[I, I] = -(a + b)
+    return linalg.expm(Q)
+
+
+def _hyper(S, I, n):
+    """P(i infected among n drawn without replacement from S susceptible, I infected)."""
+    tot = math.comb(S + I, n)
+    return {i: math.comb(I, i) * math.comb(S, n - i) / tot
+            for i in range(max(0, n - S), min(n, I) + 1)}
+
+
+def two_node_exact(p):
+    ups, gam = p.coef[0]
+    alpha, beta = p.alpha[0], p.beta[0]
+    ev = list(zip(p.ev_day, p.ev_kind, p.ev_node, p.ev_dest, p.ev_n, p.ev_select))
+    dist = {(tuple(map(int, p.u0.ravel())), tuple(map(float, p.v0))): 1.0}
+    marg = []
+    for d in range(p.n_days):
+        new = defaultdict(float)
+        for (x, phi), pr in dist.items():
+            # stochastic step per node
+            rows = []
+            for k in range(2):
+                S, I = x[2 * k], x[2 * k + 1]
+                M = _sis_day_matrix(S + I, ups * phi[k], gam)
+                rows.append(M[I])
+            for I0n, p0 in enumerate(rows[0]):
+                for I1n, p1 in enumerate(rows[1]):
+                    if p0 * p1 == 0.0:
+                        continue
+                    n0, n1 = x[0] + x[1], x[2] + x[3]
+                    y = (n0 - I0n, I0n, n1 - I1n, I1n)
+                    new[(y, phi)] += pr * p0 * p1
+        dist = new
+        # events of day d in list order
+        pre_x = {}
+        for e in [e for e in ev if e[0] == d]:
+            _, kind, node, dest, n, sel = map(int, e)
+            new = defaultdict(float)
+            for (x, phi), pr in dist.items():
+                x = list(x)
+                if kind == ENTER:
+                    x[2 * node] += n
+                    new[(tuple(x), phi)] += pr
+                    continue
+                S, I = x[2 * node], x[2 * node + 1]
+                for i, ph in _hyper(S, I, n).items():
+                    y = list(x)
+                    y[2 * node] -= n - i
+                    y[2 * node + 1] -= i
+                    if kind == EXTERNAL:
+                        y[2 * dest] += n - i
+                        y[2 * dest + 1] += i
+                    new[(tuple(y), phi)] += pr * ph
+            dist = new
+        # phi update
+        new = defaultdict(float)
+        for (x, phi), pr in dist.items():
+            nphi = []
+            for k in range(2):
+                S, I = x[2 * k], x[2 * k + 1]
+                nphi.append((1.0 - beta[0]) * phi[k] + (alpha * I / (S + I) if S + I > 0 else 0.0))
+            new[(x, tuple(nphi))] += pr
+        dist = new
+        m = defaultdict(float)
+        for (x, _), pr in dist.items():
+            m[x] += pr
+        marg.append(dict(m))
+    return marg
+
+
+def two_node_exact_pre(p):
+    """Alternative reading: phi from the pre-event (post-SSA) state."""
+    ups, gam = p.coef[0]
+    alpha, beta = p.alpha[0], p.beta[0]
+    ev = list(zip(p.ev_day, p.ev_kind, p.ev_node, p.ev_dest, p.ev_n, p.ev_select))
+    dist = {(tuple(map(int, p.u0.ravel())), tuple(map(float, p.v0))): 1.0}
+    marg = []
+    for d in range(p.n_days):
+        new = defaultdict(float)
+        for (x, phi), pr in dist.items():
+            rows = [_sis_day_matrix(x[2 * k] + x[2 * k + 1], ups * phi[k], gam)[x[2 * k + 1]] for k in range(2)]
+            for I0n, p0 in enumerate(rows[0]):
+                for I1n, p1 in enumerate(rows[1]):
+                    if p0 * p1 == 0.0:
+                        continue
+                    n0, n1 = x[0] + x[1], x[2] + x[3]
+                    y = (n0 - I0n, I0n, n1 - I1n, I1n)
+                    nphi = tuple((1.0 - beta[0]) * phi[k] +
+                                 (alpha * y[2 * k + 1] / (y[2 * k] + y[2 * k + 1]) if y[2 * k] + y[2 * k + 1] else 0.0)
+                                 for k in range(2))
+                    new[(y, nphi)] += pr * p0 * p1
+        dist = new
+        for e in [e for e in ev if e[0] == d]:
+            _, kind, node, dest, n, sel = map(int, e)
+            new = defaultdict(float)
+            for (x, phi), pr in dist.items():
+                x = list(x)
+                if kind == ENTER:
+                    x[2 * node] += n
+                    new[(tuple(x), phi)] += pr
+                    continue
+                S, I = x[2 * node], x[2 * node + 1]
+                for i, ph in _hyper(S, I, n).items():
+                    y = list(x)
+                    y[2 * node] -= n - i
+                    y[2 * node + 1] -= i
+                    if kind == EXTERNAL:
+                        y[2 * dest] += n - i
+                        y[2 * dest + 1] += i
+                    new[(tuple(y), phi)] += pr * ph
+            dist = new
+        m = defaultdict(float)
+        for (x, _), pr in dist.items():
+            m[x] += pr
+        marg.append(dict(m))
+    return marg
+
+
+TWO_NODE_KW = dict(n_days=3, upsilon=0.9, gamma=0.4, alpha=1.0, beta=(0.3, 0.3, 0.3, 0.3),
+                   u0=((3, 1), (2, 0)), phi0=(1.6, 0.0))
+
+
+def two_node_samples(R=200000, lib_path=None):
+    p = synth.two_node(**TWO_NODE_KW).with_replicates(R)
+    r = O.run(p, record_days=[0, 1, 2], lib_path=lib_path)
+    return p, r["snap_u"]  # [day, R, 2, 2]
+
+
+def two_node_pvalues(snap, marg):
+    pv = []
+    for d, m in enumerate(marg):
+        keys = sorted(m)
+        index = {k: i for i, k in enumerate(keys)}
+        x = snap[d].reshape(snap.shape[1], 4)
+        counts = np.zeros(len(keys) + 1)
+        for row, c in zip(*np.unique(x, axis=0, return_counts=True)):
+            counts[index.get(tuple(int(v) for v in row), len(keys))] += c
+        probs = np.r_[[m[k] for k in keys], 0.0]
+        if counts[-1] > 0:          # a state the exact law gives probability 0
+            pv.append(0.0)
+            continue
+        pv.append(gof(counts[:-1], probs[:-1] / probs[:-1].sum()))
+    return pv
+
+
+def check_two_node(lib_path=None, R=200000):
+    p, snap = two_node_samples(R, lib_path)
+    pv = two_node_pvalues(snap, two_node_exact(p))
+    return min(pv) > P_MIN, min(pv)
+
+
+# ---------------------------------------------------------------------------
+# phi with I/N constant (all rates zero, no events): within a season beta is
+# constant and phi_n = (1-beta)^n phi_0 + alpha c (1 - (1-beta)^n) / beta.
+# ---------------------------------------------------------------------------
+
+def season_table(path):
+    rows = [tuple(map(int, l.split())) for l in open(path) if l.strip() and not l.startswith("#")]
+    return dict(rows)
+
+
+def paper_season(t):
+    """Quarter of beta(t) from the inequalities printed in Sec. 4.1."""
+    doy = t % 365
+    return 0 if doy <= 91 else 1 if doy <= 182 else 2 if doy <= 273 else 3
+
+
+def phi_closed_form(phi0, c, alpha, betas, day0, n_steps):
+    """phi after each of n_steps Euler steps, segment by segment in mpmath."""
+    mp.mp.dps = 40
+    out = []
+    phi = mp.mpf(phi0)
+    seg_start_phi, seg_len, seg_q = phi, 0, paper_season(day0)
+    for k in range(n_steps):
+        q = paper_season(day0 + k)
+        if q != seg_q:
+            b = mp.mpf(betas[seg_q])
+            a = (1 - b) ** seg_len
+            seg_start_phi = a * seg_start_phi + mp.mpf(alpha) * c * (1 - a) / b
+            seg_len, seg_q = 0, q
+        seg_len += 1
+        b = mp.mpf(betas[seg_q])
+        a = (1 - b) ** seg_len
+        out.append(a * seg_start_phi + mp.mpf(alpha) * c * (1 - a) / b)
+    return out
+
+
+def check_phi_closed_form(lib_path=None, day0=0, n_days=400):
+    beta = (0.10, 0.12, 0.10, 0.08)
+    p = synth.constant_infection(n_days=n_days, day0=day0, beta=beta, alpha=0.7)
+    r = O.run(p, record_days=np.arange(n_days), lib_path=lib_path)
+    worst = 0.0
+    for i in range(p.n_nodes):
+        S, I = p.u0[i]
+        c = mp.mpf(int(I)) / (int(S) + int(I)) if S + I > 0 else mp.mpf(0)
+        exact = phi_closed_form(p.v0[i], c, 0.7, [mp.mpf(b) for b in beta], day0, n_days)
+        got = r["snap_v"][:, 0, i]
+        for g, e in zip(got, exact):
+            if e != 0:
+                worst = max(worst, float(abs((mp.mpf(g) - e) / e)))
+            elif g != 0:
+                worst = max(worst, 1.0)
+    return worst <= 1e-12, worst
+
+
+# ---------------------------------------------------------------------------
+# Events
+# ---------------------------------------------------------------------------
+
+def check_hypergeometric(lib_path=None, n_nodes=6000):
+    """EXIT of 4 animals from (S, I) = (7, 5): the infected count removed is
+    Hypergeometric(12, 5, 4)."""
+    u0 = np.tile([[7, 5]], (n_nodes, 1))
+    ev = [(0, EXIT, np.arange(n_nodes), -1, 4, 1, -1)]
+    p = synth.events_only(u0, ev, n_days=1)
+    r = O.run(p, lib_path=lib_path)
+    removed_I = 5 - r["u"][0, :, 1]
+    pmf = stats.hypergeom.pmf(np.arange(5), 12, 5, 4)
+    pv = gof(np.bincount(removed_I, minlength=5)[:5], pmf)
+    return pv > P_MIN and (r["u"] >= 0).all(), pv
+
+
+def check_multivariate_walk(lib_path=None, n_nodes=6000):
+    """EXIT of 3 from the selection {S1, S2, I2} holding (4, 5, 3), with 6
+    animals in the unselected I1 between them: the composition is multivariate
+    hypergeometric and I1 is never touched."""
+    m = synth.sise3_model(coef=np.zeros(6))
+    E = np.zeros((6, 1), np.int32)
+    sel = [0, 2, 3]
+    E[sel, 0] = 1
+    u0 = np.zeros((n_nodes, 6), np.int64)
+    u0[:, 0], u0[:, 1], u0[:, 2], u0[:, 3] = 4, 6, 5, 3
+    z = np.zeros(n_nodes, np.int32)
+    from farmnet import Problem
+    m.update(E=E)
+    p = Problem(n_nodes=n_nodes, n_rep=1, n_days=1, u0=u0, v0=np.zeros(n_nodes),
+                ev_day=z, ev_kind=z + EXIT, ev_node=np.arange(n_nodes), ev_dest=z - 1, ev_n=z + 3,
+                ev_select=z, ev_shift=z - 1, **m)
+    r = O.run(p, lib_path=lib_path)
+    taken = np.array([4, 5, 3]) - r["u"][0][:, sel]
+    keys, counts = np.unique(taken, axis=0, return_counts=True)
+    probs = [stats.multivariate_hypergeom.pmf(k, [4, 5, 3], 3) for k in keys]
+    ok_support = (taken.sum(axis=1) == 3).all() and (taken >= 0).all() and (r["u"][0][:, 1] == 6).all()
+    if not ok_support:
+        return False, 0.0
+    pv = gof(counts, np.array(probs) / np.sum(probs))
+    return pv > P_MIN and abs(np.sum(probs) - 1.0) < 1e-9, pv
+
+
+def class_totals_replay(p):
+    """Per node and class, the deterministic animal count after all events:
+    SSA transitions never move an animal between classes, so only the events
+    change these totals (integer bookkeeping)."""
+    if p.n_comp == 2:
+        cls_of = np.array([0, 0])
+    else:
+        cls_of = np.array([0, 0, 1, 1, 2, 2])
+    ncls = cls_of.max() + 1
+    T = np.zeros((p.n_nodes, ncls), np.int64)
+    np.add.at(T, (np.repeat(np.arange(p.n_nodes), p.n_comp), np.tile(cls_of, p.n_nodes)), p.u0.ravel())
+    for d, kind, node, dest, n, sel, sh in zip(p.ev_day, p.ev_kind, p.ev_node, p.ev_dest, p.ev_n,
+                                              p.ev_select, p.ev_shift):
+        comps = np.flatnonzero(p.E[:, sel])
+        c = cls_of[comps[0]]
+        if kind == ENTER:
+            T[node, c] += n
+        elif kind == EXIT:
+            T[node, c] -= n
+        elif kind == INTERNAL:
+            T[node, c] -= n
+            T[node, cls_of[comps[0] + p.N[comps[0], sh]]] += n
+        else:
+            T[node, c] -= n
+            T[dest, c] += n
+    return T, cls_of
+
+
+def check_conservation(lib_path=None):
+    p = synth.sise3_network(n_nodes=300, n_days=150, seed=21, u=10.0, age_days=(20, 60),
+                            e1_per_node_day=0.6, e2_per_node_day=0.2)
+    want, cls_of = class_totals_replay(p)
+    ok = True
+    for seed in (1, 2):
+        p.seed = seed
+        r = O.run(p, lib_path=lib_path)
+        got = np.zeros_like(want)
+        for c in range(p.n_comp):
+            got[:, cls_of[c]] += r["u"][0, :, c]
+        ok = ok and (got == want).all() and (r["u"] >= 0).all() and r["transitions"].sum() > 1000
+    return ok, int(np.abs(got - want).sum())

@@ -1,0 +1,130 @@
+"""The oracle against laws fixed by the paper and the mathematics (CPU only)."""
+import numpy as np
+import pytest
+
+from farmnet import ENTER, EXIT, EXTERNAL, synth
+from oracle import oracle as O
+
+from . import laws
+
+
+def test_sis_decay_is_binomial_thinning():
+    ok, pv = laws.check_sis_decay()
+    assert ok, pv
+
+
+def test_flip_model_state_law():
+    ok, pv = laws.check_flip_state()
+    assert ok, pv
+
+
+def test_flip_model_transitions_are_poisson_2000():
+    ok, pv = laws.check_flip_clock()
+    assert ok, pv
+
+
+def test_two_node_exact_master_equation():
+    ok, pv = laws.check_two_node()
+    assert ok, pv
+
+
+def test_two_node_distinguishes_phi_reading():
+    """The same samples reject the reading that feeds phi from the pre-event state,
+    so the exact test above really pins the order SSA -> events -> phi."""
+    p, snap = laws.two_node_samples()
+    pv = laws.two_node_pvalues(snap, laws.two_node_exact_pre(p))
+    assert min(pv) < 1e-8, pv
+
+
+@pytest.mark.parametrize("day0", [0, 50, 300])
+def test_phi_closed_form(day0):
+    ok, worst = laws.check_phi_closed_form(day0=day0)
+    assert ok, worst
+
+
+def test_hypergeometric_removal():
+    ok, pv = laws.check_hypergeometric()
+    assert ok, pv
+
+
+def test_multivariate_walk():
+    ok, pv = laws.check_multivariate_walk()
+    assert ok, pv
+
+
+def test_class_totals_follow_the_events():
+    ok, diff = laws.check_conservation()
+    assert ok, diff
+
+
+def test_single_compartment_events_are_deterministic():
+    # node 0 holds only susceptibles: every removal is forced (Sec. 3.3)
+    u0 = [[5, 0], [0, 0], [0, 0]]
+    ev = [(0, EXTERNAL, 0, 1, 3, 1, -1), (0, EXTERNAL, 1, 2, 3, 1, -1), (1, ENTER, 2, -1, 4, 0, -1),
+          (1, EXIT, 2, -1, 2, 1, -1)]
+    p = synth.events_only(u0, ev, n_days=2)
+    for seed in (1, 2, 3):
+        p.seed = seed
+        r = O.run(p)
+        assert r["u"][0].tolist() == [[2, 0], [0, 0], [5, 0]]
+
+
+def test_events_apply_in_list_order():
+    u0 = [[5, 0], [0, 0], [0, 0]]
+    ev = [(0, EXTERNAL, 1, 2, 3, 1, -1), (0, EXTERNAL, 0, 1, 3, 1, -1)]
+    p = synth.events_only(u0, ev, n_days=1)
+    r = O.run(p, raise_on_error=False)
+    assert r["rc"] == -4 and r["err_event"] == 0 and r["err_day"] == 0
+
+
+def test_infeasible_reports_smallest_event_and_replicate():
+    # select column 2 = {I}: whether 3 infected can leave depends on the SSA
+    m = synth.sis_model(upsilon=0.5, gamma=0.5)
+    E = np.concatenate([m["E"], [[0], [1]]], axis=1)
+    n = 40
+    u0 = np.tile([[3, 3]], (n, 1))
+    ev = [(1, EXIT, np.arange(n), -1, 3, 2, -1)]
+    p = synth.events_only(u0, ev, n_days=2, n_rep=8)
+    p.E = E.astype(np.int32)
+    p.coef[:] = [0.5, 0.5]
+    p.uses_phi[:] = 0
+    r = O.run(p, raise_on_error=False)
+    assert r["rc"] == -4
+    # recompute per replicate which events were infeasible, from the state before day 1's events
+    per_rep = []
+    for rep in range(8):
+        q = synth.events_only(u0, ev, n_days=2)
+        q.E = p.E; q.coef[:] = p.coef[0]; q.uses_phi[:] = 0
+        q.replicate_id = np.array([rep], np.uint32)
+        s = O.run(q, d_begin=0, d_end=1)
+        rr = O.run(q, d_begin=1, d_end=2, u=s["u"], v=s["v"], raise_on_error=False)
+        if rr["rc"] == -4:
+            per_rep.append((rr["err_event"], rep))
+    assert per_rep and (r["err_event"], r["err_rep"]) == min(per_rep)
+
+
+def test_threads_are_bit_identical():
+    p = synth.config1()
+    a = O.run(p, threads=1)
+    b = O.run(p, threads=4)
+    for k in ("u", "v", "prevalence", "transitions", "totals"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_resume_is_bit_identical():
+    p = synth.config1()
+    p.record_days = np.array([10, 200, 364], np.int32)
+    full = O.run(p)
+    a = O.run(p, d_begin=0, d_end=137)
+    b = O.run(p, d_begin=137, d_end=365, u=a["u"], v=a["v"])
+    assert np.array_equal(full["u"], b["u"]) and np.array_equal(full["v"], b["v"])
+    assert np.array_equal(full["prevalence"], np.r_[a["prevalence"], b["prevalence"]])
+    assert np.array_equal(full["snap_u"], np.r_[a["snap_u"], b["snap_u"]])
+
+
+def test_replicates_are_independent_streams():
+    p = synth.config1().with_replicates(3, replicate_id=np.array([5, 9, 5], np.uint32))
+    r = O.run(p)
+    assert np.array_equal(r["u"][0], r["u"][2]) and not np.array_equal(r["u"][0], r["u"][1])
+    one = O.run(synth.config1().with_replicates(1, replicate_id=np.array([9], np.uint32)))
+    assert np.array_equal(one["u"][0], r["u"][1])
