@@ -1,0 +1,177 @@
+#!/usr/bin/env python3
+"""Throughput of the per-day hot path on one MI355X.
+
+Workload: the SISe3 farm network of 37,000 nodes over 1461 days (about 5.3M
+scheduled events, seed 2), synthetic (see farmnet/synth.py). One step is one
+full simulation of the horizon from the initial state: every day runs the SSA
+of every node, the day's events in dependency levels, and the phi update.
+Inputs are resident in HBM before the timed region; the state is reset between
+steps outside it.
+
+Prints one JSON line: node-days/s (value), SSA transitions/s, the dominant
+kernel's achieved algorithmic bandwidth against the HBM peak, and the oracle
+timed on the host's cores on the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, vendor peak
+
+WORKLOADS = {
+    "sise3-37k": dict(desc="SISe3 farm network, 37,000 nodes x 1461 days, seed 2",
+                      make=lambda synth: synth.config2()),
+    "sis-1k": dict(desc="SIS farm network, 1,000 nodes x 365 days, seed 1",
+                   make=lambda synth: synth.config1()),
+    "sise3-1m": dict(desc="SISe3 farm network, 1,000,000 nodes x 1461 days, seed 3",
+                     make=lambda synth: synth.config3()),
+}
+
+
+def algorithmic_bytes(p, day_launches, ev_counts_by_kind):
+    """Bytes the method must move: per node-day the state u (4 B per
+    compartment) and phi (8 B), read and written; per event a 20 B record plus
+    4 B read and 4 B written per compartment touched."""
+    per_node_day = 2 * (4 * p.n_comp + 8)
+    node_days = p.n_nodes * p.n_rep * day_launches
+    ev_bytes = 0
+    for kind, n in ev_counts_by_kind.items():
+        width = {0: 2, 1: 1, 2: 4, 3: 4}[kind] if p.n_comp == 6 else {0: 2, 1: 1, 2: 2, 3: 4}[kind]
+        ev_bytes += n * p.n_rep * (20 + 8 * width)
+    return node_days * per_node_day, ev_bytes, per_node_day
+
+
+def cpu_baseline(p, seconds):
+    from oracle import oracle as O
+    threads = min(os.cpu_count() or 1, 16)
+    runs, t_total, trans = 0, 0.0, 0
+    while t_total < seconds or runs == 0:
+        t0 = time.perf_counter()
+        r = O.run(p, threads=threads)
+        t_total += time.perf_counter() - t0
+        trans += int(r["transitions"].sum())
+        runs += 1
+        if runs >= 20:
+            break
+    nd = p.n_nodes * p.n_days * p.n_rep * runs
+    return dict(value=nd / t_total, unit="node-days/s", cores=threads, kind="oracle",
+                sample=f"the full workload ({p.n_nodes} nodes x {p.n_days} days), {runs} run(s), "
+                       f"oracle fork-join over {threads} threads, {t_total:.1f} s",
+                transitions_per_s=trans / t_total)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="sise3-37k", choices=sorted(WORKLOADS))
+    ap.add_argument("--launch", default="kernels", choices=["kernels", "persistent"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the per-node hot path "
+              "is measured on a single MI355X; see DESIGN.md for how it would shard.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1502_02908_amd as P
+    from farmnet import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    wl = WORKLOADS[args.workload]
+    p = wl["make"](synth)
+    launch = P.LAUNCH_PERSISTENT if args.launch == "persistent" else P.LAUNCH_KERNELS
+    print(f"[bench] {wl['desc']}: {p.n_events} events, launch={args.launch}", file=sys.stderr, flush=True)
+    sim = P.Simulator(p, launch=launch)
+    u0 = np.tile(p.u0[None], (p.n_rep, 1, 1))
+    v0 = np.tile(p.v0[None], (p.n_rep, 1))
+
+    def one_step():
+        sim.run(0)
+
+    for _ in range(args.warmup):
+        sim.set_state(u0, v0, 0)
+        one_step()
+        sim.sync()
+    times = []
+    for k in range(args.steps):
+        sim.set_state(u0, v0, 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        one_step()
+        sim.sync()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        print(f"[bench] step {k}: {times[-1] * 1e3:.2f} ms", file=sys.stderr, flush=True)
+    traj = sim.trajectory()
+    trans_per_step = int(traj["transitions"].sum())
+    total = sum(times)
+    node_days = p.n_nodes * p.n_days * p.n_rep * args.steps
+    value = node_days / total
+
+    # per-kernel durations, HIP events on the launch stream, same configuration
+    sim.kernel_times(-1)
+    sim.kernel_times(1)
+    for _ in range(max(1, min(args.steps, 3))):
+        sim.set_state(u0, v0, 0)
+        one_step()
+    kt = sim.kernel_times(0)
+    steps_timed = max(1, min(args.steps, 3))
+    dom = max(kt, key=lambda k: kt[k][0])
+    dom_ms, dom_n = kt[dom]
+    counts = {k: int((p.ev_kind == k).sum()) for k in range(4)}
+    nd_bytes, ev_bytes, per_nd = algorithmic_bytes(p, p.n_days, counts)
+    if dom == "day":
+        bytes_per_launch = p.n_nodes * p.n_rep * per_nd
+        unit_desc = f"{per_nd} B per node-day x {p.n_nodes * p.n_rep} node-days per launch"
+    elif dom == "persist":
+        bytes_per_launch = nd_bytes + ev_bytes
+        unit_desc = (f"{per_nd} B per node-day x {p.n_nodes * p.n_days * p.n_rep} node-days + "
+                     f"event bytes {ev_bytes} per launch")
+    elif dom == "events":
+        n_lv = sim.levels()[0]
+        bytes_per_launch = ev_bytes / max(n_lv, 1)
+        unit_desc = f"event bytes {ev_bytes} over {n_lv} level launches"
+    else:
+        bytes_per_launch = p.n_nodes * p.n_rep * per_nd / 2
+        unit_desc = f"{per_nd // 2} B per node (read) per launch"
+    avg_s = dom_ms / 1e3 / dom_n
+    achieved = bytes_per_launch / avg_s / 1e9
+    roofline = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 5), traffic=None,
+                    kernel=dom, avg_launch_us=round(avg_s * 1e6, 3), launches_per_step=dom_n // steps_timed,
+                    per_unit=unit_desc)
+    kernel_breakdown = {k: dict(ms_per_step=round(v[0] / steps_timed, 4), launches_per_step=v[1] // steps_timed)
+                        for k, v in kt.items() if v[1]}
+    sim.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(p, args.cpu_seconds)
+        cpu = {k: (round(v, 1) if isinstance(v, float) else v) for k, v in cpu.items()}
+
+    line = dict(
+        metric="SISe3 node-days/s + SSA transitions/s at 37k nodes; batched replicates/s vs plain",
+        value=round(value, 1), unit="node-days/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+        ms_per_step=round(total / args.steps * 1e3, 3), higher_is_better=True, scaling="weak",
+        vs_baseline=None, dtype="f64", data="synthetic",
+        config=dict(workload=wl["desc"], nodes=p.n_nodes, days=p.n_days, replicates=p.n_rep,
+                    events=p.n_events, launch=args.launch, step="one full-horizon simulation"),
+        transitions_per_s=round(trans_per_step * args.steps / total, 1),
+        transitions_per_step=trans_per_step,
+        roofline=roofline, kernels=kernel_breakdown, cpu_baseline=cpu)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,79 @@
+// Internal layout shared by the host side (episim_host.cpp) and the gfx950
+// kernels (episim_device.hip) of the library. Not part of the public ABI.
+//
+// Device data layout (one handle = one network, R replicate trajectories):
+//   lane l = node * R + r (replicate fastest), L = Nn * R lanes
+//   u[c * L + l]        int32 compartment counts, compartment-major (SoA) so
+//                       that a wavefront's loads of one compartment coalesce
+//   phi[l]              binary64 environmental infectious pressure
+//   events              SoA in execution order (day, then level, then list
+//                       order), 20 bytes per event: global index g, node,
+//                       dest, n, packed meta (kind, select mask, shift id)
+#pragma once
+#include <cstdint>
+
+namespace episim {
+
+constexpr int MAXC = 8;
+constexpr int MAXT = 8;
+constexpr unsigned long long STATUS_OK = ~0ull;  // else (g << 32) | replicate of an infeasible event
+constexpr unsigned long long STATUS_LIMIT_TAG = 0xFFFFFFFEull;  // high word when a node hit SIM_MAX_FIRED
+
+// meta word of an event: bits 0-1 kind, bits 2-9 select mask, bits 10-15 shift id + 1 (0 = none)
+__host__ __device__ inline uint32_t meta_pack(int kind, uint32_t mask, int shift) {
+    return (uint32_t)kind | (mask << 2) | ((uint32_t)(shift + 1) << 10);
+}
+constexpr int MAX_SHIFT_IDS = 63;
+
+// Model description, passed by value (lands in the kernel-argument segment,
+// read with scalar loads).
+struct Model {
+    int32_t nc, nt;
+    int32_t day0;
+    uint32_t seed;
+    uint32_t uses_phi;          // bit k: rate k proportional to phi
+    uint32_t imask, nmask;      // compartments counted in I and in N
+    int32_t reactant[MAXT];
+    int32_t S[MAXC][MAXT];      // S[c][k]
+};
+
+struct DevState {
+    int32_t *u;                 // [nc][L]
+    double *phi;                // [L]
+    int64_t L;                  // Nn * R
+    int32_t Nn, R;
+    int32_t n_days;
+    const double *coef;         // [R][nt]
+    const double *alpha;        // [R]
+    const double *beta;         // [R][4]
+    const uint32_t *repid;      // [R]
+    const int32_t *shift;       // [n_shift_ids][MAXC] compartment offsets
+    unsigned long long *status; // first infeasible event, or STATUS_OK
+    // daily records
+    int32_t *prevalence;        // [D][R]
+    int64_t *transitions;       // [D][R]
+    int64_t *totals;            // [D][R][nc]
+    int32_t *snap_u;            // [n_record][R][Nn][nc]
+    double *snap_v;             // [n_record][R][Nn]
+    const int32_t *rec_slot;    // [D] snapshot slot of day d, or -1
+};
+
+struct DevEvents {
+    const int32_t *g;
+    const int32_t *node;
+    const int32_t *dest;
+    const int32_t *n;
+    const uint32_t *meta;
+    const int64_t *lvl_off;     // level boundaries into the arrays above
+    const int32_t *lvl_ptr;     // [D+1]: levels of day d are lvl_ptr[d] .. lvl_ptr[d+1]-1
+};
+
+// Host-side launchers (episim_device.hip). Each returns a hipError_t as int.
+int launch_day(const Model &m, const DevState &s, int32_t d, int prologue, int ssa, int block,
+               void *stream);
+int launch_events(const Model &m, const DevState &s, const DevEvents &ev, int32_t d, int64_t begin,
+                  int64_t end, void *stream);
+int launch_persistent(const Model &m, const DevState &s, const DevEvents &ev, int32_t d_begin,
+                      int32_t d_end, int block, void *stream, char *why, int why_len);
+
+}  // namespace episim

@@ -1,0 +1,176 @@
+"""GPU path against the oracle, element by element, on seeded inputs: every
+compartment count, daily record and snapshot bit-exact, phi within 1e-12
+relative (and in practice bit-identical). Calls go through the C ABI."""
+import numpy as np
+import pytest
+
+from farmnet import ENTER, EXIT, EXTERNAL, synth
+from oracle import oracle as O
+import paper_1502_02908_amd as P
+
+from .gpu_common import assert_parity, gpu_run, say
+
+pytestmark = pytest.mark.gpu
+
+
+def both(p, **kw):
+    say(f"[parity] {p.name} Nn={p.n_nodes} R={p.n_rep} D={p.n_days} events={p.n_events} {kw}")
+    g = gpu_run(p, **kw)
+    o = O.run(p, threads=8)
+    return g, o
+
+
+def test_config1_full():
+    p = synth.config1()
+    p.record_days = np.array([0, 1, 90, 91, 182, 364], np.int32)
+    g, o = both(p)
+    assert_parity(g, o)
+    assert o["transitions"].sum() > 1000
+
+
+@pytest.mark.parametrize("launch", [P.LAUNCH_KERNELS, P.LAUNCH_PERSISTENT])
+def test_sise3_small_network(launch):
+    p = synth.sise3_network(n_nodes=3000, n_days=120, seed=5, u=10.0, age_days=(15, 40))
+    p.record_days = np.array([7, 60, 119], np.int32)
+    g, o = both(p, launch=launch)
+    assert_parity(g, o)
+    assert o["transitions"].sum() > 10000
+
+
+def test_serial_events_equal_levels():
+    p = synth.sise3_network(n_nodes=500, n_days=60, seed=6, age_days=(10, 30),
+                            e1_per_node_day=0.4, e2_per_node_day=0.1)
+    a = gpu_run(p, events_mode=P.EVENTS_LEVELS)
+    b = gpu_run(p, events_mode=P.EVENTS_SERIAL)
+    for k in ("u", "v", "prevalence", "transitions", "totals"):
+        assert np.array_equal(a[k], b[k]), k
+    assert a["levels"][0] < b["levels"][0]
+    assert_parity(a, O.run(p))
+
+
+def test_replicates_with_own_parameters():
+    base = synth.sise3_network(n_nodes=700, n_days=90, seed=8, age_days=(10, 30))
+    coef, alpha, beta = synth.prior_draws(5, seed=4)
+    p = base.with_replicates(5, coef=coef * 5, alpha=alpha, beta=beta,
+                             replicate_id=np.array([3, 1, 4, 1, 5], np.uint32))
+    p.record_days = np.array([10, 89], np.int32)
+    g, o = both(p)
+    assert_parity(g, o)
+
+
+@pytest.mark.parametrize("launch", [P.LAUNCH_KERNELS, P.LAUNCH_PERSISTENT])
+def test_many_replicates_ragged(launch):
+    p = synth.config1().truncated(40).with_replicates(67)
+    g, o = both(p, launch=launch)
+    assert_parity(g, o)
+
+
+def test_flip_model_heavy_ssa():
+    # the paper's synthetic benchmark model: ~2000 transitions per node-day
+    p = synth.flip_model(n_nodes=333, n_days=3)
+    g, o = both(p)
+    assert_parity(g, o)
+    assert o["transitions"].sum() > 1_900_000
+
+
+def test_two_node_replicates():
+    from .laws import TWO_NODE_KW
+    p = synth.two_node(**TWO_NODE_KW).with_replicates(4099)
+    p.record_days = np.array([0, 1, 2], np.int32)
+    g, o = both(p)
+    assert_parity(g, o)
+
+
+def test_phi_closed_form_system():
+    p = synth.constant_infection(n_days=400, day0=50)
+    p.record_days = np.arange(400, dtype=np.int32)
+    g, o = both(p)
+    assert_parity(g, o)
+
+
+def test_chunked_runs_and_checkpoint():
+    p = synth.config1()
+    p.record_days = np.array([3, 100, 250, 364], np.int32)
+    full = gpu_run(p)
+    chunked = gpu_run(p, chunks=[1, 99, 165, 100])
+    for k in ("u", "v", "prevalence", "transitions", "totals", "snap_u", "snap_v"):
+        assert np.array_equal(full[k], chunked[k]), k
+    # save at day 137, restore into a fresh handle, finish
+    with P.Simulator(p) as a:
+        a.run(137)
+        u, v, day = a.get_state()
+    with P.Simulator(p) as b:
+        b.set_state(u, v, day)
+        b.run(0)
+        u2, v2, day2 = b.get_state()
+        tb = b.trajectory()
+    assert day == 137 and day2 == 365
+    assert np.array_equal(u2, full["u"]) and np.array_equal(v2, full["v"])
+    assert np.array_equal(tb["prevalence"][137:], full["prevalence"][137:])
+
+
+def test_empty_and_degenerate_inputs():
+    # no events at all, a single node, zero-day run
+    p = synth.sis_decay(n_nodes=1, I0=7, gamma=0.9, n_days=5)
+    g, o = both(p)
+    assert_parity(g, o)
+    p0 = synth.config1().truncated(10)
+    with P.Simulator(p0) as s:
+        s.run(3)
+        s.run(0)
+        with pytest.raises(P.SimError):
+            s.run(1)
+        u, v, d = s.get_state()
+        assert d == 10
+
+
+def test_deterministic_events_and_order():
+    u0 = [[5, 0], [0, 0], [0, 0]]
+    ev = [(0, EXTERNAL, 0, 1, 3, 1, -1), (0, EXTERNAL, 1, 2, 3, 1, -1), (1, ENTER, 2, -1, 4, 0, -1),
+          (1, EXIT, 2, -1, 2, 1, -1)]
+    p = synth.events_only(u0, ev, n_days=2)
+    g = gpu_run(p)
+    assert g["u"][0].tolist() == [[2, 0], [0, 0], [5, 0]]
+
+
+def test_infeasible_event_reports_smallest_index():
+    u0 = [[5, 0], [0, 0], [0, 0]]
+    ev = [(0, EXTERNAL, 1, 2, 3, 1, -1), (0, EXTERNAL, 0, 1, 3, 1, -1), (0, EXIT, 2, -1, 9, 1, -1)]
+    p = synth.events_only(u0, ev, n_days=2)
+    o = O.run(p, raise_on_error=False)
+    assert o["rc"] == -4
+    with P.Simulator(p) as s:
+        s.run(0)
+        with pytest.raises(P.SimError) as e:
+            s.sync()
+        assert e.value.code == -4
+        assert f"infeasible event {o['err_event']} (replicate {o['err_rep']})" in str(e.value)
+
+
+def test_infeasible_depends_on_replicate():
+    m = synth.sis_model(upsilon=0.5, gamma=0.5)
+    E = np.concatenate([m["E"], [[0], [1]]], axis=1)
+    n = 40
+    u0 = np.tile([[3, 3]], (n, 1))
+    ev = [(1, EXIT, np.arange(n), -1, 3, 2, -1)]
+    p = synth.events_only(u0, ev, n_days=2, n_rep=8)
+    p.E = E.astype(np.int32)
+    p.coef[:] = [0.5, 0.5]
+    p.uses_phi[:] = 0
+    o = O.run(p, raise_on_error=False)
+    assert o["rc"] == -4
+    with P.Simulator(p) as s:
+        s.run(0)
+        with pytest.raises(P.SimError) as e:
+            s.sync()
+        assert f"infeasible event {o['err_event']} (replicate {o['err_rep']})" in str(e.value)
+
+
+@pytest.mark.parametrize("launch", [P.LAUNCH_KERNELS, P.LAUNCH_PERSISTENT])
+def test_config2_full_37k_nodes_1461_days(launch):
+    p = synth.config2()
+    p.record_days = np.array([0, 400, 1000, 1460], np.int32)
+    g, o = both(p, launch=launch)
+    assert_parity(g, o)
+    n_lv, mx = g["levels"]
+    say(f"[parity] config2 levels total={n_lv} max/day={mx} transitions={o['transitions'].sum()}")
