@@ -107,35 +107,73 @@ __device__ __forceinline__ bool trans_on(const Model &m, int k) {
     return NT != MAXT || k < m.nt;
 }
 
-// omega_k and lambda (Sec. 3.3), summed in transition order.
+// omega_k = cphi_k * X[reactant_k], where cphi_k is the rate constant times
+// phi for the transitions that use phi (the product (c * phi) * X of Sec. 3.3,
+// eq:rate_s_to_i); lambda and the running sums cum_k in transition order.
 template <int NC, int NT>
-__device__ __forceinline__ double propensities(const Model &m, const double (&c)[NT], double phi,
-                                               const int32_t (&x)[NC], double (&w)[NT]) {
+__device__ __forceinline__ double propensities(const Model &m, const double (&cphi)[NT],
+                                               const int32_t (&x)[NC], double (&w)[NT],
+                                               double (&cum)[NT]) {
     double lam = 0.0;
 #pragma unroll
     for (int k = 0; k < NT; ++k) {
         w[k] = 0.0;
+        cum[k] = lam;
         if (!trans_on<NT>(m, k)) continue;
-        double v = c[k];
-        if ((m.uses_phi >> k) & 1u) v = v * phi;
         int32_t xr = 0;
 #pragma unroll
         for (int cc = 0; cc < NC; ++cc)
             if (m.reactant[k] == cc) xr = x[cc];
-        v = v * (double)xr;
-        w[k] = v;
-        lam = lam + v;
+        w[k] = cphi[k] * (double)xr;
+        lam = lam + w[k];
+        cum[k] = lam;
     }
     return lam;
 }
 
-// The direct method over one window for one lane; x is updated in place.
+// Inversion of eq:sampling2: the first transition with a positive rate whose
+// running sum reaches target (the last positive one if rounding leaves none).
+template <int NT>
+__device__ __forceinline__ int choose(const Model &m, const double (&w)[NT], const double (&cum)[NT],
+                                      double target) {
+    int j = -1, last = -1;
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+        if (!trans_on<NT>(m, k)) continue;
+        if (w[k] > 0.0) {
+            last = k;
+            if (j < 0 && cum[k] >= target) j = k;
+        }
+    }
+    return j < 0 ? last : j;
+}
+
 template <int NC, int NT>
-__device__ __forceinline__ int32_t ssa_window(const Model &m, const double (&c)[NT], double phi,
-                                              int32_t (&x)[NC], uint32_t node, uint32_t day,
-                                              uint32_t key1, unsigned long long *status, int32_t r) {
-    double w[NT];
-    double lam = propensities<NC, NT>(m, c, phi, x, w);
+__device__ __forceinline__ void apply_transition(const Model &m, int j, int32_t (&x)[NC]) {
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+        if (k == j) {
+#pragma unroll
+            for (int cc = 0; cc < NC; ++cc) x[cc] += m.S[cc][k];
+        }
+    }
+}
+
+__device__ __forceinline__ double lane_f64(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Per-lane direct method over the window [d, d+1) (Algorithm 1's inner loop):
+// attempt k draws one Philox block (k, node, d, 0); x is updated in place.
+template <int NC, int NT>
+__device__ __forceinline__ int32_t ssa_lane(const Model &m, const double (&cphi)[NT], int32_t (&x)[NC],
+                                            uint32_t node, uint32_t day, uint32_t key1,
+                                            unsigned long long *status, int32_t r) {
+    double w[NT], cum[NT];
+    double lam = propensities<NC, NT>(m, cphi, x, w, cum);
     double clock = 0.0;
     uint32_t draw = 0;
     int32_t fired = 0;
@@ -145,32 +183,59 @@ __device__ __forceinline__ int32_t ssa_window(const Model &m, const double (&c)[
         const double tau = minus_log(unit_open(o.a, o.b)) / lam;
         if (!(clock + tau < 1.0)) break;
         clock = clock + tau;
-        const double target = unit_open(o.c, o.d) * lam;
-        int j = -1, last = -1;
-        double cum = 0.0;
-#pragma unroll
-        for (int k = 0; k < NT; ++k) {
-            if (!trans_on<NT>(m, k)) continue;
-            cum = cum + w[k];
-            if (w[k] > 0.0) {
-                last = k;
-                if (j < 0 && cum >= target) j = k;
-            }
-        }
-        if (j < 0) j = last;
-#pragma unroll
-        for (int k = 0; k < NT; ++k) {
-            if (k == j) {
-#pragma unroll
-                for (int cc = 0; cc < NC; ++cc) x[cc] += m.S[cc][k];
-            }
-        }
+        const int j = choose<NT>(m, w, cum, unit_open(o.c, o.d) * lam);
+        apply_transition<NC, NT>(m, j, x);
         fired = fired + 1;
         if (fired >= SIM_MAX_FIRED) {  // bounded work per lane: report instead of running on
             atomicMin(status, (STATUS_LIMIT_TAG << 32) | (unsigned long long)(uint32_t)r);
             break;
         }
-        lam = propensities<NC, NT>(m, c, phi, x, w);
+        lam = propensities<NC, NT>(m, cphi, x, w, cum);
+    }
+    return fired;
+}
+
+// The same chain for one heavy lane h, run by the whole wavefront: the draws
+// do not depend on the state, so lane i computes Philox block k0 + i and its
+// -log(rand) in parallel; the state-dependent part (division, comparison,
+// inversion, update) then walks those 64 draws in order with every lane
+// holding the same values. Returns the transitions and leaves the new counts
+// in x (identical in all lanes).
+template <int NC, int NT>
+__device__ __forceinline__ int32_t ssa_wave(const Model &m, const double (&cphi)[NT], int32_t (&x)[NC],
+                                            uint32_t node, uint32_t day, uint32_t key1,
+                                            unsigned long long *status, int32_t r) {
+    const uint32_t lane = threadIdx.x & 63u;
+    double w[NT], cum[NT];
+    double lam = propensities<NC, NT>(m, cphi, x, w, cum);
+    double clock = 0.0;
+    int32_t fired = 0;
+    bool go = lam > 0.0;
+    for (uint32_t k0 = 0; go; k0 += 64) {
+        const Word4 o = philox4x32_10(Word4{k0 + lane, node, day, 0u}, m.seed, key1);
+        const double e_mine = minus_log(unit_open(o.a, o.b));
+        const double u_mine = unit_open(o.c, o.d);
+        for (int i = 0; i < 64; ++i) {
+            const double tau = lane_f64(e_mine, i) / lam;
+            if (!(clock + tau < 1.0)) {
+                go = false;
+                break;
+            }
+            clock = clock + tau;
+            const int j = choose<NT>(m, w, cum, lane_f64(u_mine, i) * lam);
+            apply_transition<NC, NT>(m, j, x);
+            fired = fired + 1;
+            if (fired >= SIM_MAX_FIRED) {
+                if (lane == 0) atomicMin(status, (STATUS_LIMIT_TAG << 32) | (unsigned long long)(uint32_t)r);
+                go = false;
+                break;
+            }
+            lam = propensities<NC, NT>(m, cphi, x, w, cum);
+            if (!(lam > 0.0)) {
+                go = false;
+                break;
+            }
+        }
     }
     return fired;
 }
@@ -239,20 +304,37 @@ __device__ __forceinline__ void flush_lane(const Model &m, const DevState &s, co
                   (unsigned long long)t.trans);
 }
 
-// One lane of the day phase: close day d-1 (phi update + record) if
-// prologue, then run the SSA of day d if ssa. Adds the lane's counts to t.
+// Lanes whose total rate at the start of the window is at least kHeavy run
+// their chain cooperatively (ssa_wave) when a wavefront holds at most
+// kWaveChains of them; everything else runs per lane. Both paths perform the
+// same arithmetic on the same draws.
+constexpr double kHeavy = 12.0;
+constexpr int kWaveChains = 4;
+
+// The day phase for the lane l of a wavefront (every lane of the wavefront
+// must call it; lanes with l >= L take part in the wavefront-level steps
+// only): close day d-1 (phi update + record) if prologue, then run the SSA of
+// day d if ssa. Adds the lane's counts to t.
 template <int NC, int NT>
-__device__ __forceinline__ void day_lane(const Model &m, const DevState &s, int64_t l, int32_t d,
+__device__ __forceinline__ void day_wave(const Model &m, const DevState &s, int64_t l, int32_t d,
                                          bool prologue, bool ssa, Tally<NC> &t) {
+    const bool active = l < s.L;
     const int32_t R = s.R;
-    const int32_t r = R == 1 ? 0 : (int32_t)(l % R);
-    const int32_t node = R == 1 ? (int32_t)l : (int32_t)(l / R);
+    const int32_t r = !active || R == 1 ? 0 : (int32_t)(l % R);
+    const int32_t pos = !active ? 0 : (R == 1 ? (int32_t)l : (int32_t)(l / R));
     int32_t x[NC];
+    double phi = 0.0;
+    uint32_t node = 0;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) x[c] = comp_on<NC>(m, c) ? s.u[(int64_t)c * s.L + l] : 0;
-    double phi = s.phi[l];
-    const double phi_in = phi;
-    if (prologue) {
+    for (int c = 0; c < NC; ++c) x[c] = 0;
+    if (active) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) x[c] = comp_on<NC>(m, c) ? s.u[(int64_t)c * s.L + l] : 0;
+        phi = s.phi[l];
+        node = (uint32_t)s.node_id[pos];
+    }
+    if (active && prologue) {
+        const double phi_in = phi;
         const int32_t dp = d - 1;
         long long I = 0, N = 0;
 #pragma unroll
@@ -278,18 +360,51 @@ __device__ __forceinline__ void day_lane(const Model &m, const DevState &s, int6
         }
         if (__double_as_longlong(phi) != __double_as_longlong(phi_in)) s.phi[l] = phi;
     }
-    if (ssa) {
-        double coef[NT];
+    if (!ssa) return;
+    double cphi[NT];
+    const uint32_t key1 = active ? s.repid[r] : 0u;
 #pragma unroll
-        for (int k = 0; k < NT; ++k) coef[k] = trans_on<NT>(m, k) ? s.coef[r * m.nt + k] : 0.0;
-        const int32_t fired = ssa_window<NC, NT>(m, coef, phi, x, (uint32_t)node, (uint32_t)d, s.repid[r],
-                                                  s.status, r);
-        t.trans += fired;
-        if (fired) {
+    for (int k = 0; k < NT; ++k) {
+        double c = active && trans_on<NT>(m, k) ? s.coef[r * m.nt + k] : 0.0;
+        if ((m.uses_phi >> k) & 1u) c = c * phi;
+        cphi[k] = c;
+    }
+    double w0[NT], cum0[NT];
+    const double lam0 = propensities<NC, NT>(m, cphi, x, w0, cum0);
+    const bool heavy = active && lam0 >= kHeavy;
+    const unsigned long long hmask = __ballot(heavy);
+    const int n_heavy = __popcll(hmask);
+    const bool wave_path = n_heavy >= 1 && n_heavy <= kWaveChains;
+    int32_t fired = 0;
+    if (active && !(wave_path && heavy))
+        fired = ssa_lane<NC, NT>(m, cphi, x, node, (uint32_t)d, key1, s.status, r);
+    if (wave_path) {
+        unsigned long long todo = hmask;
+        while (todo) {
+            const int h = __ffsll((long long)todo) - 1;
+            todo &= todo - 1;
+            int32_t xh[NC];
+            double ch[NT];
 #pragma unroll
-            for (int c = 0; c < NC; ++c)
-                if (comp_on<NC>(m, c)) s.u[(int64_t)c * s.L + l] = x[c];
+            for (int c = 0; c < NC; ++c) xh[c] = __builtin_amdgcn_readlane(x[c], h);
+#pragma unroll
+            for (int k = 0; k < NT; ++k) ch[k] = lane_f64(cphi[k], h);
+            const uint32_t nh = (uint32_t)__builtin_amdgcn_readlane((int)node, h);
+            const uint32_t kh = (uint32_t)__builtin_amdgcn_readlane((int)key1, h);
+            const int32_t rh = __builtin_amdgcn_readlane(r, h);
+            const int32_t fh = ssa_wave<NC, NT>(m, ch, xh, nh, (uint32_t)d, kh, s.status, rh);
+            if ((int)(threadIdx.x & 63u) == h) {
+                fired = fh;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) x[c] = xh[c];
+            }
         }
+    }
+    t.trans += fired;
+    if (active && fired) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (comp_on<NC>(m, c)) s.u[(int64_t)c * s.L + l] = x[c];
     }
 }
 
@@ -299,17 +414,13 @@ __global__ __launch_bounds__(kBlock) void k_day(Model m, DevState s, int32_t d, 
     if (*(volatile unsigned long long *)s.status != STATUS_OK) return;  // uniform early exit
     const int64_t l = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     Tally<NC> t{};
-    int32_t r = 0;
-    if (l < s.L) {
-        r = s.R == 1 ? 0 : (int32_t)(l % s.R);
-        day_lane<NC, NT>(m, s, l, d, prologue != 0, ssa != 0, t);
-    }
+    day_wave<NC, NT>(m, s, l, d, prologue != 0, ssa != 0, t);
     const int32_t d_rec = prologue ? d - 1 : -1;
     const int32_t d_ssa = ssa ? d : -1;
     if (s.R == 1) {
         flush_block<NC>(m, s, t, d_rec, d_ssa);
     } else if (l < s.L) {
-        flush_lane<NC>(m, s, t, r, d_rec, d_ssa);
+        flush_lane<NC>(m, s, t, (int32_t)(l % s.R), d_rec, d_ssa);
     }
 }
 
@@ -452,13 +563,15 @@ __global__ __launch_bounds__(kBlock) void k_persist(Model m, DevState s, DevEven
         const bool ssa = d < d_end;
         if (*(volatile unsigned long long *)s.status == STATUS_OK) {
             Tally<NC> t{};
-            for (int64_t l = first; l < s.L; l += stride) {
+            const int64_t span = ((s.L + kBlock - 1) / kBlock) * kBlock;  // whole workgroups
+            for (int64_t l = first; l < span; l += stride) {
                 if (s.R == 1) {
-                    day_lane<NC, NT>(m, s, l, d, prologue, ssa, t);
+                    day_wave<NC, NT>(m, s, l, d, prologue, ssa, t);
                 } else {
                     Tally<NC> one{};
-                    day_lane<NC, NT>(m, s, l, d, prologue, ssa, one);
-                    flush_lane<NC>(m, s, one, (int32_t)(l % s.R), prologue ? d - 1 : -1, ssa ? d : -1);
+                    day_wave<NC, NT>(m, s, l, d, prologue, ssa, one);
+                    if (l < s.L)
+                        flush_lane<NC>(m, s, one, (int32_t)(l % s.R), prologue ? d - 1 : -1, ssa ? d : -1);
                 }
             }
             if (s.R == 1) flush_block<NC>(m, s, t, prologue ? d - 1 : -1, ssa ? d : -1);

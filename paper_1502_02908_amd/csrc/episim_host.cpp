@@ -90,7 +90,7 @@ int check_device(hipError_t e, std::string *err, const char *what) {
 
 // Device buffer layout of one handle.
 struct Layout {
-    size_t u, phi, coef, alpha, beta, repid, shift, status, ev_g, ev_node, ev_dest, ev_n, ev_meta,
+    size_t u, phi, node_id, coef, alpha, beta, repid, shift, status, ev_g, ev_node, ev_dest, ev_n, ev_meta,
         lvl_off, lvl_ptr, prevalence, transitions, totals, snap_u, snap_v, rec_slot, total;
 };
 
@@ -108,6 +108,7 @@ Layout layout_for(int64_t Nn, int64_t Nc, int64_t Nt, int64_t R, int64_t D, int6
     const int64_t L = Nn * R;
     l.u = take(sizeof(int32_t) * Nc * L);
     l.phi = take(sizeof(double) * L);
+    l.node_id = take(sizeof(int32_t) * Nn);
     l.coef = take(sizeof(double) * R * Nt);
     l.alpha = take(sizeof(double) * R);
     l.beta = take(sizeof(double) * R * 4);
@@ -129,6 +130,32 @@ Layout layout_for(int64_t Nn, int64_t Nc, int64_t Nt, int64_t R, int64_t D, int6
     l.rec_slot = take(sizeof(int32_t) * D);
     l.total = off;
     return l;
+}
+
+// Position of every node: herds sorted by size (largest first) are dealt out
+// one per wavefront in turn, so that the longest SSA chains of a day run in
+// different wavefronts and start first. perm[pos] = node, inv[node] = pos.
+void order_nodes(const sim_problem *p, std::vector<int32_t> *perm, std::vector<int32_t> *inv) {
+    const int64_t Nn = p->n_nodes, Nc = p->n_comp;
+    std::vector<int64_t> size(Nn, 0);
+    for (int64_t i = 0; i < Nn; ++i)
+        for (int64_t c = 0; c < Nc; ++c) size[i] += p->u0[i * Nc + c];
+    std::vector<int32_t> rank(Nn);
+    for (int64_t i = 0; i < Nn; ++i) rank[i] = (int32_t)i;
+    std::stable_sort(rank.begin(), rank.end(), [&](int32_t a, int32_t b) { return size[a] > size[b]; });
+    const int64_t G = std::max<int64_t>(1, 64 / p->n_rep);  // nodes per wavefront
+    const int64_t W = (Nn + G - 1) / G;                     // wavefronts
+    perm->assign(Nn, 0);
+    inv->assign(Nn, 0);
+    int64_t q = 0;
+    for (int64_t j = 0; j < G; ++j)
+        for (int64_t w = 0; w < W; ++w) {
+            const int64_t pos = w * G + j;
+            if (pos >= Nn) continue;
+            const int32_t node = rank[q++];
+            (*perm)[pos] = node;
+            (*inv)[node] = (int32_t)pos;
+        }
 }
 
 uint32_t column_mask(const sim_problem *p, int32_t s) {
@@ -230,6 +257,7 @@ struct sim_handle {
     Model model{};
     DevState st{};
     DevEvents ev{};
+    std::vector<int32_t> perm, inv;  // position -> node, node -> position
     std::vector<int64_t> lvl_off;   // host copy of the level boundaries
     std::vector<int32_t> lvl_ptr;   // [D+1]
     Layout lay{};
@@ -366,6 +394,7 @@ int sim_create(const sim_problem *p, const sim_device_opts *o, sim_handle **out)
     h->launch = opts.launch;
     h->block = opts.block > 0 ? opts.block : 256;
     const int64_t n = p->n_events;
+    order_nodes(p, &h->perm, &h->inv);
 
     // --- dependency pass and execution order (stable by day, level, list order)
     std::vector<int32_t> level(n);
@@ -389,8 +418,8 @@ int sim_create(const sim_problem *p, const sim_device_opts *o, sim_handle **out)
     for (int64_t e = 0; e < n; ++e) {
         const int64_t pos = fill[h->lvl_ptr[p->ev_day[e]] + level[e] - 1]++;
         eg[pos] = (int32_t)e;
-        enode[pos] = p->ev_node[e];
-        edest[pos] = p->ev_kind[e] == SIM_EXTERNAL ? p->ev_dest[e] : -1;
+        enode[pos] = h->inv[p->ev_node[e]];
+        edest[pos] = p->ev_kind[e] == SIM_EXTERNAL ? h->inv[p->ev_dest[e]] : -1;
         en[pos] = p->ev_n[e];
         emeta[pos] = meta_pack(p->ev_kind[e], column_mask(p, p->ev_select[e]), p->ev_shift[e]);
     }
@@ -433,6 +462,7 @@ int sim_create(const sim_problem *p, const sim_device_opts *o, sim_handle **out)
     DevState &s = h->st;
     s.u = at<int32_t>(h->ws, l.u);
     s.phi = at<double>(h->ws, l.phi);
+    s.node_id = at<int32_t>(h->ws, l.node_id);
     s.L = h->L;
     s.Nn = h->Nn;
     s.R = h->R;
@@ -488,6 +518,7 @@ int sim_create(const sim_problem *p, const sim_device_opts *o, sim_handle **out)
         {(void *)ev.lvl_off, h->lvl_off.data(), sizeof(int64_t) * (n_levels + 1)},
         {(void *)ev.lvl_ptr, h->lvl_ptr.data(), sizeof(int32_t) * (h->D + 1)},
         {(void *)s.rec_slot, rec_slot.data(), sizeof(int32_t) * h->D},
+        {(void *)s.node_id, h->perm.data(), sizeof(int32_t) * h->Nn},
     };
     for (const Up &up : ups) {
         if (up.bytes == 0) continue;
@@ -507,7 +538,7 @@ int sim_create(const sim_problem *p, const sim_device_opts *o, sim_handle **out)
     std::vector<double> v(h->L);
     for (int64_t i = 0; i < h->Nn; ++i)
         for (int r = 0; r < h->R; ++r) {
-            const int64_t lane = i * h->R + r;
+            const int64_t lane = (int64_t)h->inv[i] * h->R + r;
             for (int c = 0; c < h->Nc; ++c) u[(size_t)c * h->L + lane] = p->u0[i * h->Nc + c];
             v[lane] = p->v0[i];
         }
@@ -620,7 +651,7 @@ int sim_get_state(sim_handle *h, int32_t *u, double *v, int32_t *day) {
     if (rc) return rc;
     for (int r = 0; r < h->R; ++r)
         for (int64_t i = 0; i < h->Nn; ++i) {
-            const int64_t lane = i * h->R + r;
+            const int64_t lane = (int64_t)h->inv[i] * h->R + r;
             if (u)
                 for (int c = 0; c < h->Nc; ++c) u[((size_t)r * h->Nn + i) * h->Nc + c] = du[(size_t)c * h->L + lane];
             if (v) v[(size_t)r * h->Nn + i] = dv[lane];
@@ -638,7 +669,7 @@ int sim_set_state(sim_handle *h, const int32_t *u, const double *v, int32_t day)
     std::vector<double> dv(h->L);
     for (int r = 0; r < h->R; ++r)
         for (int64_t i = 0; i < h->Nn; ++i) {
-            const int64_t lane = i * h->R + r;
+            const int64_t lane = (int64_t)h->inv[i] * h->R + r;
             for (int c = 0; c < h->Nc; ++c) {
                 const int32_t x = u[((size_t)r * h->Nn + i) * h->Nc + c];
                 if (x < 0) return h->err = "negative count in state", SIM_EINVAL;

@@ -2,7 +2,10 @@
 // kernels (episim_device.hip) of the library. Not part of the public ABI.
 //
 // Device data layout (one handle = one network, R replicate trajectories):
-//   lane l = node * R + r (replicate fastest), L = Nn * R lanes
+//   lane l = pos * R + r (replicate fastest), L = Nn * R lanes, where pos is
+//   the node's position: nodes are reordered so that the largest herds (the
+//   longest SSA chains) sit in different wavefronts, largest first;
+//   node_id[pos] gives the caller's numbering (used for the random streams)
 //   u[c * L + l]        int32 compartment counts, compartment-major (SoA) so
 //                       that a wavefront's loads of one compartment coalesce
 //   phi[l]              binary64 environmental infectious pressure
@@ -43,6 +46,7 @@ struct DevState {
     int64_t L;                  // Nn * R
     int32_t Nn, R;
     int32_t n_days;
+    const int32_t *node_id;     // [Nn] node (as numbered by the caller) at each position
     const double *coef;         // [R][nt]
     const double *alpha;        // [R]
     const double *beta;         // [R][4]

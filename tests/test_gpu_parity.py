@@ -174,3 +174,19 @@ def test_config2_full_37k_nodes_1461_days(launch):
     assert_parity(g, o)
     n_lv, mx = g["levels"]
     say(f"[parity] config2 levels total={n_lv} max/day={mx} transitions={o['transitions'].sum()}")
+
+
+@pytest.mark.parametrize("heavy_per_wave", [1, 4, 5, 64])
+def test_heavy_chains_per_wavefront(heavy_per_wave):
+    # flip model (S<->I at rate 1): herds of 2000 run ~2000 transitions a day,
+    # herds of 2 almost none; the node order deals the big herds out across
+    # wavefronts, so each of the 10 wavefronts gets heavy_per_wave of them
+    n = 640
+    p = synth.flip_model(n_nodes=n, n_days=2)
+    big = np.zeros(n, bool)
+    big[np.random.default_rng(1).choice(n, 10 * heavy_per_wave, replace=False)] = True
+    p.u0[~big] = [1, 1]
+    p.record_days = np.array([0, 1], np.int32)
+    g, o = both(p)
+    assert_parity(g, o)
+    assert o["transitions"].sum() > 10 * heavy_per_wave * 3000
