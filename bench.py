@@ -46,6 +46,27 @@ def algorithmic_bytes(p, day_launches, ev_counts_by_kind):
     return node_days * per_node_day, ev_bytes, per_node_day
 
 
+def counter_traffic(kernel):
+    """HBM bytes per launch of kernel from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a copy of known size), or
+    None if the kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_counters_sise3_37k.txt")
+    src = os.path.join(ROOT, "paper_1502_02908_amd", "csrc", "episim_device.hip")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip().split()[0] if v.strip() else ""
+    now = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if fields.get("source_sha256") != now:
+        return None
+    v = fields.get(f"traffic_bytes_per_launch {kernel}")
+    return int(v) if v else None
+
+
 def cpu_baseline(p, seconds):
     from oracle import oracle as O
     threads = min(os.cpu_count() or 1, 16)
@@ -74,6 +95,8 @@ def main():
     ap.add_argument("--launch", default="kernels", choices=["kernels", "persistent"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES bytes (profiler calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the per-node hot path "
@@ -88,6 +111,18 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        # a copy of known size: the hardware counters of the profiled kernels
+        # are scaled by what the same counters read for it
+        n = args.calibrate_copy // 4
+        a = torch.arange(n, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(calibration="copy", bytes_read=n * 4, bytes_written=n * 4, launches=3)))
+        return
     wl = WORKLOADS[args.workload]
     p = wl["make"](synth)
     launch = P.LAUNCH_PERSISTENT if args.launch == "persistent" else P.LAUNCH_KERNELS
@@ -147,8 +182,9 @@ def main():
         unit_desc = f"{per_nd // 2} B per node (read) per launch"
     avg_s = dom_ms / 1e3 / dom_n
     achieved = bytes_per_launch / avg_s / 1e9
+    traffic = counter_traffic("k_day") if (dom == "day" and args.workload == "sise3-37k") else None
     roofline = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 5), traffic=None,
+                    frac=round(achieved / HBM_PEAK_GBS, 5), traffic=traffic,
                     kernel=dom, avg_launch_us=round(avg_s * 1e6, 3), launches_per_step=dom_n // steps_timed,
                     per_unit=unit_desc)
     kernel_breakdown = {k: dict(ms_per_step=round(v[0] / steps_timed, 4), launches_per_step=v[1] // steps_timed)

@@ -27,6 +27,7 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 constexpr int kEvKindMask = 3;
+constexpr int kEvBlock = 1024;  // workgroup that runs a group of small event levels
 
 // ---------------------------------------------------------------------------
 // Counter-based random numbers: Philox4x32-10 (Salmon et al., SC'11).
@@ -38,11 +39,9 @@ struct Word4 {
 __device__ __forceinline__ Word4 philox4x32_10(Word4 x, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int i = 0; i < 10; ++i) {
-        const uint32_t lo_a = 0xD2511F53u * x.a;
-        const uint32_t hi_a = __umulhi(0xD2511F53u, x.a);
-        const uint32_t lo_c = 0xCD9E8D57u * x.c;
-        const uint32_t hi_c = __umulhi(0xCD9E8D57u, x.c);
-        x = Word4{hi_c ^ x.b ^ k0, lo_c, hi_a ^ x.d ^ k1, lo_a};
+        const uint64_t pa = (uint64_t)0xD2511F53u * (uint64_t)x.a;  // one 32x32->64 multiply each
+        const uint64_t pc = (uint64_t)0xCD9E8D57u * (uint64_t)x.c;
+        x = Word4{(uint32_t)(pc >> 32) ^ x.b ^ k0, (uint32_t)pc, (uint32_t)(pa >> 32) ^ x.d ^ k1, (uint32_t)pa};
         k0 += 0x9E3779B9u;  // Weyl increments of the key between rounds
         k1 += 0xBB67AE85u;
     }
@@ -107,56 +106,153 @@ __device__ __forceinline__ bool trans_on(const Model &m, int k) {
     return NT != MAXT || k < m.nt;
 }
 
-// omega_k = cphi_k * X[reactant_k], where cphi_k is the rate constant times
-// phi for the transitions that use phi (the product (c * phi) * X of Sec. 3.3,
-// eq:rate_s_to_i); lambda and the running sums cum_k in transition order.
-template <int NC, int NT>
-__device__ __forceinline__ double propensities(const Model &m, const double (&cphi)[NT],
-                                               const int32_t (&x)[NC], double (&w)[NT],
-                                               double (&cum)[NT]) {
-    double lam = 0.0;
-#pragma unroll
-    for (int k = 0; k < NT; ++k) {
-        w[k] = 0.0;
-        cum[k] = lam;
-        if (!trans_on<NT>(m, k)) continue;
-        int32_t xr = 0;
+// ---------------------------------------------------------------------------
+// The stochastic step (Sec. 3.3, Algorithm 1's inner loop; eq:sampling and
+// eq:sampling2). A lane's chain keeps its counts as exact binary64 values
+// (counts stay far below 2^53), so omega_k = cphi_k * X[reactant_k] is the
+// same product (c * phi) * (double)X in the same order as the plain method;
+// cphi_k is the rate constant times phi for the transitions that use phi.
+// lambda and the running sums cum_k are summed in transition order.
+// ---------------------------------------------------------------------------
+template <int NC_, int NT_>
+struct Chain {
+    static constexpr int NC = NC_, NT = NT_;
+    double xd[NC_];
+    double cphi[NT_];
+    double cum[NT_];
+    double lam, clock;
+    int32_t fired;
+};
+
+// Any stoichiometry (column k: -1 at reactant k, non-negative elsewhere).
+template <int NC_, int NT_>
+struct GenericRules {
+    static constexpr int NC = NC_, NT = NT_;
+    using State = Chain<NC, NT>;
+    __device__ static __forceinline__ double rate(const Model &m, const State &c, int k) {
+        double xr = 0.0;
 #pragma unroll
         for (int cc = 0; cc < NC; ++cc)
-            if (m.reactant[k] == cc) xr = x[cc];
-        w[k] = cphi[k] * (double)xr;
-        lam = lam + w[k];
-        cum[k] = lam;
+            if (m.reactant[k] == cc) xr = c.xd[cc];
+        return c.cphi[k] * xr;
     }
-    return lam;
-}
+    __device__ static __forceinline__ void rates(const Model &m, State &c) {
+        double lam = 0.0;
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            if (trans_on<NT>(m, k)) lam = lam + rate(m, c, k);
+            c.cum[k] = lam;
+        }
+        c.lam = lam;
+    }
+    __device__ static __forceinline__ void apply(const Model &m, int j, State &c) {
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            if (k == j) {
+#pragma unroll
+                for (int cc = 0; cc < NC; ++cc) c.xd[cc] = c.xd[cc] + (double)m.S[cc][k];
+            }
+        }
+    }
+    // j is the same in every lane: apply it and recompute all rates
+    __device__ static __forceinline__ void apply_uniform(const Model &m, int j, State &c) {
+        apply(m, j, c);
+        rates(m, c);
+    }
+};
+
+// Paired classes: compartments [S_1, I_1, ..., S_P, I_P] and transitions
+// 2p: S_p -> I_p, 2p+1: I_p -> S_p, each with its own compartment as reactant
+// (eq:vectorJSDE for eq:vtectrans; P = 1 is the plain SIS model). The host
+// selects these rules only when S and the reactants have exactly this form.
+template <int NP>
+struct PairRules {
+    static constexpr int NC = 2 * NP, NT = 2 * NP;
+    using State = Chain<NC, NT>;
+    __device__ static __forceinline__ double rate(const Model &, const State &c, int k) {
+        return c.cphi[k] * c.xd[k];
+    }
+    __device__ static __forceinline__ void rates(const Model &m, State &c) {
+        double lam = 0.0;
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            lam = lam + rate(m, c, k);
+            c.cum[k] = lam;
+        }
+        c.lam = lam;
+    }
+    __device__ static __forceinline__ void apply(const Model &, int j, State &c) {
+        const int p = j >> 1;
+        const double dS = (j & 1) ? 1.0 : -1.0;  // infection takes an S, recovery returns one
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            const double dq = q == p ? dS : 0.0;
+            c.xd[2 * q] = c.xd[2 * q] + dq;
+            c.xd[2 * q + 1] = c.xd[2 * q + 1] - dq;
+        }
+    }
+    // j is the same in every lane (a scalar): only class j/2 changes, so only
+    // the running sums from its first transition on are recomputed (the
+    // earlier ones are unchanged, so the values equal a full recomputation).
+    __device__ static __forceinline__ void apply_uniform(const Model &m, int j, State &c) {
+        const int p = j >> 1;
+        const double dS = (j & 1) ? 1.0 : -1.0;
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            if (q == p) {
+                c.xd[2 * q] = c.xd[2 * q] + dS;
+                c.xd[2 * q + 1] = c.xd[2 * q + 1] - dS;
+                double lam = q == 0 ? 0.0 : c.cum[2 * q - 1];
+#pragma unroll
+                for (int k = 2 * q; k < NT; ++k) {
+                    lam = lam + rate(m, c, k);
+                    c.cum[k] = lam;
+                }
+                c.lam = lam;
+            }
+        }
+    }
+};
 
 // Inversion of eq:sampling2: the first transition with a positive rate whose
-// running sum reaches target (the last positive one if rounding leaves none).
-template <int NT>
-__device__ __forceinline__ int choose(const Model &m, const double (&w)[NT], const double (&cum)[NT],
-                                      double target) {
-    int j = -1, last = -1;
+// running sum reaches target. With target > 0 that is the number of running
+// sums below target (they never decrease, and a transition with rate 0 cannot
+// be the first to reach a positive target); target can be 0 only if U*lambda
+// underflows, and then it is the first positive rate.
+template <class Rules>
+__device__ __forceinline__ int invert(const Model &m, const typename Rules::State &c, double target) {
+    constexpr int NT = Rules::NT;
+    int j = 0;
 #pragma unroll
-    for (int k = 0; k < NT; ++k) {
-        if (!trans_on<NT>(m, k)) continue;
-        if (w[k] > 0.0) {
-            last = k;
-            if (j < 0 && cum[k] >= target) j = k;
-        }
+    for (int k = 0; k < NT; ++k) j += c.cum[k] < target ? 1 : 0;
+    if (__builtin_expect(!(target > 0.0), 0)) {
+        j = NT;
+#pragma unroll
+        for (int k = NT - 1; k >= 0; --k)
+            if (trans_on<NT>(m, k) && Rules::rate(m, c, k) > 0.0) j = k;
     }
-    return j < 0 ? last : j;
+    return j;
 }
 
-template <int NC, int NT>
-__device__ __forceinline__ void apply_transition(const Model &m, int j, int32_t (&x)[NC]) {
-#pragma unroll
-    for (int k = 0; k < NT; ++k) {
-        if (k == j) {
-#pragma unroll
-            for (int cc = 0; cc < NC; ++cc) x[cc] += m.S[cc][k];
-        }
+// One attempt of the direct method with the draw (E, U) = (-log rand_1,
+// rand_2): tau = E / lambda; the transition fires only if it lands inside the
+// window. Returns whether the chain goes on.
+template <class Rules>
+__device__ __forceinline__ bool chain_step(const Model &m, typename Rules::State &c, double E, double U,
+                                           unsigned long long *status, int32_t r) {
+    const double tau = E / c.lam;
+    const double t1 = c.clock + tau;
+    const int j = invert<Rules>(m, c, U * c.lam);
+    if (!(t1 < 1.0)) return false;
+    c.clock = t1;
+    Rules::apply(m, j, c);
+    c.fired = c.fired + 1;
+    Rules::rates(m, c);
+    if (c.fired >= SIM_MAX_FIRED) {  // bounded work per lane: report instead of running on
+        atomicMin(status, (STATUS_LIMIT_TAG << 32) | (unsigned long long)(uint32_t)r);
+        return false;
     }
+    return c.lam > 0.0;
 }
 
 __device__ __forceinline__ double lane_f64(double v, int lane) {
@@ -166,78 +262,121 @@ __device__ __forceinline__ double lane_f64(double v, int lane) {
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// Per-lane direct method over the window [d, d+1) (Algorithm 1's inner loop):
-// attempt k draws one Philox block (k, node, d, 0); x is updated in place.
-template <int NC, int NT>
-__device__ __forceinline__ int32_t ssa_lane(const Model &m, const double (&cphi)[NT], int32_t (&x)[NC],
-                                            uint32_t node, uint32_t day, uint32_t key1,
-                                            unsigned long long *status, int32_t r) {
-    double w[NT], cum[NT];
-    double lam = propensities<NC, NT>(m, cphi, x, w, cum);
-    double clock = 0.0;
-    uint32_t draw = 0;
-    int32_t fired = 0;
-    while (lam > 0.0) {
-        const Word4 o = philox4x32_10(Word4{draw, node, day, 0u}, m.seed, key1);
-        draw = draw + 1;
-        const double tau = minus_log(unit_open(o.a, o.b)) / lam;
-        if (!(clock + tau < 1.0)) break;
-        clock = clock + tau;
-        const int j = choose<NT>(m, w, cum, unit_open(o.c, o.d) * lam);
-        apply_transition<NC, NT>(m, j, x);
-        fired = fired + 1;
-        if (fired >= SIM_MAX_FIRED) {  // bounded work per lane: report instead of running on
-            atomicMin(status, (STATUS_LIMIT_TAG << 32) | (unsigned long long)(uint32_t)r);
-            break;
-        }
-        lam = propensities<NC, NT>(m, cphi, x, w, cum);
-    }
-    return fired;
-}
-
-// The same chain for one heavy lane h, run by the whole wavefront: the draws
-// do not depend on the state, so lane i computes Philox block k0 + i and its
-// -log(rand) in parallel; the state-dependent part (division, comparison,
-// inversion, update) then walks those 64 draws in order with every lane
-// holding the same values. Returns the transitions and leaves the new counts
-// in x (identical in all lanes).
-template <int NC, int NT>
-__device__ __forceinline__ int32_t ssa_wave(const Model &m, const double (&cphi)[NT], int32_t (&x)[NC],
-                                            uint32_t node, uint32_t day, uint32_t key1,
-                                            unsigned long long *status, int32_t r) {
+// A single live chain, run by the whole wavefront with every lane holding
+// the same state: lane i computes attempt kbase + i, and the attempts are
+// walked in order with the chosen transition held in a scalar register.
+template <class Rules>
+__device__ __forceinline__ void chain_uniform(const Model &m, typename Rules::State &c, uint32_t kbase,
+                                              uint32_t node, uint32_t day, uint32_t key1,
+                                              unsigned long long *status, int32_t r) {
     const uint32_t lane = threadIdx.x & 63u;
-    double w[NT], cum[NT];
-    double lam = propensities<NC, NT>(m, cphi, x, w, cum);
-    double clock = 0.0;
-    int32_t fired = 0;
-    bool go = lam > 0.0;
-    for (uint32_t k0 = 0; go; k0 += 64) {
-        const Word4 o = philox4x32_10(Word4{k0 + lane, node, day, 0u}, m.seed, key1);
+    for (;;) {
+        const Word4 o = philox4x32_10(Word4{kbase + lane, node, day, 0u}, m.seed, key1);
         const double e_mine = minus_log(unit_open(o.a, o.b));
         const double u_mine = unit_open(o.c, o.d);
         for (int i = 0; i < 64; ++i) {
-            const double tau = lane_f64(e_mine, i) / lam;
-            if (!(clock + tau < 1.0)) {
-                go = false;
-                break;
-            }
-            clock = clock + tau;
-            const int j = choose<NT>(m, w, cum, lane_f64(u_mine, i) * lam);
-            apply_transition<NC, NT>(m, j, x);
-            fired = fired + 1;
-            if (fired >= SIM_MAX_FIRED) {
+            const double tau = lane_f64(e_mine, i) / c.lam;
+            const double t1 = c.clock + tau;
+            const int j = __builtin_amdgcn_readfirstlane(invert<Rules>(m, c, lane_f64(u_mine, i) * c.lam));
+            if (!(t1 < 1.0)) return;
+            c.clock = t1;
+            Rules::apply_uniform(m, j, c);
+            c.fired = c.fired + 1;
+            if (c.fired >= SIM_MAX_FIRED) {
                 if (lane == 0) atomicMin(status, (STATUS_LIMIT_TAG << 32) | (unsigned long long)(uint32_t)r);
-                go = false;
-                break;
+                return;
             }
-            lam = propensities<NC, NT>(m, cphi, x, w, cum);
-            if (!(lam > 0.0)) {
-                go = false;
-                break;
-            }
+            if (!(c.lam > 0.0)) return;
         }
+        kbase = kbase + 64;
     }
-    return fired;
+}
+
+// Every chain of a wavefront to the end of the window. Attempt k of a chain
+// uses Philox block (k, node, day, 0); the blocks do not depend on the state,
+// so while m < 64 chains are live the wavefront computes 64/m blocks per
+// chain in parallel (their -log rand and rand), parks them in LDS, and each
+// live lane then walks its own in order. With all 64 lanes live each lane
+// draws its own block. Every lane of the wavefront must call this.
+template <class Rules>
+__device__ __forceinline__ void run_chains(const Model &m, typename Rules::State &c, bool live, uint32_t node,
+                                           uint32_t day, uint32_t key1, unsigned long long *status, int32_t r) {
+    __shared__ double sh_e[kWaves][64], sh_u[kWaves][64];
+    __shared__ uint32_t sh_node[kWaves][64], sh_key[kWaves][64], sh_k[kWaves][64];
+    const int wave = threadIdx.x >> 6;
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t kbase = 0;  // next attempt index of this lane's chain
+    live = live && c.lam > 0.0;
+    for (;;) {
+        const unsigned long long mask = __ballot(live);
+        if (mask == 0ull) break;
+        if (mask == ~0ull) {
+            const Word4 o = philox4x32_10(Word4{kbase, node, day, 0u}, m.seed, key1);
+            kbase = kbase + 1;
+            live = chain_step<Rules>(m, c, minus_log(unit_open(o.a, o.b)), unit_open(o.c, o.d), status, r);
+            continue;
+        }
+        const uint32_t nlive = (uint32_t)__popcll(mask);
+        if (nlive == 1) {  // one chain left: the whole wavefront walks it
+            const int h = __ffsll((long long)mask) - 1;
+            typename Rules::State u;
+#pragma unroll
+            for (int k = 0; k < Rules::NC; ++k) u.xd[k] = lane_f64(c.xd[k], h);
+#pragma unroll
+            for (int k = 0; k < Rules::NT; ++k) {
+                u.cphi[k] = lane_f64(c.cphi[k], h);
+                u.cum[k] = lane_f64(c.cum[k], h);
+            }
+            u.lam = lane_f64(c.lam, h);
+            u.clock = lane_f64(c.clock, h);
+            u.fired = __builtin_amdgcn_readlane(c.fired, h);
+            chain_uniform<Rules>(m, u, (uint32_t)__builtin_amdgcn_readlane((int)kbase, h),
+                                 (uint32_t)__builtin_amdgcn_readlane((int)node, h), day,
+                                 (uint32_t)__builtin_amdgcn_readlane((int)key1, h), status,
+                                 __builtin_amdgcn_readlane(r, h));
+            if ((int)lane == h) c = u;
+            break;
+        }
+        const uint32_t per = 64u / nlive;
+        const uint32_t rank = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+        if (live) {
+            sh_node[wave][rank] = node;
+            sh_key[wave][rank] = key1;
+            sh_k[wave][rank] = kbase;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane < nlive * per) {
+            const uint32_t ch = lane % nlive, t = lane / nlive;
+            const Word4 o = philox4x32_10(Word4{sh_k[wave][ch] + t, sh_node[wave][ch], day, 0u}, m.seed,
+                                          sh_key[wave][ch]);
+            sh_e[wave][ch * per + t] = minus_log(unit_open(o.a, o.b));
+            sh_u[wave][ch * per + t] = unit_open(o.c, o.d);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (live) {
+            for (uint32_t t = 0; t < per; ++t) {
+                live = chain_step<Rules>(m, c, sh_e[wave][rank * per + t], sh_u[wave][rank * per + t], status, r);
+                if (!live) break;
+            }
+            kbase = kbase + per;
+        }
+        __builtin_amdgcn_wave_barrier();  // the next round rewrites the LDS slots
+    }
+}
+
+// Whether no error has been recorded, read once per workgroup so that every
+// thread takes the same branch (another wavefront of the workgroup may record
+// an error while this one is still starting). Every thread must call it.
+__device__ __forceinline__ bool block_ok(const DevState &s) {
+    __shared__ int ok;
+    __syncthreads();
+    if (threadIdx.x == 0) ok = *(volatile unsigned long long *)s.status == STATUS_OK;
+    __syncthreads();
+    return ok != 0;
 }
 
 __device__ __forceinline__ long long wave_sum(long long v) {
@@ -304,20 +443,14 @@ __device__ __forceinline__ void flush_lane(const Model &m, const DevState &s, co
                   (unsigned long long)t.trans);
 }
 
-// Lanes whose total rate at the start of the window is at least kHeavy run
-// their chain cooperatively (ssa_wave) when a wavefront holds at most
-// kWaveChains of them; everything else runs per lane. Both paths perform the
-// same arithmetic on the same draws.
-constexpr double kHeavy = 12.0;
-constexpr int kWaveChains = 4;
-
 // The day phase for the lane l of a wavefront (every lane of the wavefront
 // must call it; lanes with l >= L take part in the wavefront-level steps
 // only): close day d-1 (phi update + record) if prologue, then run the SSA of
 // day d if ssa. Adds the lane's counts to t.
-template <int NC, int NT>
+template <class Rules>
 __device__ __forceinline__ void day_wave(const Model &m, const DevState &s, int64_t l, int32_t d,
-                                         bool prologue, bool ssa, Tally<NC> &t) {
+                                         bool prologue, bool ssa, Tally<Rules::NC> &t) {
+    constexpr int NC = Rules::NC, NT = Rules::NT;
     const bool active = l < s.L;
     const int32_t R = s.R;
     const int32_t r = !active || R == 1 ? 0 : (int32_t)(l % R);
@@ -361,60 +494,36 @@ __device__ __forceinline__ void day_wave(const Model &m, const DevState &s, int6
         if (__double_as_longlong(phi) != __double_as_longlong(phi_in)) s.phi[l] = phi;
     }
     if (!ssa) return;
-    double cphi[NT];
+    typename Rules::State ch;
     const uint32_t key1 = active ? s.repid[r] : 0u;
 #pragma unroll
     for (int k = 0; k < NT; ++k) {
         double c = active && trans_on<NT>(m, k) ? s.coef[r * m.nt + k] : 0.0;
         if ((m.uses_phi >> k) & 1u) c = c * phi;
-        cphi[k] = c;
+        ch.cphi[k] = c;
     }
-    double w0[NT], cum0[NT];
-    const double lam0 = propensities<NC, NT>(m, cphi, x, w0, cum0);
-    const bool heavy = active && lam0 >= kHeavy;
-    const unsigned long long hmask = __ballot(heavy);
-    const int n_heavy = __popcll(hmask);
-    const bool wave_path = n_heavy >= 1 && n_heavy <= kWaveChains;
-    int32_t fired = 0;
-    if (active && !(wave_path && heavy))
-        fired = ssa_lane<NC, NT>(m, cphi, x, node, (uint32_t)d, key1, s.status, r);
-    if (wave_path) {
-        unsigned long long todo = hmask;
-        while (todo) {
-            const int h = __ffsll((long long)todo) - 1;
-            todo &= todo - 1;
-            int32_t xh[NC];
-            double ch[NT];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) xh[c] = __builtin_amdgcn_readlane(x[c], h);
-#pragma unroll
-            for (int k = 0; k < NT; ++k) ch[k] = lane_f64(cphi[k], h);
-            const uint32_t nh = (uint32_t)__builtin_amdgcn_readlane((int)node, h);
-            const uint32_t kh = (uint32_t)__builtin_amdgcn_readlane((int)key1, h);
-            const int32_t rh = __builtin_amdgcn_readlane(r, h);
-            const int32_t fh = ssa_wave<NC, NT>(m, ch, xh, nh, (uint32_t)d, kh, s.status, rh);
-            if ((int)(threadIdx.x & 63u) == h) {
-                fired = fh;
-#pragma unroll
-                for (int c = 0; c < NC; ++c) x[c] = xh[c];
-            }
-        }
-    }
-    t.trans += fired;
-    if (active && fired) {
+    for (int c = 0; c < NC; ++c) ch.xd[c] = (double)x[c];
+    ch.clock = 0.0;
+    ch.fired = 0;
+    Rules::rates(m, ch);
+    run_chains<Rules>(m, ch, active, node, (uint32_t)d, key1, s.status, r);
+    t.trans += ch.fired;
+    if (active && ch.fired) {
 #pragma unroll
         for (int c = 0; c < NC; ++c)
-            if (comp_on<NC>(m, c)) s.u[(int64_t)c * s.L + l] = x[c];
+            if (comp_on<NC>(m, c)) s.u[(int64_t)c * s.L + l] = (int32_t)ch.xd[c];
     }
 }
 
-template <int NC, int NT>
+template <class Rules>
 __global__ __launch_bounds__(kBlock) void k_day(Model m, DevState s, int32_t d, int32_t prologue,
                                                 int32_t ssa) {
-    if (*(volatile unsigned long long *)s.status != STATUS_OK) return;  // uniform early exit
+    constexpr int NC = Rules::NC;
+    if (!block_ok(s)) return;
     const int64_t l = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     Tally<NC> t{};
-    day_wave<NC, NT>(m, s, l, d, prologue != 0, ssa != 0, t);
+    day_wave<Rules>(m, s, l, d, prologue != 0, ssa != 0, t);
     const int32_t d_rec = prologue ? d - 1 : -1;
     const int32_t d_ssa = ssa ? d : -1;
     if (s.R == 1) {
@@ -430,6 +539,13 @@ __global__ __launch_bounds__(kBlock) void k_day(Model m, DevState s, int32_t d, 
 // only added to, so draws use plain loads/stores and additions commute
 // (integer atomics).
 // ---------------------------------------------------------------------------
+// Loads of the state in the event phase go to L2 (relaxed atomic loads at
+// device scope), where the additions of earlier levels were made, so a
+// workgroup that runs several levels back to back never reads a stale line.
+__device__ __forceinline__ int32_t load_l2(const int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <int NC>
 __device__ __forceinline__ void event_one(const Model &m, const DevState &s, const DevEvents &ev,
                                           int64_t e, int32_t r, int32_t d) {
@@ -452,7 +568,7 @@ __device__ __forceinline__ void event_one(const Model &m, const DevState &s, con
     for (int c = 0; c < NC; ++c) {
         x[c] = 0;
         if ((mask >> c) & 1u) {
-            x[c] = s.u[(int64_t)c * s.L + ls];
+            x[c] = load_l2(&s.u[(int64_t)c * s.L + ls]);
             tot += x[c];
         }
     }
@@ -508,7 +624,7 @@ __device__ __forceinline__ void event_one(const Model &m, const DevState &s, con
                 for (int cc = 0; cc < NC; ++cc) {
                     if (cc == to) {
                         if (!((touched >> cc) & 1u)) {
-                            y[cc] = s.u[(int64_t)cc * s.L + ls];
+                            y[cc] = load_l2(&s.u[(int64_t)cc * s.L + ls]);
                             touched |= 1u << cc;
                         }
                         y[cc] += take[c];
@@ -548,12 +664,30 @@ __global__ __launch_bounds__(kBlock) void k_events(Model m, DevState s, DevEvent
     event_one<NC>(m, s, ev, e, r, d);
 }
 
+// A run of small levels [lv_begin, lv_end) of day d in one workgroup, with a
+// workgroup barrier between levels (the levels' order is all that links them).
+template <int NC>
+__global__ __launch_bounds__(kEvBlock) void k_event_levels(Model m, DevState s, DevEvents ev, int32_t d,
+                                                           int32_t lv_begin, int32_t lv_end) {
+    if (!block_ok(s)) return;
+    for (int32_t lv = lv_begin; lv < lv_end; ++lv) {
+        const int64_t begin = ev.lvl_off[lv], end = ev.lvl_off[lv + 1];
+        const int64_t count = (end - begin) * s.R;
+        for (int64_t t = threadIdx.x; t < count; t += kEvBlock) {
+            const int64_t e = begin + (s.R == 1 ? t : t / s.R);
+            event_one<NC>(m, s, ev, e, s.R == 1 ? 0 : (int32_t)(t % s.R), d);
+        }
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------------------
 // A run of days in one cooperative launch: phases separated by grid barriers.
 // ---------------------------------------------------------------------------
-template <int NC, int NT>
+template <class Rules>
 __global__ __launch_bounds__(kBlock) void k_persist(Model m, DevState s, DevEvents ev, int32_t d_begin,
                                                     int32_t d_end) {
+    constexpr int NC = Rules::NC;
     namespace cg = cooperative_groups;
     cg::grid_group grid = cg::this_grid();
     const int64_t stride = (int64_t)gridDim.x * kBlock;
@@ -561,15 +695,15 @@ __global__ __launch_bounds__(kBlock) void k_persist(Model m, DevState s, DevEven
     for (int32_t d = d_begin; d <= d_end; ++d) {
         const bool prologue = d > d_begin;
         const bool ssa = d < d_end;
-        if (*(volatile unsigned long long *)s.status == STATUS_OK) {
+        if (block_ok(s)) {
             Tally<NC> t{};
             const int64_t span = ((s.L + kBlock - 1) / kBlock) * kBlock;  // whole workgroups
             for (int64_t l = first; l < span; l += stride) {
                 if (s.R == 1) {
-                    day_wave<NC, NT>(m, s, l, d, prologue, ssa, t);
+                    day_wave<Rules>(m, s, l, d, prologue, ssa, t);
                 } else {
                     Tally<NC> one{};
-                    day_wave<NC, NT>(m, s, l, d, prologue, ssa, one);
+                    day_wave<Rules>(m, s, l, d, prologue, ssa, one);
                     if (l < s.L)
                         flush_lane<NC>(m, s, one, (int32_t)(l % s.R), prologue ? d - 1 : -1, ssa ? d : -1);
                 }
@@ -578,35 +712,63 @@ __global__ __launch_bounds__(kBlock) void k_persist(Model m, DevState s, DevEven
         }
         if (!ssa) break;
         grid.sync();
-        for (int32_t lv = ev.lvl_ptr[d]; lv < ev.lvl_ptr[d + 1]; ++lv) {
-            const int64_t begin = ev.lvl_off[lv], end = ev.lvl_off[lv + 1];
-            const int64_t count = (end - begin) * s.R;
-            if (*(volatile unsigned long long *)s.status == STATUS_OK) {
-                for (int64_t t = first; t < count; t += stride) {
-                    const int64_t e = begin + (s.R == 1 ? t : t / s.R);
-                    event_one<NC>(m, s, ev, e, s.R == 1 ? 0 : (int32_t)(t % s.R), d);
+        // big levels are spread over the grid; a run of small levels is done
+        // by workgroup 0 alone; one grid barrier follows either
+        int32_t lv = ev.lvl_ptr[d];
+        const int32_t lv_end = ev.lvl_ptr[d + 1];
+        while (lv < lv_end) {
+            const int64_t size = (ev.lvl_off[lv + 1] - ev.lvl_off[lv]) * s.R;
+            if (size > kSmallLevel) {
+                const int64_t begin = ev.lvl_off[lv];
+                if (*(volatile unsigned long long *)s.status == STATUS_OK) {
+                    for (int64_t t = first; t < size; t += stride) {
+                        const int64_t e = begin + (s.R == 1 ? t : t / s.R);
+                        event_one<NC>(m, s, ev, e, s.R == 1 ? 0 : (int32_t)(t % s.R), d);
+                    }
                 }
+                ++lv;
+            } else {
+                int32_t stop = lv + 1;
+                while (stop < lv_end && (ev.lvl_off[stop + 1] - ev.lvl_off[stop]) * s.R <= kSmallLevel) ++stop;
+                if (blockIdx.x == 0) {
+                    for (int32_t k = lv; k < stop; ++k) {
+                        const int64_t begin = ev.lvl_off[k];
+                        const int64_t count = (ev.lvl_off[k + 1] - begin) * s.R;
+                        for (int64_t t = threadIdx.x; t < count; t += kBlock) {
+                            const int64_t e = begin + (s.R == 1 ? t : t / s.R);
+                            event_one<NC>(m, s, ev, e, s.R == 1 ? 0 : (int32_t)(t % s.R), d);
+                        }
+                        __syncthreads();
+                    }
+                }
+                lv = stop;
             }
             grid.sync();
         }
     }
 }
 
-template <int NC, int NT>
+template <class Rules>
 struct Kernels {
-    static void *day() { return (void *)&k_day<NC, NT>; }
-    static void *events() { return (void *)&k_events<NC>; }
-    static void *persist() { return (void *)&k_persist<NC, NT>; }
+    static void *day() { return (void *)&k_day<Rules>; }
+    static void *events() { return (void *)&k_events<Rules::NC>; }
+    static void *levels() { return (void *)&k_event_levels<Rules::NC>; }
+    static void *persist() { return (void *)&k_persist<Rules>; }
 };
 
 struct Table {
-    void *day, *events, *persist;
+    void *day, *events, *persist, *levels;
 };
 
-Table pick(int nc, int nt) {
-    if (nc == 2 && nt == 2) return {Kernels<2, 2>::day(), Kernels<2, 2>::events(), Kernels<2, 2>::persist()};
-    if (nc == 6 && nt == 6) return {Kernels<6, 6>::day(), Kernels<6, 6>::events(), Kernels<6, 6>::persist()};
-    return {Kernels<MAXC, MAXT>::day(), Kernels<MAXC, MAXT>::events(), Kernels<MAXC, MAXT>::persist()};
+template <class Rules>
+Table table() {
+    return {Kernels<Rules>::day(), Kernels<Rules>::events(), Kernels<Rules>::persist(), Kernels<Rules>::levels()};
+}
+
+Table pick(const Model &m) {
+    if (m.pairs && m.nc == 2) return table<PairRules<1>>();
+    if (m.pairs && m.nc == 6) return table<PairRules<3>>();
+    return table<GenericRules<MAXC, MAXT>>();
 }
 
 }  // namespace
@@ -615,7 +777,7 @@ int launch_day(const Model &m, const DevState &s, int32_t d, int prologue, int s
                void *stream) {
     (void)block;
     if (s.L == 0) return hipSuccess;
-    const Table t = pick(m.nc, m.nt);
+    const Table t = pick(m);
     const unsigned grid = (unsigned)((s.L + kBlock - 1) / kBlock);
     Model mm = m;
     DevState ss = s;
@@ -628,7 +790,7 @@ int launch_events(const Model &m, const DevState &s, const DevEvents &ev, int32_
                   int64_t end, void *stream) {
     const int64_t count = (end - begin) * s.R;
     if (count <= 0) return hipSuccess;
-    const Table t = pick(m.nc, m.nt);
+    const Table t = pick(m);
     const unsigned grid = (unsigned)((count + kBlock - 1) / kBlock);
     Model mm = m;
     DevState ss = s;
@@ -639,10 +801,22 @@ int launch_events(const Model &m, const DevState &s, const DevEvents &ev, int32_
     return (int)hipLaunchKernel(t.events, dim3(grid), dim3(kBlock), args, 0, (hipStream_t)stream);
 }
 
+int launch_event_levels(const Model &m, const DevState &s, const DevEvents &ev, int32_t d, int32_t lv_begin,
+                        int32_t lv_end, void *stream) {
+    if (lv_end <= lv_begin) return hipSuccess;
+    const Table t = pick(m);
+    Model mm = m;
+    DevState ss = s;
+    DevEvents ee = ev;
+    int32_t dd = d, a = lv_begin, b = lv_end;
+    void *args[] = {&mm, &ss, &ee, &dd, &a, &b};
+    return (int)hipLaunchKernel(t.levels, dim3(1), dim3(kEvBlock), args, 0, (hipStream_t)stream);
+}
+
 int launch_persistent(const Model &m, const DevState &s, const DevEvents &ev, int32_t d_begin,
                       int32_t d_end, int block, void *stream, char *why, int why_len) {
     (void)block;
-    const Table t = pick(m.nc, m.nt);
+    const Table t = pick(m);
     int dev = 0;
     hipError_t err = hipGetDevice(&dev);
     if (err != hipSuccess) return (int)err;

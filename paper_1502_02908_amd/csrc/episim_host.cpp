@@ -133,8 +133,10 @@ Layout layout_for(int64_t Nn, int64_t Nc, int64_t Nt, int64_t R, int64_t D, int6
 }
 
 // Position of every node: herds sorted by size (largest first) are dealt out
-// one per wavefront in turn, so that the longest SSA chains of a day run in
-// different wavefronts and start first. perm[pos] = node, inv[node] = pos.
+// one per wavefront in turn, back and forth (snake order), so that the
+// longest SSA chains of a day run in different wavefronts, start first, and
+// share their wavefront with the lightest herds of the next round.
+// perm[pos] = node, inv[node] = pos.
 void order_nodes(const sim_problem *p, std::vector<int32_t> *perm, std::vector<int32_t> *inv) {
     const int64_t Nn = p->n_nodes, Nc = p->n_comp;
     std::vector<int64_t> size(Nn, 0);
@@ -149,7 +151,8 @@ void order_nodes(const sim_problem *p, std::vector<int32_t> *perm, std::vector<i
     inv->assign(Nn, 0);
     int64_t q = 0;
     for (int64_t j = 0; j < G; ++j)
-        for (int64_t w = 0; w < W; ++w) {
+        for (int64_t ww = 0; ww < W; ++ww) {
+            const int64_t w = (j & 1) ? W - 1 - ww : ww;
             const int64_t pos = w * G + j;
             if (pos >= Nn) continue;
             const int32_t node = rank[q++];
@@ -438,6 +441,15 @@ int sim_create(const sim_problem *p, const sim_device_opts *o, sim_handle **out)
     }
     m.imask = p->phi_I_mask;
     m.nmask = p->phi_N_mask;
+    // paired S <-> I classes: transition k moves one individual from compartment k to k ^ 1
+    m.pairs = (h->Nc == h->Nt && h->Nc % 2 == 0) ? 1 : 0;
+    for (int k = 0; k < h->Nt && m.pairs; ++k) {
+        if (p->reactant[k] != k) m.pairs = 0;
+        for (int c = 0; c < h->Nc && m.pairs; ++c) {
+            const int want = c == k ? -1 : (c == (k ^ 1) ? 1 : 0);
+            if (p->S[(size_t)c * h->Nt + k] != want) m.pairs = 0;
+        }
+    }
 
     // --- device memory
     h->lay = layout_for(h->Nn, h->Nc, h->Nt, h->R, h->D, n, count_shift_ids(p), n_levels, h->n_record);
@@ -580,10 +592,23 @@ int sim_run(sim_handle *h, int32_t n_days) {
         for (int32_t d = d0; d < d1; ++d) {
             hipError_t e = timed(h, SIM_K_DAY, [&] { return launch_day(h->model, h->st, d, d > d0, 1, h->block, h->stream); });
             if (e != hipSuccess) return h->err = fmt("day kernel: %s", hipGetErrorString(e)), SIM_EDEVICE;
-            for (int32_t lv = h->lvl_ptr[d]; lv < h->lvl_ptr[d + 1]; ++lv) {
-                e = timed(h, SIM_K_EVENTS, [&] {
-                    return launch_events(h->model, h->st, h->ev, d, h->lvl_off[lv], h->lvl_off[lv + 1], h->stream);
-                });
+            // big levels get a launch of their own; runs of small ones share one workgroup
+            int32_t lv = h->lvl_ptr[d];
+            const int32_t lv_end = h->lvl_ptr[d + 1];
+            while (lv < lv_end) {
+                const int64_t size = (h->lvl_off[lv + 1] - h->lvl_off[lv]) * h->R;
+                if (size > kSmallLevel) {
+                    e = timed(h, SIM_K_EVENTS, [&] {
+                        return launch_events(h->model, h->st, h->ev, d, h->lvl_off[lv], h->lvl_off[lv + 1], h->stream);
+                    });
+                    ++lv;
+                } else {
+                    int32_t stop = lv + 1;
+                    while (stop < lv_end && (h->lvl_off[stop + 1] - h->lvl_off[stop]) * h->R <= kSmallLevel) ++stop;
+                    const int32_t a = lv;
+                    e = timed(h, SIM_K_EVENTS, [&] { return launch_event_levels(h->model, h->st, h->ev, d, a, stop, h->stream); });
+                    lv = stop;
+                }
                 if (e != hipSuccess) return h->err = fmt("event kernel: %s", hipGetErrorString(e)), SIM_EDEVICE;
             }
         }

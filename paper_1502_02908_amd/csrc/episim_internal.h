@@ -32,6 +32,7 @@ constexpr int MAX_SHIFT_IDS = 63;
 // read with scalar loads).
 struct Model {
     int32_t nc, nt;
+    int32_t pairs;              // 1: compartments [S1,I1,...], transitions S_p<->I_p (see PairRules)
     int32_t day0;
     uint32_t seed;
     uint32_t uses_phi;          // bit k: rate k proportional to phi
@@ -77,6 +78,11 @@ int launch_day(const Model &m, const DevState &s, int32_t d, int prologue, int s
                void *stream);
 int launch_events(const Model &m, const DevState &s, const DevEvents &ev, int32_t d, int64_t begin,
                   int64_t end, void *stream);
+int launch_event_levels(const Model &m, const DevState &s, const DevEvents &ev, int32_t d, int32_t lv_begin,
+                        int32_t lv_end, void *stream);
+// levels of at most this many (event, replicate) pairs are grouped into one
+// single-workgroup launch
+constexpr int64_t kSmallLevel = 512;
 int launch_persistent(const Model &m, const DevState &s, const DevEvents &ev, int32_t d_begin,
                       int32_t d_end, int block, void *stream, char *why, int why_len);
 

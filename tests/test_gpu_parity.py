@@ -190,3 +190,28 @@ def test_heavy_chains_per_wavefront(heavy_per_wave):
     g, o = both(p)
     assert_parity(g, o)
     assert o["transitions"].sum() > 10 * heavy_per_wave * 3000
+
+
+def sir_network(n_days=60, waning=0.05):
+    """S -> I (upsilon*phi*S), I -> R (gamma*I), R -> S (waning*R): a model
+    outside the paired S<->I form, so the general stoichiometry path runs."""
+    base = synth.sis_network(n_nodes=800, n_days=n_days, seed=31, p_exit=0.01, p_enter=0.01, p_ext=0.005)
+    S = np.array([[-1, 0, 1], [1, -1, 0], [0, 1, -1]], np.int32)
+    u0 = np.zeros((base.n_nodes, 3), np.int32)
+    u0[:, :2] = base.u0
+    u0[::7, 1] += 5
+    E = np.array([[1, 1], [0, 1], [0, 1]], np.int32)
+    import dataclasses
+    return dataclasses.replace(
+        base, n_comp=3, n_trans=3, u0=u0, S=S, reactant=np.array([0, 1, 2], np.int32),
+        uses_phi=np.array([1, 0, 0], np.int32), coef=np.array([[0.3, 0.2, waning]]),
+        phi_I_mask=0b010, phi_N_mask=0b111, E=E, N=np.zeros((3, 0), np.int32), name="sir")
+
+
+@pytest.mark.parametrize("launch", [P.LAUNCH_KERNELS, P.LAUNCH_PERSISTENT])
+def test_general_stoichiometry_sir(launch):
+    p = sir_network()
+    p.record_days = np.array([5, 59], np.int32)
+    g, o = both(p, launch=launch)
+    assert_parity(g, o)
+    assert o["transitions"].sum() > 5000
