@@ -155,6 +155,21 @@ size_t sim_workspace_bytes(const sim_problem *p, const sim_device_opts *o);
  * describes it (thread-local). */
 int sim_create(const sim_problem *p, const sim_device_opts *o, sim_handle **out);
 
+/* One handle for several instances of one model (the problems share n_comp,
+ * n_trans, S, reactant, uses_phi, the phi masks, E, N, n_rep, n_days, day0 and
+ * record_days; they differ in nodes, state, rates, events, seed and
+ * replicate ids). Their nodes run in the same launches; every random stream
+ * uses the instance's own node numbers, event numbers and seed, so each
+ * instance follows exactly the trajectory it follows alone (the paper's
+ * fitting workload of many trajectories over one event database, Sec. 4.3).
+ * Records are indexed by set = instance * n_rep + replicate:
+ * prevalence[D * n_problems * n_rep] etc. State, snapshots and get/set_state
+ * use the instances' nodes concatenated in order: [r][node][c]. */
+int sim_create_batch(const sim_problem *const *problems, int32_t n_problems, const sim_device_opts *o,
+                     sim_handle **out);
+size_t sim_workspace_bytes_batch(const sim_problem *const *problems, int32_t n_problems,
+                                 const sim_device_opts *o);
+
 /* Enqueue days [day, day + n_days) on the handle's stream (n_days = 0: to the
  * horizon). Asynchronous: device-side errors (SIM_EINFEASIBLE) are reported
  * by the next synchronising call. SIM_ESTATE past the horizon. */

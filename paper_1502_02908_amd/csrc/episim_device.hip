@@ -267,11 +267,11 @@ __device__ __forceinline__ double lane_f64(double v, int lane) {
 // walked in order with the chosen transition held in a scalar register.
 template <class Rules>
 __device__ __forceinline__ void chain_uniform(const Model &m, typename Rules::State &c, uint32_t kbase,
-                                              uint32_t node, uint32_t day, uint32_t key1,
+                                              uint32_t node, uint32_t day, uint32_t key0, uint32_t key1,
                                               unsigned long long *status, int32_t r) {
     const uint32_t lane = threadIdx.x & 63u;
     for (;;) {
-        const Word4 o = philox4x32_10(Word4{kbase + lane, node, day, 0u}, m.seed, key1);
+        const Word4 o = philox4x32_10(Word4{kbase + lane, node, day, 0u}, key0, key1);
         const double e_mine = minus_log(unit_open(o.a, o.b));
         const double u_mine = unit_open(o.c, o.d);
         for (int i = 0; i < 64; ++i) {
@@ -300,9 +300,10 @@ __device__ __forceinline__ void chain_uniform(const Model &m, typename Rules::St
 // draws its own block. Every lane of the wavefront must call this.
 template <class Rules>
 __device__ __forceinline__ void run_chains(const Model &m, typename Rules::State &c, bool live, uint32_t node,
-                                           uint32_t day, uint32_t key1, unsigned long long *status, int32_t r) {
+                                           uint32_t day, uint32_t key0, uint32_t key1,
+                                           unsigned long long *status, int32_t r) {
     __shared__ double sh_e[kWaves][64], sh_u[kWaves][64];
-    __shared__ uint32_t sh_node[kWaves][64], sh_key[kWaves][64], sh_k[kWaves][64];
+    __shared__ uint32_t sh_node[kWaves][64], sh_key[kWaves][64], sh_seed[kWaves][64], sh_k[kWaves][64];
     const int wave = threadIdx.x >> 6;
     const uint32_t lane = threadIdx.x & 63u;
     uint32_t kbase = 0;  // next attempt index of this lane's chain
@@ -311,7 +312,7 @@ __device__ __forceinline__ void run_chains(const Model &m, typename Rules::State
         const unsigned long long mask = __ballot(live);
         if (mask == 0ull) break;
         if (mask == ~0ull) {
-            const Word4 o = philox4x32_10(Word4{kbase, node, day, 0u}, m.seed, key1);
+            const Word4 o = philox4x32_10(Word4{kbase, node, day, 0u}, key0, key1);
             kbase = kbase + 1;
             live = chain_step<Rules>(m, c, minus_log(unit_open(o.a, o.b)), unit_open(o.c, o.d), status, r);
             continue;
@@ -332,6 +333,7 @@ __device__ __forceinline__ void run_chains(const Model &m, typename Rules::State
             u.fired = __builtin_amdgcn_readlane(c.fired, h);
             chain_uniform<Rules>(m, u, (uint32_t)__builtin_amdgcn_readlane((int)kbase, h),
                                  (uint32_t)__builtin_amdgcn_readlane((int)node, h), day,
+                                 (uint32_t)__builtin_amdgcn_readlane((int)key0, h),
                                  (uint32_t)__builtin_amdgcn_readlane((int)key1, h), status,
                                  __builtin_amdgcn_readlane(r, h));
             if ((int)lane == h) c = u;
@@ -342,6 +344,7 @@ __device__ __forceinline__ void run_chains(const Model &m, typename Rules::State
         if (live) {
             sh_node[wave][rank] = node;
             sh_key[wave][rank] = key1;
+            sh_seed[wave][rank] = key0;
             sh_k[wave][rank] = kbase;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -349,8 +352,8 @@ __device__ __forceinline__ void run_chains(const Model &m, typename Rules::State
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         if (lane < nlive * per) {
             const uint32_t ch = lane % nlive, t = lane / nlive;
-            const Word4 o = philox4x32_10(Word4{sh_k[wave][ch] + t, sh_node[wave][ch], day, 0u}, m.seed,
-                                          sh_key[wave][ch]);
+            const Word4 o = philox4x32_10(Word4{sh_k[wave][ch] + t, sh_node[wave][ch], day, 0u},
+                                          sh_seed[wave][ch], sh_key[wave][ch]);
             sh_e[wave][ch * per + t] = minus_log(unit_open(o.a, o.b));
             sh_u[wave][ch * per + t] = unit_open(o.c, o.d);
         }
@@ -392,12 +395,14 @@ struct Tally {
     long long tot[NC];
 };
 
-// Sum tallies over the workgroup (R == 1) and add them to the day's records.
+// Sum tallies over the workgroup and add them to the records of one set
+// (every lane of the workgroup belongs to the same trajectory).
 template <int NC>
-__device__ void flush_block(const Model &m, const DevState &s, const Tally<NC> &t, int32_t d_rec,
+__device__ void flush_block(const Model &m, const DevState &s, const Tally<NC> &t, int32_t set, int32_t d_rec,
                             int32_t d_ssa) {
     __shared__ long long part[kWaves][2 + NC];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t S = (int64_t)s.n_inst * s.R;
     long long v[2 + NC];
     v[0] = t.prev;
     v[1] = t.trans;
@@ -415,23 +420,58 @@ __device__ void flush_block(const Model &m, const DevState &s, const Tally<NC> &
 #pragma unroll
         for (int q = 0; q < kWaves; ++q) sum += part[q][i];
         if (i == 0 && d_rec >= 0) {
-            if (sum) atomicAdd(&s.prevalence[d_rec], (int32_t)sum);
+            if (sum) atomicAdd(&s.prevalence[d_rec * S + set], (int32_t)sum);
         } else if (i == 1 && d_ssa >= 0) {
-            if (sum) atomicAdd((unsigned long long *)&s.transitions[d_ssa], (unsigned long long)sum);
+            if (sum) atomicAdd((unsigned long long *)&s.transitions[d_ssa * S + set], (unsigned long long)sum);
         } else if (i >= 2 && d_rec >= 0 && comp_on<NC>(m, i - 2)) {
-            if (sum) atomicAdd((unsigned long long *)&s.totals[(int64_t)d_rec * m.nc + (i - 2)],
+            if (sum) atomicAdd((unsigned long long *)&s.totals[(d_rec * S + set) * m.nc + (i - 2)],
                                (unsigned long long)sum);
         }
     }
     __syncthreads();
 }
 
-// Per-lane records when lanes of a workgroup belong to different replicates.
+// Sum tallies over the wavefronts of a replicate tile (lane = replicate) and
+// add them to the records of the lane's set.
+template <int NC>
+__device__ void flush_tile(const Model &m, const DevState &s, const Tally<NC> &t, int32_t set, int32_t d_rec,
+                           int32_t d_ssa) {
+    __shared__ long long part[kWaves][64][2 + NC];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t S = (int64_t)s.n_inst * s.R;
+    part[wave][lane][0] = t.prev;
+    part[wave][lane][1] = t.trans;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) part[wave][lane][2 + c] = t.tot[c];
+    __syncthreads();
+    if (wave == 0) {
+        long long v[2 + NC];
+#pragma unroll
+        for (int i = 0; i < 2 + NC; ++i) {
+            v[i] = 0;
+#pragma unroll
+            for (int q = 0; q < kWaves; ++q) v[i] += part[q][lane][i];
+        }
+        if (d_rec >= 0) {
+            if (v[0]) atomicAdd(&s.prevalence[d_rec * S + set], (int32_t)v[0]);
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                if (comp_on<NC>(m, c) && v[2 + c])
+                    atomicAdd((unsigned long long *)&s.totals[(d_rec * S + set) * m.nc + c], (unsigned long long)v[2 + c]);
+        }
+        if (d_ssa >= 0 && v[1])
+            atomicAdd((unsigned long long *)&s.transitions[d_ssa * S + set], (unsigned long long)v[1]);
+    }
+    __syncthreads();
+}
+
+// Per-lane records when the lanes of a workgroup belong to different sets.
 template <int NC>
 __device__ __forceinline__ void flush_lane(const Model &m, const DevState &s, const Tally<NC> &t,
-                                           int r, int32_t d_rec, int32_t d_ssa) {
+                                           int32_t set, int32_t d_rec, int32_t d_ssa) {
+    const int64_t S = (int64_t)s.n_inst * s.R;
     if (d_rec >= 0) {
-        const int64_t row = (int64_t)d_rec * s.R + r;
+        const int64_t row = d_rec * S + set;
         if (t.prev) atomicAdd(&s.prevalence[row], (int32_t)t.prev);
 #pragma unroll
         for (int c = 0; c < NC; ++c)
@@ -439,8 +479,7 @@ __device__ __forceinline__ void flush_lane(const Model &m, const DevState &s, co
                 atomicAdd((unsigned long long *)&s.totals[row * m.nc + c], (unsigned long long)t.tot[c]);
     }
     if (d_ssa >= 0 && t.trans)
-        atomicAdd((unsigned long long *)&s.transitions[(int64_t)d_ssa * s.R + r],
-                  (unsigned long long)t.trans);
+        atomicAdd((unsigned long long *)&s.transitions[d_ssa * S + set], (unsigned long long)t.trans);
 }
 
 // The day phase for the lane l of a wavefront (every lane of the wavefront
@@ -451,20 +490,23 @@ template <class Rules>
 __device__ __forceinline__ void day_wave(const Model &m, const DevState &s, int64_t l, int32_t d,
                                          bool prologue, bool ssa, Tally<Rules::NC> &t) {
     constexpr int NC = Rules::NC, NT = Rules::NT;
-    const bool active = l < s.L;
     const int32_t R = s.R;
-    const int32_t r = !active || R == 1 ? 0 : (int32_t)(l % R);
-    const int32_t pos = !active ? 0 : (R == 1 ? (int32_t)l : (int32_t)(l / R));
+    const bool in_range = l < s.L;
+    const int32_t r = !in_range || R == 1 ? 0 : (int32_t)(l % R);
+    const int32_t pos = !in_range ? 0 : (R == 1 ? (int32_t)l : (int32_t)(l / R));
+    const int32_t nid = in_range ? s.node_id[pos] : -1;
+    const bool active = nid >= 0;  // padding positions take part in the wavefront steps only
+    const int32_t inst = active ? s.inst[pos] : 0;
+    const int32_t set = inst * R + r;
     int32_t x[NC];
     double phi = 0.0;
-    uint32_t node = 0;
+    const uint32_t node = active ? (uint32_t)nid : 0u;
 #pragma unroll
     for (int c = 0; c < NC; ++c) x[c] = 0;
     if (active) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) x[c] = comp_on<NC>(m, c) ? s.u[(int64_t)c * s.L + l] : 0;
         phi = s.phi[l];
-        node = (uint32_t)s.node_id[pos];
     }
     if (active && prologue) {
         const double phi_in = phi;
@@ -476,16 +518,16 @@ __device__ __forceinline__ void day_wave(const Model &m, const DevState &s, int6
             if ((m.nmask >> c) & 1u) N += x[c];
         }
         const int q = season((int64_t)m.day0 + dp);
-        const double a = 1.0 - s.beta[r * 4 + q];
+        const double a = 1.0 - s.beta[set * 4 + q];
         const double b = a * phi;
-        const double shed = N > 0 ? s.alpha[r] * ((double)I / (double)N) : 0.0;
+        const double shed = N > 0 ? s.alpha[set] * ((double)I / (double)N) : 0.0;
         phi = b + shed;
         t.prev += I > 0 ? 1 : 0;
 #pragma unroll
         for (int c = 0; c < NC; ++c) t.tot[c] += x[c];
         const int32_t slot = s.rec_slot[dp];
         if (slot >= 0) {
-            const int64_t base = (((int64_t)slot * R + r) * s.Nn + node);
+            const int64_t base = (((int64_t)slot * R + r) * s.n_nodes + s.inst_off[inst] + node);
 #pragma unroll
             for (int c = 0; c < NC; ++c)
                 if (comp_on<NC>(m, c)) s.snap_u[base * m.nc + c] = x[c];
@@ -495,10 +537,11 @@ __device__ __forceinline__ void day_wave(const Model &m, const DevState &s, int6
     }
     if (!ssa) return;
     typename Rules::State ch;
-    const uint32_t key1 = active ? s.repid[r] : 0u;
+    const uint32_t key0 = active ? s.seed[inst] : 0u;
+    const uint32_t key1 = active ? s.repid[set] : 0u;
 #pragma unroll
     for (int k = 0; k < NT; ++k) {
-        double c = active && trans_on<NT>(m, k) ? s.coef[r * m.nt + k] : 0.0;
+        double c = active && trans_on<NT>(m, k) ? s.coef[set * m.nt + k] : 0.0;
         if ((m.uses_phi >> k) & 1u) c = c * phi;
         ch.cphi[k] = c;
     }
@@ -507,7 +550,7 @@ __device__ __forceinline__ void day_wave(const Model &m, const DevState &s, int6
     ch.clock = 0.0;
     ch.fired = 0;
     Rules::rates(m, ch);
-    run_chains<Rules>(m, ch, active, node, (uint32_t)d, key1, s.status, r);
+    run_chains<Rules>(m, ch, active, node, (uint32_t)d, key0, key1, s.status, set);
     t.trans += ch.fired;
     if (active && ch.fired) {
 #pragma unroll
@@ -527,10 +570,33 @@ __global__ __launch_bounds__(kBlock) void k_day(Model m, DevState s, int32_t d, 
     const int32_t d_rec = prologue ? d - 1 : -1;
     const int32_t d_ssa = ssa ? d : -1;
     if (s.R == 1) {
-        flush_block<NC>(m, s, t, d_rec, d_ssa);
-    } else if (l < s.L) {
-        flush_lane<NC>(m, s, t, (int32_t)(l % s.R), d_rec, d_ssa);
+        // instances are padded to whole workgroups: one set per workgroup
+        flush_block<NC>(m, s, t, s.inst[(int64_t)blockIdx.x * kBlock], d_rec, d_ssa);
+    } else if (l < s.L && s.node_id[l / s.R] >= 0) {
+        flush_lane<NC>(m, s, t, s.inst[l / s.R] * s.R + (int32_t)(l % s.R), d_rec, d_ssa);
     }
+}
+
+// Replicate tiles (R a multiple of 64): workgroup (x, y) takes positions
+// [x * kTileNodes, (x + 1) * kTileNodes) and replicates [64 y, 64 y + 64);
+// wavefront w walks the positions w, w + 4, ... so a lane always holds the
+// same replicate and its counts add up in registers.
+template <class Rules>
+__global__ __launch_bounds__(kBlock) void k_day_tile(Model m, DevState s, int32_t d, int32_t prologue,
+                                                     int32_t ssa) {
+    constexpr int NC = Rules::NC;
+    if (!block_ok(s)) return;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t pos0 = (int64_t)blockIdx.x * kTileNodes;
+    const int32_t r = (int32_t)blockIdx.y * 64 + lane;
+    Tally<NC> t{};
+    for (int j = wave; j < kTileNodes; j += kWaves) {
+        const int64_t pos = pos0 + j;
+        if (pos >= s.Np) break;
+        day_wave<Rules>(m, s, pos * s.R + r, d, prologue != 0, ssa != 0, t);
+    }
+    // instances are padded to whole tiles: one instance per workgroup
+    flush_tile<NC>(m, s, t, s.inst[pos0] * s.R + r, prologue ? d - 1 : -1, ssa ? d : -1);
 }
 
 // ---------------------------------------------------------------------------
@@ -573,19 +639,22 @@ __device__ __forceinline__ void event_one(const Model &m, const DevState &s, con
         }
     }
     const uint32_t g = (uint32_t)ev.g[e];
+    const int32_t inst = s.inst[node];
+    const int32_t set = inst * s.R + r;
     if ((long long)n > tot) {
-        atomicMin(s.status, ((unsigned long long)g << 32) | (unsigned long long)(uint32_t)r);
+        atomicMin(s.status, ((unsigned long long)(uint32_t)ev.gm[e] << 32) | (unsigned long long)(uint32_t)set);
         return;
     }
     int32_t take[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) take[c] = 0;
-    const uint32_t key1 = s.repid[r];
+    const uint32_t key0 = s.seed[inst];
+    const uint32_t key1 = s.repid[set];
     Word4 o{0, 0, 0, 0};
     for (int32_t q = 0; q < n; ++q) {
         uint64_t bits;
         if ((q & 1) == 0) {
-            o = philox4x32_10(Word4{(uint32_t)q >> 1, g, (uint32_t)d, 1u}, m.seed, key1);
+            o = philox4x32_10(Word4{(uint32_t)q >> 1, g, (uint32_t)d, 1u}, key0, key1);
             bits = ((uint64_t)o.b << 32) | o.a;
         } else {
             bits = ((uint64_t)o.d << 32) | o.c;
@@ -686,7 +755,7 @@ __global__ __launch_bounds__(kEvBlock) void k_event_levels(Model m, DevState s, 
 // ---------------------------------------------------------------------------
 template <class Rules>
 __global__ __launch_bounds__(kBlock) void k_persist(Model m, DevState s, DevEvents ev, int32_t d_begin,
-                                                    int32_t d_end) {
+                                                    int32_t d_end, int32_t layout) {
     constexpr int NC = Rules::NC;
     namespace cg = cooperative_groups;
     cg::grid_group grid = cg::this_grid();
@@ -695,20 +764,36 @@ __global__ __launch_bounds__(kBlock) void k_persist(Model m, DevState s, DevEven
     for (int32_t d = d_begin; d <= d_end; ++d) {
         const bool prologue = d > d_begin;
         const bool ssa = d < d_end;
+        const int32_t d_rec = prologue ? d - 1 : -1, d_ssa = ssa ? d : -1;
         if (block_ok(s)) {
-            Tally<NC> t{};
-            const int64_t span = ((s.L + kBlock - 1) / kBlock) * kBlock;  // whole workgroups
-            for (int64_t l = first; l < span; l += stride) {
-                if (s.R == 1) {
+            if (layout == LAYOUT_TILE) {
+                const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+                const int64_t nx = (s.Np + kTileNodes - 1) / kTileNodes;
+                const int64_t n_tiles = nx * (s.R / 64);
+                for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+                    const int64_t pos0 = (tile % nx) * kTileNodes;
+                    const int32_t r = (int32_t)(tile / nx) * 64 + lane;
+                    Tally<NC> t{};
+                    for (int j = wave; j < kTileNodes; j += kWaves) {
+                        const int64_t pos = pos0 + j;
+                        if (pos >= s.Np) break;
+                        day_wave<Rules>(m, s, pos * s.R + r, d, prologue, ssa, t);
+                    }
+                    flush_tile<NC>(m, s, t, s.inst[pos0] * s.R + r, d_rec, d_ssa);
+                }
+            } else {
+                const int64_t chunks = (s.L + kBlock - 1) / kBlock;
+                for (int64_t chunk = blockIdx.x; chunk < chunks; chunk += gridDim.x) {
+                    const int64_t l = chunk * kBlock + threadIdx.x;
+                    Tally<NC> t{};
                     day_wave<Rules>(m, s, l, d, prologue, ssa, t);
-                } else {
-                    Tally<NC> one{};
-                    day_wave<Rules>(m, s, l, d, prologue, ssa, one);
-                    if (l < s.L)
-                        flush_lane<NC>(m, s, one, (int32_t)(l % s.R), prologue ? d - 1 : -1, ssa ? d : -1);
+                    if (s.R == 1) {
+                        flush_block<NC>(m, s, t, s.inst[chunk * kBlock], d_rec, d_ssa);
+                    } else if (l < s.L && s.node_id[l / s.R] >= 0) {
+                        flush_lane<NC>(m, s, t, s.inst[l / s.R] * s.R + (int32_t)(l % s.R), d_rec, d_ssa);
+                    }
                 }
             }
-            if (s.R == 1) flush_block<NC>(m, s, t, prologue ? d - 1 : -1, ssa ? d : -1);
         }
         if (!ssa) break;
         grid.sync();
@@ -751,18 +836,20 @@ __global__ __launch_bounds__(kBlock) void k_persist(Model m, DevState s, DevEven
 template <class Rules>
 struct Kernels {
     static void *day() { return (void *)&k_day<Rules>; }
+    static void *tile() { return (void *)&k_day_tile<Rules>; }
     static void *events() { return (void *)&k_events<Rules::NC>; }
     static void *levels() { return (void *)&k_event_levels<Rules::NC>; }
     static void *persist() { return (void *)&k_persist<Rules>; }
 };
 
 struct Table {
-    void *day, *events, *persist, *levels;
+    void *day, *events, *persist, *levels, *tile;
 };
 
 template <class Rules>
 Table table() {
-    return {Kernels<Rules>::day(), Kernels<Rules>::events(), Kernels<Rules>::persist(), Kernels<Rules>::levels()};
+    return {Kernels<Rules>::day(), Kernels<Rules>::events(), Kernels<Rules>::persist(), Kernels<Rules>::levels(),
+            Kernels<Rules>::tile()};
 }
 
 Table pick(const Model &m) {
@@ -773,16 +860,20 @@ Table pick(const Model &m) {
 
 }  // namespace
 
-int launch_day(const Model &m, const DevState &s, int32_t d, int prologue, int ssa, int block,
+int launch_day(const Model &m, const DevState &s, int32_t d, int prologue, int ssa, int layout,
                void *stream) {
-    (void)block;
     if (s.L == 0) return hipSuccess;
     const Table t = pick(m);
-    const unsigned grid = (unsigned)((s.L + kBlock - 1) / kBlock);
     Model mm = m;
     DevState ss = s;
     int32_t dd = d, pro = prologue, sa = ssa;
     void *args[] = {&mm, &ss, &dd, &pro, &sa};
+    if (layout == LAYOUT_TILE) {
+        const unsigned nx = (unsigned)((s.Np + kTileNodes - 1) / kTileNodes);
+        return (int)hipLaunchKernel(t.tile, dim3(nx, (unsigned)(s.R / 64)), dim3(kBlock), args, 0,
+                                    (hipStream_t)stream);
+    }
+    const unsigned grid = (unsigned)((s.L + kBlock - 1) / kBlock);
     return (int)hipLaunchKernel(t.day, dim3(grid), dim3(kBlock), args, 0, (hipStream_t)stream);
 }
 
@@ -814,8 +905,7 @@ int launch_event_levels(const Model &m, const DevState &s, const DevEvents &ev, 
 }
 
 int launch_persistent(const Model &m, const DevState &s, const DevEvents &ev, int32_t d_begin,
-                      int32_t d_end, int block, void *stream, char *why, int why_len) {
-    (void)block;
+                      int32_t d_end, int layout, void *stream, char *why, int why_len) {
     const Table t = pick(m);
     int dev = 0;
     hipError_t err = hipGetDevice(&dev);
@@ -829,14 +919,15 @@ int launch_persistent(const Model &m, const DevState &s, const DevEvents &ev, in
         snprintf(why, why_len, "persistent kernel cannot be resident (occupancy 0)");
         return (int)hipErrorInvalidConfiguration;
     }
-    const int64_t want = (s.L + kBlock - 1) / kBlock;
+    const int64_t want = layout == LAYOUT_TILE ? ((s.Np + kTileNodes - 1) / kTileNodes) * (s.R / 64)
+                                               : (s.L + kBlock - 1) / kBlock;
     int64_t grid = (int64_t)cus * per_cu;
     if (want < grid) grid = want > 0 ? want : 1;
     Model mm = m;
     DevState ss = s;
     DevEvents ee = ev;
-    int32_t a = d_begin, b = d_end;
-    void *args[] = {&mm, &ss, &ee, &a, &b};
+    int32_t a = d_begin, b = d_end, lay = layout;
+    void *args[] = {&mm, &ss, &ee, &a, &b, &lay};
     return (int)hipLaunchCooperativeKernel(t.persist, dim3((unsigned)grid), dim3(kBlock), args, 0,
                                            (hipStream_t)stream);
 }

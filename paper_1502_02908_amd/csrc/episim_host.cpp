@@ -11,6 +11,12 @@
 // meeting these rules, so one level runs fully in parallel and levels run in
 // order. The levels are computed once per handle and reused by every run and
 // replicate, as the paper reuses its re-arranged lists across runs.
+//
+// A handle holds one or more instances (networks) of one model. Instances are
+// packed into one range of node positions, each padded to whole wavefronts /
+// workgroups / tiles so that every unit of work belongs to one instance; the
+// random streams use each instance's own node numbers, event numbers and
+// seed, so an instance packed with others gives the same trajectory as alone.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -43,7 +49,7 @@ std::string fmt(const char *f, ...) {
 bool is_sampler(int kind) { return kind == SIM_EXIT || kind == SIM_INTERNAL || kind == SIM_EXTERNAL; }
 
 // Level of every event within its day; events must already be sorted by day.
-// Returns the number of levels of each day in day_levels (resized to n_days).
+// Records the number of levels of each day in day_levels (resized to n_days).
 void plan_levels(int64_t n, const int32_t *day, const int32_t *kind, const int32_t *node,
                  const int32_t *dest, int32_t n_nodes, int32_t *level,
                  std::vector<int32_t> *day_levels, int32_t n_days) {
@@ -51,13 +57,12 @@ void plan_levels(int64_t n, const int32_t *day, const int32_t *kind, const int32
     // the day stored in stamp (so nothing is cleared between days)
     std::vector<int32_t> stamp(n_nodes, -1), last_any(n_nodes, 0), last_draw(n_nodes, 0);
     if (day_levels) day_levels->assign(n_days > 0 ? n_days : 0, 0);
-    auto get = [&](std::vector<int32_t> &a, int32_t x, int32_t d) {
+    auto touch = [&](int32_t x, int32_t d) {
         if (stamp[x] != d) {
             stamp[x] = d;
             last_any[x] = 0;
             last_draw[x] = 0;
         }
-        return a[x];
     };
     for (int64_t e = 0; e < n; ++e) {
         const int32_t d = day[e];
@@ -66,18 +71,20 @@ void plan_levels(int64_t n, const int32_t *day, const int32_t *kind, const int32
         const bool draws = is_sampler(kind[e]);
         // the node an event adds to: ENTER adds at its node, EXTERNAL at dest
         const int32_t add = kind[e] == SIM_ENTER ? src : (kind[e] == SIM_EXTERNAL ? dest[e] : -1);
-        if (draws) L = std::max(L, get(last_any, src, d) + 1);
-        if (add >= 0) L = std::max(L, get(last_draw, add, d) + 1);
+        if (draws) {
+            touch(src, d);
+            L = std::max(L, last_any[src] + 1);
+        }
+        if (add >= 0) {
+            touch(add, d);
+            L = std::max(L, last_draw[add] + 1);
+        }
         level[e] = L;
         if (draws) {
-            get(last_any, src, d);
             last_any[src] = std::max(last_any[src], L);
             last_draw[src] = L;
         }
-        if (add >= 0) {
-            get(last_any, add, d);
-            last_any[add] = std::max(last_any[add], L);
-        }
+        if (add >= 0) last_any[add] = std::max(last_any[add], L);
         if (day_levels) (*day_levels)[d] = std::max((*day_levels)[d], L);
     }
 }
@@ -88,79 +95,6 @@ int check_device(hipError_t e, std::string *err, const char *what) {
     return SIM_EDEVICE;
 }
 
-// Device buffer layout of one handle.
-struct Layout {
-    size_t u, phi, node_id, coef, alpha, beta, repid, shift, status, ev_g, ev_node, ev_dest, ev_n, ev_meta,
-        lvl_off, lvl_ptr, prevalence, transitions, totals, snap_u, snap_v, rec_slot, total;
-};
-
-size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
-
-Layout layout_for(int64_t Nn, int64_t Nc, int64_t Nt, int64_t R, int64_t D, int64_t n_events,
-                  int64_t n_shift_ids, int64_t n_levels, int64_t n_record) {
-    Layout l{};
-    size_t off = 0;
-    auto take = [&](size_t bytes) {
-        size_t at = off;
-        off = align_up(off + std::max<size_t>(bytes, 1));
-        return at;
-    };
-    const int64_t L = Nn * R;
-    l.u = take(sizeof(int32_t) * Nc * L);
-    l.phi = take(sizeof(double) * L);
-    l.node_id = take(sizeof(int32_t) * Nn);
-    l.coef = take(sizeof(double) * R * Nt);
-    l.alpha = take(sizeof(double) * R);
-    l.beta = take(sizeof(double) * R * 4);
-    l.repid = take(sizeof(uint32_t) * R);
-    l.shift = take(sizeof(int32_t) * MAXC * std::max<int64_t>(n_shift_ids, 1));
-    l.status = take(sizeof(unsigned long long));
-    l.ev_g = take(sizeof(int32_t) * n_events);
-    l.ev_node = take(sizeof(int32_t) * n_events);
-    l.ev_dest = take(sizeof(int32_t) * n_events);
-    l.ev_n = take(sizeof(int32_t) * n_events);
-    l.ev_meta = take(sizeof(uint32_t) * n_events);
-    l.lvl_off = take(sizeof(int64_t) * (n_levels + 1));
-    l.lvl_ptr = take(sizeof(int32_t) * (D + 1));
-    l.prevalence = take(sizeof(int32_t) * D * R);
-    l.transitions = take(sizeof(int64_t) * D * R);
-    l.totals = take(sizeof(int64_t) * D * R * Nc);
-    l.snap_u = take(sizeof(int32_t) * n_record * R * Nn * Nc);
-    l.snap_v = take(sizeof(double) * n_record * R * Nn);
-    l.rec_slot = take(sizeof(int32_t) * D);
-    l.total = off;
-    return l;
-}
-
-// Position of every node: herds sorted by size (largest first) are dealt out
-// one per wavefront in turn, back and forth (snake order), so that the
-// longest SSA chains of a day run in different wavefronts, start first, and
-// share their wavefront with the lightest herds of the next round.
-// perm[pos] = node, inv[node] = pos.
-void order_nodes(const sim_problem *p, std::vector<int32_t> *perm, std::vector<int32_t> *inv) {
-    const int64_t Nn = p->n_nodes, Nc = p->n_comp;
-    std::vector<int64_t> size(Nn, 0);
-    for (int64_t i = 0; i < Nn; ++i)
-        for (int64_t c = 0; c < Nc; ++c) size[i] += p->u0[i * Nc + c];
-    std::vector<int32_t> rank(Nn);
-    for (int64_t i = 0; i < Nn; ++i) rank[i] = (int32_t)i;
-    std::stable_sort(rank.begin(), rank.end(), [&](int32_t a, int32_t b) { return size[a] > size[b]; });
-    const int64_t G = std::max<int64_t>(1, 64 / p->n_rep);  // nodes per wavefront
-    const int64_t W = (Nn + G - 1) / G;                     // wavefronts
-    perm->assign(Nn, 0);
-    inv->assign(Nn, 0);
-    int64_t q = 0;
-    for (int64_t j = 0; j < G; ++j)
-        for (int64_t ww = 0; ww < W; ++ww) {
-            const int64_t w = (j & 1) ? W - 1 - ww : ww;
-            const int64_t pos = w * G + j;
-            if (pos >= Nn) continue;
-            const int32_t node = rank[q++];
-            (*perm)[pos] = node;
-            (*inv)[node] = (int32_t)pos;
-        }
-}
-
 uint32_t column_mask(const sim_problem *p, int32_t s) {
     uint32_t m = 0;
     for (int c = 0; c < p->n_comp; ++c)
@@ -168,7 +102,7 @@ uint32_t column_mask(const sim_problem *p, int32_t s) {
     return m;
 }
 
-// Full validation of the problem statement (the contract in episim.h).
+// Full validation of one problem statement (the contract in episim.h).
 int validate(const sim_problem *p, std::string *err) {
     if (!p) return *err = "problem is NULL", SIM_EINVAL;
     if (p->n_nodes < 0) return *err = "n_nodes < 0", SIM_EINVAL;
@@ -252,15 +186,267 @@ int validate(const sim_problem *p, std::string *err) {
     return SIM_OK;
 }
 
+
+// Problems packed into one handle must share the model and the run shape.
+int same_model(const sim_problem *a, const sim_problem *b, std::string *err) {
+    auto eq = [](const void *x, const void *y, size_t n) { return n == 0 || std::memcmp(x, y, n) == 0; };
+    const size_t Nc = a->n_comp, Nt = a->n_trans;
+    if (a->n_comp != b->n_comp || a->n_trans != b->n_trans || a->n_rep != b->n_rep || a->n_days != b->n_days ||
+        a->day0 != b->day0 || a->phi_I_mask != b->phi_I_mask || a->phi_N_mask != b->phi_N_mask ||
+        a->n_select != b->n_select || a->n_shift != b->n_shift || a->n_record != b->n_record)
+        return *err = "packed problems must share sizes, replicates, horizon, day0, masks and record days", SIM_EINVAL;
+    if (!eq(a->S, b->S, sizeof(int32_t) * Nc * Nt) || !eq(a->reactant, b->reactant, sizeof(int32_t) * Nt) ||
+        !eq(a->uses_phi, b->uses_phi, sizeof(int32_t) * Nt) ||
+        !eq(a->E, b->E, sizeof(int32_t) * Nc * a->n_select) || !eq(a->N, b->N, sizeof(int32_t) * Nc * a->n_shift) ||
+        !eq(a->record_days, b->record_days, sizeof(int32_t) * a->n_record))
+        return *err = "packed problems must share the model (S, reactants, uses_phi, E, N) and record days", SIM_EINVAL;
+    return SIM_OK;
+}
+
+int choose_layout(int32_t R) {
+    if (R == 1) return LAYOUT_LANES;
+    if (R % 64 == 0) return LAYOUT_TILE;
+    return LAYOUT_LANES_ATOMIC;
+}
+
+// Nodes of one unit of work and the padding granule of an instance.
+int64_t unit_nodes(int layout, int32_t R) {
+    if (layout == LAYOUT_TILE) return kTileNodes;
+    return std::max<int64_t>(1, 64 / R);
+}
+int64_t pad_nodes(int layout, int32_t R) {
+    if (layout == LAYOUT_TILE) return kTileNodes;
+    if (layout == LAYOUT_LANES) return 256;  // one workgroup
+    return std::max<int64_t>(1, 64 / R);
+}
+
+// Positions of one instance's nodes: herds sorted by size (largest first)
+// are dealt one per unit of work in turn, back and forth (snake order), so the
+// longest SSA chains of a day run in different units, start first, and share
+// their unit with the lightest herds of the next round. Returns the number of
+// positions (a multiple of the padding granule); pos_node[pos] = node or -1.
+int64_t order_nodes(const sim_problem *p, int layout, std::vector<int32_t> *pos_node) {
+    const int64_t Nn = p->n_nodes, Nc = p->n_comp;
+    std::vector<int64_t> size(Nn, 0);
+    for (int64_t i = 0; i < Nn; ++i)
+        for (int64_t c = 0; c < Nc; ++c) size[i] += p->u0[i * Nc + c];
+    std::vector<int32_t> rank(Nn);
+    for (int64_t i = 0; i < Nn; ++i) rank[i] = (int32_t)i;
+    std::stable_sort(rank.begin(), rank.end(), [&](int32_t a, int32_t b) { return size[a] > size[b]; });
+    const int64_t G = unit_nodes(layout, p->n_rep), P = pad_nodes(layout, p->n_rep);
+    const int64_t Np = Nn == 0 ? 0 : ((Nn + P - 1) / P) * P;
+    const int64_t U = Np / G;
+    pos_node->assign(Np, -1);
+    int64_t q = 0;
+    for (int64_t j = 0; j < G && q < Nn; ++j)
+        for (int64_t uu = 0; uu < U && q < Nn; ++uu) {
+            const int64_t u = (j & 1) ? U - 1 - uu : uu;
+            (*pos_node)[u * G + j] = rank[q++];
+        }
+    return Np;
+}
+
+// Device buffer layout of one handle.
+struct Layout {
+    size_t u, phi, node_id, inst, inst_off, seed, coef, alpha, beta, repid, shift, status, ev_g, ev_gm, ev_node,
+        ev_dest, ev_n, ev_meta, lvl_off, lvl_ptr, prevalence, transitions, totals, snap_u, snap_v, rec_slot, total;
+};
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+Layout layout_for(int64_t Np, int64_t n_nodes, int64_t n_inst, int64_t Nc, int64_t Nt, int64_t R, int64_t D,
+                  int64_t n_events, int64_t n_shift_ids, int64_t n_levels, int64_t n_record) {
+    Layout l{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + std::max<size_t>(bytes, 1));
+        return at;
+    };
+    const int64_t L = Np * R, S = n_inst * R;
+    l.u = take(sizeof(int32_t) * Nc * L);
+    l.phi = take(sizeof(double) * L);
+    l.node_id = take(sizeof(int32_t) * Np);
+    l.inst = take(sizeof(int32_t) * Np);
+    l.inst_off = take(sizeof(int32_t) * n_inst);
+    l.seed = take(sizeof(uint32_t) * n_inst);
+    l.coef = take(sizeof(double) * S * Nt);
+    l.alpha = take(sizeof(double) * S);
+    l.beta = take(sizeof(double) * S * 4);
+    l.repid = take(sizeof(uint32_t) * S);
+    l.shift = take(sizeof(int32_t) * MAXC * std::max<int64_t>(n_shift_ids, 1));
+    l.status = take(sizeof(unsigned long long));
+    l.ev_g = take(sizeof(int32_t) * n_events);
+    l.ev_gm = take(sizeof(int32_t) * n_events);
+    l.ev_node = take(sizeof(int32_t) * n_events);
+    l.ev_dest = take(sizeof(int32_t) * n_events);
+    l.ev_n = take(sizeof(int32_t) * n_events);
+    l.ev_meta = take(sizeof(uint32_t) * n_events);
+    l.lvl_off = take(sizeof(int64_t) * (n_levels + 1));
+    l.lvl_ptr = take(sizeof(int32_t) * (D + 1));
+    l.prevalence = take(sizeof(int32_t) * D * S);
+    l.transitions = take(sizeof(int64_t) * D * S);
+    l.totals = take(sizeof(int64_t) * D * S * Nc);
+    l.snap_u = take(sizeof(int32_t) * n_record * R * n_nodes * Nc);
+    l.snap_v = take(sizeof(double) * n_record * R * n_nodes);
+    l.rec_slot = take(sizeof(int32_t) * D);
+    l.total = off;
+    return l;
+}
+
+// Everything a handle uploads, built on the host from one or more problems.
+struct Packed {
+    int32_t n_inst = 0, R = 0, D = 0, Nc = 0, Nt = 0, n_record = 0, layout = 0;
+    int64_t Np = 0, n_nodes = 0, n_events = 0, n_levels = 0;
+    std::vector<int32_t> node_id, inst, inst_off, inst_pos0;
+    std::vector<uint32_t> seed, repid;
+    std::vector<double> coef, alpha, beta;
+    std::vector<int32_t> lane_of;  // [n_nodes] position of each concatenated node
+    // merged events in execution order and their levels
+    std::vector<int32_t> eg, egm, enode, edest, en, ev_inst, ev_local;
+    std::vector<uint32_t> emeta;
+    std::vector<int32_t> lvl_ptr;
+    std::vector<int64_t> lvl_off;
+    std::vector<int32_t> rec_slot;
+};
+
+int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, Packed *pk, std::string *err) {
+    if (n < 1 || !ps) return *err = "no problems", SIM_EINVAL;
+    for (int32_t k = 0; k < n; ++k) {
+        int rc = validate(ps[k], err);
+        if (rc) {
+            if (n > 1) *err = fmt("problem %d: %s", k, err->c_str());
+            return rc;
+        }
+        if (k > 0 && (rc = same_model(ps[0], ps[k], err))) return rc;
+    }
+    if (events_mode != SIM_EVENTS_LEVELS && events_mode != SIM_EVENTS_SERIAL)
+        return *err = "unknown events_mode", SIM_EINVAL;
+    const sim_problem *p0 = ps[0];
+    pk->n_inst = n;
+    pk->R = p0->n_rep;
+    pk->D = p0->n_days;
+    pk->Nc = p0->n_comp;
+    pk->Nt = p0->n_trans;
+    pk->n_record = p0->n_record;
+    pk->layout = choose_layout(pk->R);
+    const int32_t R = pk->R;
+    // positions
+    std::vector<std::vector<int32_t>> pos_node(n);
+    pk->inst_off.assign(n, 0);
+    pk->inst_pos0.assign(n, 0);
+    for (int32_t k = 0; k < n; ++k) {
+        pk->inst_off[k] = (int32_t)pk->n_nodes;
+        pk->inst_pos0[k] = (int32_t)pk->Np;
+        pk->Np += order_nodes(ps[k], pk->layout, &pos_node[k]);
+        pk->n_nodes += ps[k]->n_nodes;
+        pk->n_events += ps[k]->n_events;
+    }
+    if (pk->Np * (int64_t)R > INT32_MAX) return *err = "positions x replicates must stay below 2^31", SIM_EINVAL;
+    if (pk->n_events > INT32_MAX) return *err = "too many events", SIM_EINVAL;
+    pk->node_id.assign(pk->Np, -1);
+    pk->inst.assign(pk->Np, 0);
+    pk->lane_of.assign(pk->n_nodes, 0);
+    for (int32_t k = 0; k < n; ++k) {
+        const int64_t P = (int64_t)pos_node[k].size();
+        for (int64_t j = 0; j < P; ++j) {
+            const int64_t pos = pk->inst_pos0[k] + j;
+            pk->node_id[pos] = pos_node[k][j];
+            pk->inst[pos] = k;
+            if (pos_node[k][j] >= 0) pk->lane_of[pk->inst_off[k] + pos_node[k][j]] = (int32_t)pos;
+        }
+    }
+    // parameters per set = instance * R + replicate
+    const int64_t S = (int64_t)n * R;
+    pk->seed.resize(n);
+    pk->coef.resize(S * pk->Nt);
+    pk->alpha.resize(S);
+    pk->beta.resize(S * 4);
+    pk->repid.resize(S);
+    for (int32_t k = 0; k < n; ++k) {
+        const sim_problem *p = ps[k];
+        pk->seed[k] = p->seed;
+        std::memcpy(&pk->coef[(size_t)k * R * pk->Nt], p->coef, sizeof(double) * R * pk->Nt);
+        std::memcpy(&pk->alpha[(size_t)k * R], p->alpha, sizeof(double) * R);
+        std::memcpy(&pk->beta[(size_t)k * R * 4], p->beta, sizeof(double) * R * 4);
+        for (int32_t r = 0; r < R; ++r) pk->repid[(size_t)k * R + r] = p->replicate_id ? p->replicate_id[r] : (uint32_t)r;
+    }
+    // merged event list: day by day, instance by instance, list order
+    const int64_t E = pk->n_events;
+    std::vector<int32_t> mday(E), mkind(E), mnode(E), mdest(E), minst(E), mlocal(E);
+    {
+        std::vector<int64_t> cur(n, 0);
+        int64_t m = 0;
+        for (int32_t d = 0; d < pk->D; ++d)
+            for (int32_t k = 0; k < n; ++k) {
+                const sim_problem *p = ps[k];
+                while (cur[k] < p->n_events && p->ev_day[cur[k]] == d) {
+                    const int64_t e = cur[k]++;
+                    mday[m] = d;
+                    mkind[m] = p->ev_kind[e];
+                    mnode[m] = pk->lane_of[pk->inst_off[k] + p->ev_node[e]];
+                    mdest[m] = p->ev_kind[e] == SIM_EXTERNAL ? pk->lane_of[pk->inst_off[k] + p->ev_dest[e]] : -1;
+                    minst[m] = k;
+                    mlocal[m] = (int32_t)e;
+                    ++m;
+                }
+            }
+    }
+    std::vector<int32_t> level(E), day_levels;
+    if (events_mode == SIM_EVENTS_SERIAL) {
+        day_levels.assign(pk->D, 0);
+        for (int64_t e = 0; e < E; ++e) level[e] = ++day_levels[mday[e]];
+    } else {
+        plan_levels(E, mday.data(), mkind.data(), mnode.data(), mdest.data(), (int32_t)std::max<int64_t>(pk->Np, 1),
+                    level.data(), &day_levels, pk->D);
+    }
+    pk->lvl_ptr.assign(pk->D + 1, 0);
+    for (int32_t d = 0; d < pk->D; ++d) pk->lvl_ptr[d + 1] = pk->lvl_ptr[d] + day_levels[d];
+    pk->n_levels = pk->lvl_ptr[pk->D];
+    pk->lvl_off.assign(pk->n_levels + 1, 0);
+    for (int64_t e = 0; e < E; ++e) pk->lvl_off[pk->lvl_ptr[mday[e]] + level[e]]++;
+    for (int64_t i = 0; i < pk->n_levels; ++i) pk->lvl_off[i + 1] += pk->lvl_off[i];
+    std::vector<int64_t> fill(pk->lvl_off.begin(), pk->lvl_off.end() - 1);
+    pk->eg.resize(E);
+    pk->egm.resize(E);
+    pk->enode.resize(E);
+    pk->edest.resize(E);
+    pk->en.resize(E);
+    pk->emeta.resize(E);
+    pk->ev_inst = minst;
+    pk->ev_local = mlocal;
+    for (int64_t e = 0; e < E; ++e) {
+        const sim_problem *p = ps[minst[e]];
+        const int64_t le = mlocal[e];
+        const int64_t pos = fill[pk->lvl_ptr[mday[e]] + level[e] - 1]++;
+        pk->eg[pos] = (int32_t)le;
+        pk->egm[pos] = (int32_t)e;
+        pk->enode[pos] = mnode[e];
+        pk->edest[pos] = mdest[e];
+        pk->en[pos] = p->ev_n[le];
+        pk->emeta[pos] = meta_pack(p->ev_kind[le], column_mask(p, p->ev_select[le]), p->ev_shift[le]);
+    }
+    pk->rec_slot.assign(std::max(pk->D, 1), -1);
+    for (int k = 0; k < p0->n_record; ++k) pk->rec_slot[p0->record_days[k]] = k;
+    return SIM_OK;
+}
+
+Layout layout_of(const Packed &pk, const sim_problem *p0) {
+    return layout_for(pk.Np, pk.n_nodes, pk.n_inst, pk.Nc, pk.Nt, pk.R, pk.D, pk.n_events, p0->n_shift, pk.n_levels,
+                      pk.n_record);
+}
+
 }  // namespace
 
 struct sim_handle {
-    int32_t Nn = 0, Nc = 0, Nt = 0, R = 0, D = 0, n_record = 0;
-    int64_t L = 0;
+    int32_t Nc = 0, Nt = 0, R = 0, D = 0, n_record = 0, n_inst = 0, layout = 0;
+    int64_t Np = 0, L = 0, n_nodes = 0;
     Model model{};
     DevState st{};
     DevEvents ev{};
-    std::vector<int32_t> perm, inv;  // position -> node, node -> position
+    std::vector<int32_t> lane_of;   // position of each concatenated node
+    std::vector<int32_t> node_id;   // node number within its instance per position (-1: padding)
+    std::vector<int32_t> ev_inst, ev_local, ev_day;  // merged event index -> instance, local index, day
     std::vector<int64_t> lvl_off;   // host copy of the level boundaries
     std::vector<int32_t> lvl_ptr;   // [D+1]
     Layout lay{};
@@ -268,7 +454,6 @@ struct sim_handle {
     bool own_ws = false;
     hipStream_t stream = nullptr;
     int32_t launch = SIM_LAUNCH_KERNELS;
-    int32_t block = 256;
     int32_t day = 0;
     std::string err;
     // kernel timing (sim_kernel_times)
@@ -289,8 +474,6 @@ template <typename T>
 T *at(void *base, size_t off) {
     return reinterpret_cast<T *>(static_cast<char *>(base) + off);
 }
-
-int64_t count_shift_ids(const sim_problem *p) { return p->n_shift; }
 
 hipEvent_t take_event(sim_handle *h) {
     if (!h->ev_pool.empty()) {
@@ -331,100 +514,49 @@ int collect_marks(sim_handle *h) {
     return SIM_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-int sim_plan_levels(int64_t n_events, const int32_t *ev_day, const int32_t *ev_kind,
-                    const int32_t *ev_node, const int32_t *ev_dest, int32_t n_nodes, int32_t *level_out) {
-    if (n_events < 0 || n_nodes < 0 || (n_events > 0 && (!ev_day || !ev_kind || !ev_node || !ev_dest || !level_out)))
-        return SIM_EINVAL;
-    int32_t max_day = -1;
-    for (int64_t e = 0; e < n_events; ++e) {
-        if (ev_node[e] < 0 || ev_node[e] >= n_nodes || ev_kind[e] < 0 || ev_kind[e] > 3 || ev_day[e] < 0 ||
-            (e > 0 && ev_day[e] < ev_day[e - 1]) ||
-            (ev_kind[e] == SIM_EXTERNAL && (ev_dest[e] < 0 || ev_dest[e] >= n_nodes)))
-            return SIM_EINVAL;
-        max_day = std::max(max_day, ev_day[e]);
-    }
-    plan_levels(n_events, ev_day, ev_kind, ev_node, ev_dest, n_nodes, level_out, nullptr, max_day + 1);
-    return SIM_OK;
-}
-
-size_t sim_workspace_bytes(const sim_problem *p, const sim_device_opts *o) {
-    std::string err;
-    if (validate(p, &err) != SIM_OK) return 0;
-    const int32_t mode = o ? o->events_mode : SIM_EVENTS_LEVELS;
-    int64_t n_levels = 0;
-    if (mode == SIM_EVENTS_SERIAL) {
-        n_levels = p->n_events;
-    } else if (mode == SIM_EVENTS_LEVELS) {
-        std::vector<int32_t> level(p->n_events);
-        std::vector<int32_t> day_levels;
-        plan_levels(p->n_events, p->ev_day, p->ev_kind, p->ev_node, p->ev_dest, p->n_nodes, level.data(),
-                    &day_levels, p->n_days);
-        for (int32_t v : day_levels) n_levels += v;
-    } else {
-        return 0;
-    }
-    return layout_for(p->n_nodes, p->n_comp, p->n_trans, p->n_rep, p->n_days, p->n_events,
-                      count_shift_ids(p), n_levels, p->n_record).total;
-}
-
-int sim_create(const sim_problem *p, const sim_device_opts *o, sim_handle **out) {
+int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, sim_handle **out) {
     g_create_error.clear();
     if (!out) return g_create_error = "out is NULL", SIM_EINVAL;
     *out = nullptr;
-    int rc = validate(p, &g_create_error);
-    if (rc != SIM_OK) return rc;
     sim_device_opts opts{};
     if (o) opts = *o;
-    if (opts.events_mode != SIM_EVENTS_LEVELS && opts.events_mode != SIM_EVENTS_SERIAL)
-        return g_create_error = "unknown events_mode", SIM_EINVAL;
     if (opts.launch != SIM_LAUNCH_KERNELS && opts.launch != SIM_LAUNCH_PERSISTENT)
         return g_create_error = "unknown launch mode", SIM_EINVAL;
+    Packed pk;
+    int rc = build_packed(ps, n, opts.events_mode, &pk, &g_create_error);
+    if (rc != SIM_OK) return rc;
+    const sim_problem *p = ps[0];
 
     sim_handle *h = new (std::nothrow) sim_handle();
     if (!h) return g_create_error = "out of host memory", SIM_ENOMEM;
-    h->Nn = p->n_nodes;
-    h->Nc = p->n_comp;
-    h->Nt = p->n_trans;
-    h->R = p->n_rep;
-    h->D = p->n_days;
-    h->n_record = p->n_record;
-    h->L = (int64_t)p->n_nodes * p->n_rep;
+    h->Nc = pk.Nc;
+    h->Nt = pk.Nt;
+    h->R = pk.R;
+    h->D = pk.D;
+    h->n_record = pk.n_record;
+    h->n_inst = pk.n_inst;
+    h->layout = pk.layout;
+    h->Np = pk.Np;
+    h->L = pk.Np * pk.R;
+    h->n_nodes = pk.n_nodes;
     h->stream = (hipStream_t)opts.stream;
     h->launch = opts.launch;
-    h->block = opts.block > 0 ? opts.block : 256;
-    const int64_t n = p->n_events;
-    order_nodes(p, &h->perm, &h->inv);
-
-    // --- dependency pass and execution order (stable by day, level, list order)
-    std::vector<int32_t> level(n);
-    std::vector<int32_t> day_levels;
-    if (opts.events_mode == SIM_EVENTS_SERIAL) {
-        day_levels.assign(h->D, 0);
-        for (int64_t e = 0; e < n; ++e) level[e] = ++day_levels[p->ev_day[e]];
-    } else {
-        plan_levels(n, p->ev_day, p->ev_kind, p->ev_node, p->ev_dest, p->n_nodes, level.data(), &day_levels,
-                    h->D);
-    }
-    h->lvl_ptr.assign(h->D + 1, 0);
-    for (int32_t d = 0; d < h->D; ++d) h->lvl_ptr[d + 1] = h->lvl_ptr[d] + day_levels[d];
-    const int64_t n_levels = h->lvl_ptr[h->D];
-    h->lvl_off.assign(n_levels + 1, 0);
-    for (int64_t e = 0; e < n; ++e) h->lvl_off[h->lvl_ptr[p->ev_day[e]] + level[e]]++;  // count into slot+1
-    for (int64_t i = 0; i < n_levels; ++i) h->lvl_off[i + 1] += h->lvl_off[i];
-    std::vector<int64_t> fill(h->lvl_off.begin(), h->lvl_off.end() - 1);
-    std::vector<int32_t> eg(n), enode(n), edest(n), en(n);
-    std::vector<uint32_t> emeta(n);
-    for (int64_t e = 0; e < n; ++e) {
-        const int64_t pos = fill[h->lvl_ptr[p->ev_day[e]] + level[e] - 1]++;
-        eg[pos] = (int32_t)e;
-        enode[pos] = h->inv[p->ev_node[e]];
-        edest[pos] = p->ev_kind[e] == SIM_EXTERNAL ? h->inv[p->ev_dest[e]] : -1;
-        en[pos] = p->ev_n[e];
-        emeta[pos] = meta_pack(p->ev_kind[e], column_mask(p, p->ev_select[e]), p->ev_shift[e]);
+    h->lane_of = pk.lane_of;
+    h->node_id = pk.node_id;
+    h->lvl_off = pk.lvl_off;
+    h->lvl_ptr = pk.lvl_ptr;
+    h->ev_inst = pk.ev_inst;
+    h->ev_local = pk.ev_local;
+    h->ev_day.resize(pk.n_events);
+    {
+        int64_t m = 0;
+        std::vector<int64_t> cur(n, 0);
+        for (int32_t d = 0; d < pk.D; ++d)
+            for (int32_t k = 0; k < n; ++k)
+                while (cur[k] < ps[k]->n_events && ps[k]->ev_day[cur[k]] == d) {
+                    h->ev_day[m++] = d;
+                    ++cur[k];
+                }
     }
 
     // --- model constants
@@ -452,7 +584,7 @@ int sim_create(const sim_problem *p, const sim_device_opts *o, sim_handle **out)
     }
 
     // --- device memory
-    h->lay = layout_for(h->Nn, h->Nc, h->Nt, h->R, h->D, n, count_shift_ids(p), n_levels, h->n_record);
+    h->lay = layout_of(pk, p);
     std::string &err = g_create_error;
     if (opts.workspace) {
         if (opts.workspace_bytes < h->lay.total) {
@@ -474,11 +606,16 @@ int sim_create(const sim_problem *p, const sim_device_opts *o, sim_handle **out)
     DevState &s = h->st;
     s.u = at<int32_t>(h->ws, l.u);
     s.phi = at<double>(h->ws, l.phi);
-    s.node_id = at<int32_t>(h->ws, l.node_id);
     s.L = h->L;
-    s.Nn = h->Nn;
+    s.Np = (int32_t)h->Np;
     s.R = h->R;
     s.n_days = h->D;
+    s.n_inst = h->n_inst;
+    s.n_nodes = (int32_t)h->n_nodes;
+    s.node_id = at<int32_t>(h->ws, l.node_id);
+    s.inst = at<int32_t>(h->ws, l.inst);
+    s.inst_off = at<int32_t>(h->ws, l.inst_off);
+    s.seed = at<uint32_t>(h->ws, l.seed);
     s.coef = at<double>(h->ws, l.coef);
     s.alpha = at<double>(h->ws, l.alpha);
     s.beta = at<double>(h->ws, l.beta);
@@ -493,6 +630,7 @@ int sim_create(const sim_problem *p, const sim_device_opts *o, sim_handle **out)
     s.rec_slot = at<int32_t>(h->ws, l.rec_slot);
     DevEvents &ev = h->ev;
     ev.g = at<int32_t>(h->ws, l.ev_g);
+    ev.gm = at<int32_t>(h->ws, l.ev_gm);
     ev.node = at<int32_t>(h->ws, l.ev_node);
     ev.dest = at<int32_t>(h->ws, l.ev_dest);
     ev.n = at<int32_t>(h->ws, l.ev_n);
@@ -500,15 +638,11 @@ int sim_create(const sim_problem *p, const sim_device_opts *o, sim_handle **out)
     ev.lvl_off = at<int64_t>(h->ws, l.lvl_off);
     ev.lvl_ptr = at<int32_t>(h->ws, l.lvl_ptr);
 
-    // --- host staging of everything that is uploaded
-    std::vector<uint32_t> repid(h->R);
-    for (int r = 0; r < h->R; ++r) repid[r] = p->replicate_id ? p->replicate_id[r] : (uint32_t)r;
     std::vector<int32_t> shift(MAXC * std::max<int64_t>(p->n_shift, 1), 0);
     for (int hh = 0; hh < p->n_shift; ++hh)
         for (int c = 0; c < h->Nc; ++c) shift[hh * MAXC + c] = p->N[(size_t)c * p->n_shift + hh];
-    std::vector<int32_t> rec_slot(std::max(h->D, 1), -1);
-    for (int k = 0; k < p->n_record; ++k) rec_slot[p->record_days[k]] = k;
     const unsigned long long ok = STATUS_OK;
+    const int64_t S = (int64_t)h->n_inst * h->R, E = pk.n_events;
 
     struct Up {
         void *dst;
@@ -516,21 +650,25 @@ int sim_create(const sim_problem *p, const sim_device_opts *o, sim_handle **out)
         size_t bytes;
     };
     const Up ups[] = {
-        {(void *)s.coef, p->coef, sizeof(double) * h->R * h->Nt},
-        {(void *)s.alpha, p->alpha, sizeof(double) * h->R},
-        {(void *)s.beta, p->beta, sizeof(double) * h->R * 4},
-        {(void *)s.repid, repid.data(), sizeof(uint32_t) * h->R},
+        {(void *)s.node_id, pk.node_id.data(), sizeof(int32_t) * h->Np},
+        {(void *)s.inst, pk.inst.data(), sizeof(int32_t) * h->Np},
+        {(void *)s.inst_off, pk.inst_off.data(), sizeof(int32_t) * h->n_inst},
+        {(void *)s.seed, pk.seed.data(), sizeof(uint32_t) * h->n_inst},
+        {(void *)s.coef, pk.coef.data(), sizeof(double) * S * h->Nt},
+        {(void *)s.alpha, pk.alpha.data(), sizeof(double) * S},
+        {(void *)s.beta, pk.beta.data(), sizeof(double) * S * 4},
+        {(void *)s.repid, pk.repid.data(), sizeof(uint32_t) * S},
         {(void *)s.shift, shift.data(), sizeof(int32_t) * shift.size()},
         {(void *)s.status, &ok, sizeof ok},
-        {(void *)ev.g, eg.data(), sizeof(int32_t) * n},
-        {(void *)ev.node, enode.data(), sizeof(int32_t) * n},
-        {(void *)ev.dest, edest.data(), sizeof(int32_t) * n},
-        {(void *)ev.n, en.data(), sizeof(int32_t) * n},
-        {(void *)ev.meta, emeta.data(), sizeof(uint32_t) * n},
-        {(void *)ev.lvl_off, h->lvl_off.data(), sizeof(int64_t) * (n_levels + 1)},
-        {(void *)ev.lvl_ptr, h->lvl_ptr.data(), sizeof(int32_t) * (h->D + 1)},
-        {(void *)s.rec_slot, rec_slot.data(), sizeof(int32_t) * h->D},
-        {(void *)s.node_id, h->perm.data(), sizeof(int32_t) * h->Nn},
+        {(void *)ev.g, pk.eg.data(), sizeof(int32_t) * E},
+        {(void *)ev.gm, pk.egm.data(), sizeof(int32_t) * E},
+        {(void *)ev.node, pk.enode.data(), sizeof(int32_t) * E},
+        {(void *)ev.dest, pk.edest.data(), sizeof(int32_t) * E},
+        {(void *)ev.n, pk.en.data(), sizeof(int32_t) * E},
+        {(void *)ev.meta, pk.emeta.data(), sizeof(uint32_t) * E},
+        {(void *)ev.lvl_off, pk.lvl_off.data(), sizeof(int64_t) * (pk.n_levels + 1)},
+        {(void *)ev.lvl_ptr, pk.lvl_ptr.data(), sizeof(int32_t) * (h->D + 1)},
+        {(void *)s.rec_slot, pk.rec_slot.data(), sizeof(int32_t) * h->D},
     };
     for (const Up &up : ups) {
         if (up.bytes == 0) continue;
@@ -545,15 +683,16 @@ int sim_create(const sim_problem *p, const sim_device_opts *o, sim_handle **out)
         sim_destroy(h);
         return rc;
     }
-    // initial state: every replicate starts from (u0, v0)
-    std::vector<int32_t> u((size_t)h->Nc * h->L);
-    std::vector<double> v(h->L);
-    for (int64_t i = 0; i < h->Nn; ++i)
-        for (int r = 0; r < h->R; ++r) {
-            const int64_t lane = (int64_t)h->inv[i] * h->R + r;
-            for (int c = 0; c < h->Nc; ++c) u[(size_t)c * h->L + lane] = p->u0[i * h->Nc + c];
-            v[lane] = p->v0[i];
-        }
+    // initial state: every replicate of an instance starts from its (u0, v0); padding holds zeros
+    std::vector<int32_t> u((size_t)h->Nc * h->L, 0);
+    std::vector<double> v(h->L, 0.0);
+    for (int32_t k = 0; k < n; ++k)
+        for (int64_t i = 0; i < ps[k]->n_nodes; ++i)
+            for (int r = 0; r < h->R; ++r) {
+                const int64_t lane = (int64_t)h->lane_of[pk.inst_off[k] + i] * h->R + r;
+                for (int c = 0; c < h->Nc; ++c) u[(size_t)c * h->L + lane] = ps[k]->u0[i * h->Nc + c];
+                v[lane] = ps[k]->v0[i];
+            }
     if (h->L > 0) {
         rc = check_device(hipMemcpy(s.u, u.data(), sizeof(int32_t) * u.size(), hipMemcpyHostToDevice), &err, "upload u0");
         if (!rc) rc = check_device(hipMemcpy(s.phi, v.data(), sizeof(double) * v.size(), hipMemcpyHostToDevice), &err, "upload v0");
@@ -566,6 +705,44 @@ int sim_create(const sim_problem *p, const sim_device_opts *o, sim_handle **out)
     return SIM_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int sim_plan_levels(int64_t n_events, const int32_t *ev_day, const int32_t *ev_kind,
+                    const int32_t *ev_node, const int32_t *ev_dest, int32_t n_nodes, int32_t *level_out) {
+    if (n_events < 0 || n_nodes < 0 || (n_events > 0 && (!ev_day || !ev_kind || !ev_node || !ev_dest || !level_out)))
+        return SIM_EINVAL;
+    int32_t max_day = -1;
+    for (int64_t e = 0; e < n_events; ++e) {
+        if (ev_node[e] < 0 || ev_node[e] >= n_nodes || ev_kind[e] < 0 || ev_kind[e] > 3 || ev_day[e] < 0 ||
+            (e > 0 && ev_day[e] < ev_day[e - 1]) ||
+            (ev_kind[e] == SIM_EXTERNAL && (ev_dest[e] < 0 || ev_dest[e] >= n_nodes)))
+            return SIM_EINVAL;
+        max_day = std::max(max_day, ev_day[e]);
+    }
+    plan_levels(n_events, ev_day, ev_kind, ev_node, ev_dest, n_nodes, level_out, nullptr, max_day + 1);
+    return SIM_OK;
+}
+
+size_t sim_workspace_bytes_batch(const sim_problem *const *problems, int32_t n_problems, const sim_device_opts *o) {
+    std::string err;
+    Packed pk;
+    if (build_packed(problems, n_problems, o ? o->events_mode : SIM_EVENTS_LEVELS, &pk, &err) != SIM_OK) return 0;
+    return layout_of(pk, problems[0]).total;
+}
+
+size_t sim_workspace_bytes(const sim_problem *p, const sim_device_opts *o) {
+    return sim_workspace_bytes_batch(&p, 1, o);
+}
+
+int sim_create(const sim_problem *p, const sim_device_opts *o, sim_handle **out) { return create(&p, 1, o, out); }
+
+int sim_create_batch(const sim_problem *const *problems, int32_t n_problems, const sim_device_opts *o,
+                     sim_handle **out) {
+    return create(problems, n_problems, o, out);
+}
+
 int sim_run(sim_handle *h, int32_t n_days) {
     if (!h) return SIM_EINVAL;
     h->err.clear();
@@ -574,23 +751,21 @@ int sim_run(sim_handle *h, int32_t n_days) {
     if (h->day + n_days > h->D) return h->err = fmt("run of %d days from day %d passes the horizon %d", n_days, h->day, h->D), SIM_ESTATE;
     if (n_days == 0) return SIM_OK;
     const int32_t d0 = h->day, d1 = h->day + n_days;
-    const Layout &l = h->lay;
+    const int64_t S = (int64_t)h->n_inst * h->R;
     // records of the days about to be simulated start from zero
-    int rc = SIM_OK;
-    rc = check_device(hipMemsetAsync(h->st.prevalence + (size_t)d0 * h->R, 0, sizeof(int32_t) * n_days * h->R, h->stream), &h->err, "clear");
-    if (!rc) rc = check_device(hipMemsetAsync(h->st.transitions + (size_t)d0 * h->R, 0, sizeof(int64_t) * n_days * h->R, h->stream), &h->err, "clear");
-    if (!rc) rc = check_device(hipMemsetAsync(h->st.totals + (size_t)d0 * h->R * h->Nc, 0, sizeof(int64_t) * n_days * h->R * h->Nc, h->stream), &h->err, "clear");
-    (void)l;
+    int rc = check_device(hipMemsetAsync(h->st.prevalence + (size_t)d0 * S, 0, sizeof(int32_t) * n_days * S, h->stream), &h->err, "clear");
+    if (!rc) rc = check_device(hipMemsetAsync(h->st.transitions + (size_t)d0 * S, 0, sizeof(int64_t) * n_days * S, h->stream), &h->err, "clear");
+    if (!rc) rc = check_device(hipMemsetAsync(h->st.totals + (size_t)d0 * S * h->Nc, 0, sizeof(int64_t) * n_days * S * h->Nc, h->stream), &h->err, "clear");
     if (rc) return rc;
     if (h->launch == SIM_LAUNCH_PERSISTENT && h->L > 0) {
         char why[256] = {0};
         hipError_t e = timed(h, SIM_K_PERSIST, [&] {
-            return launch_persistent(h->model, h->st, h->ev, d0, d1, h->block, h->stream, why, sizeof why);
+            return launch_persistent(h->model, h->st, h->ev, d0, d1, h->layout, h->stream, why, sizeof why);
         });
         if (e != hipSuccess) return h->err = fmt("persistent launch: %s %s", hipGetErrorString(e), why), SIM_EDEVICE;
     } else {
         for (int32_t d = d0; d < d1; ++d) {
-            hipError_t e = timed(h, SIM_K_DAY, [&] { return launch_day(h->model, h->st, d, d > d0, 1, h->block, h->stream); });
+            hipError_t e = timed(h, SIM_K_DAY, [&] { return launch_day(h->model, h->st, d, d > d0, 1, h->layout, h->stream); });
             if (e != hipSuccess) return h->err = fmt("day kernel: %s", hipGetErrorString(e)), SIM_EDEVICE;
             // big levels get a launch of their own; runs of small ones share one workgroup
             int32_t lv = h->lvl_ptr[d];
@@ -612,7 +787,7 @@ int sim_run(sim_handle *h, int32_t n_days) {
                 if (e != hipSuccess) return h->err = fmt("event kernel: %s", hipGetErrorString(e)), SIM_EDEVICE;
             }
         }
-        hipError_t e = timed(h, SIM_K_CLOSE, [&] { return launch_day(h->model, h->st, d1, 1, 0, h->block, h->stream); });
+        hipError_t e = timed(h, SIM_K_CLOSE, [&] { return launch_day(h->model, h->st, d1, 1, 0, h->layout, h->stream); });
         if (e != hipSuccess) return h->err = fmt("closing kernel: %s", hipGetErrorString(e)), SIM_EDEVICE;
     }
     h->day = d1;
@@ -626,34 +801,39 @@ int sim_sync(sim_handle *h) {
     unsigned long long st = 0;
     rc = check_device(hipMemcpy(&st, h->st.status, sizeof st, hipMemcpyDeviceToHost), &h->err, "status");
     if (rc) return rc;
-    if (st != STATUS_OK && (st >> 32) == STATUS_LIMIT_TAG) {
-        return h->err = fmt("a node of replicate %llu exceeded %d SSA transitions in one day", st & 0xffffffffull,
-                            SIM_MAX_FIRED),
-               SIM_ELIMIT;
+    if (st == STATUS_OK) return SIM_OK;
+    const unsigned long long set = st & 0xffffffffull;
+    const long long inst = (long long)(set / h->R), rep = (long long)(set % h->R);
+    if ((st >> 32) == STATUS_LIMIT_TAG) {
+        h->err = fmt("a node exceeded %d SSA transitions in one day (replicate %lld", SIM_MAX_FIRED, rep);
+        if (h->n_inst > 1) h->err += fmt(" of instance %lld", inst);
+        h->err += ")";
+        return SIM_ELIMIT;
     }
-    if (st != STATUS_OK) {
-        return h->err = fmt("infeasible event %llu (replicate %llu): it asks for more individuals than the "
-                            "selected compartments hold", st >> 32, st & 0xffffffffull),
-               SIM_EINFEASIBLE;
-    }
-    return SIM_OK;
+    const int64_t gm = (int64_t)(st >> 32);
+    const int64_t local = gm < (int64_t)h->ev_local.size() ? h->ev_local[gm] : gm;
+    const int32_t day = gm < (int64_t)h->ev_day.size() ? h->ev_day[gm] : -1;
+    h->err = fmt("infeasible event %lld (replicate %lld)", (long long)local, rep);
+    if (h->n_inst > 1) h->err += fmt(" of instance %lld", inst);
+    h->err += fmt(" on day %d: it asks for more individuals than the selected compartments hold", day);
+    return SIM_EINFEASIBLE;
 }
 
 int sim_trajectory(sim_handle *h, sim_output *out) {
     if (!h || !out) return SIM_EINVAL;
     int rc = sim_sync(h);
     if (rc) return rc;
-    const size_t DR = (size_t)h->D * h->R;
+    const size_t DS = (size_t)h->D * h->n_inst * h->R;
     struct Down {
         void *dst;
         const void *src;
         size_t bytes;
     } downs[] = {
-        {out->prevalence, h->st.prevalence, sizeof(int32_t) * DR},
-        {out->transitions, h->st.transitions, sizeof(int64_t) * DR},
-        {out->totals, h->st.totals, sizeof(int64_t) * DR * h->Nc},
-        {out->snap_u, h->st.snap_u, sizeof(int32_t) * h->n_record * (size_t)h->R * h->Nn * h->Nc},
-        {out->snap_v, h->st.snap_v, sizeof(double) * h->n_record * (size_t)h->R * h->Nn},
+        {out->prevalence, h->st.prevalence, sizeof(int32_t) * DS},
+        {out->transitions, h->st.transitions, sizeof(int64_t) * DS},
+        {out->totals, h->st.totals, sizeof(int64_t) * DS * h->Nc},
+        {out->snap_u, h->st.snap_u, sizeof(int32_t) * h->n_record * (size_t)h->R * h->n_nodes * h->Nc},
+        {out->snap_v, h->st.snap_v, sizeof(double) * h->n_record * (size_t)h->R * h->n_nodes},
     };
     for (const Down &d : downs) {
         if (!d.dst || d.bytes == 0) continue;
@@ -675,11 +855,11 @@ int sim_get_state(sim_handle *h, int32_t *u, double *v, int32_t *day) {
     if (!rc) rc = check_device(hipMemcpy(dv.data(), h->st.phi, sizeof(double) * dv.size(), hipMemcpyDeviceToHost), &h->err, "download v");
     if (rc) return rc;
     for (int r = 0; r < h->R; ++r)
-        for (int64_t i = 0; i < h->Nn; ++i) {
-            const int64_t lane = (int64_t)h->inv[i] * h->R + r;
+        for (int64_t i = 0; i < h->n_nodes; ++i) {
+            const int64_t lane = (int64_t)h->lane_of[i] * h->R + r;
             if (u)
-                for (int c = 0; c < h->Nc; ++c) u[((size_t)r * h->Nn + i) * h->Nc + c] = du[(size_t)c * h->L + lane];
-            if (v) v[(size_t)r * h->Nn + i] = dv[lane];
+                for (int c = 0; c < h->Nc; ++c) u[((size_t)r * h->n_nodes + i) * h->Nc + c] = du[(size_t)c * h->L + lane];
+            if (v) v[(size_t)r * h->n_nodes + i] = dv[lane];
         }
     return SIM_OK;
 }
@@ -690,17 +870,17 @@ int sim_set_state(sim_handle *h, const int32_t *u, const double *v, int32_t day)
     if (day < 0 || day > h->D) return h->err = "day out of range", SIM_ESTATE;
     int rc = check_device(hipStreamSynchronize(h->stream), &h->err, "synchronize");
     if (rc) return rc;
-    std::vector<int32_t> du((size_t)h->Nc * h->L);
-    std::vector<double> dv(h->L);
+    std::vector<int32_t> du((size_t)h->Nc * h->L, 0);
+    std::vector<double> dv(h->L, 0.0);
     for (int r = 0; r < h->R; ++r)
-        for (int64_t i = 0; i < h->Nn; ++i) {
-            const int64_t lane = (int64_t)h->inv[i] * h->R + r;
+        for (int64_t i = 0; i < h->n_nodes; ++i) {
+            const int64_t lane = (int64_t)h->lane_of[i] * h->R + r;
             for (int c = 0; c < h->Nc; ++c) {
-                const int32_t x = u[((size_t)r * h->Nn + i) * h->Nc + c];
+                const int32_t x = u[((size_t)r * h->n_nodes + i) * h->Nc + c];
                 if (x < 0) return h->err = "negative count in state", SIM_EINVAL;
                 du[(size_t)c * h->L + lane] = x;
             }
-            const double y = v[(size_t)r * h->Nn + i];
+            const double y = v[(size_t)r * h->n_nodes + i];
             if (!(y >= 0.0) || !std::isfinite(y)) return h->err = "phi must be finite and >= 0", SIM_EINVAL;
             dv[lane] = y;
         }

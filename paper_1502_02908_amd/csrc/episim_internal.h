@@ -41,30 +41,39 @@ struct Model {
     int32_t S[MAXC][MAXT];      // S[c][k]
 };
 
+// A handle holds n_inst instances (networks) of one model, each run with the
+// same number R of replicates; "set" = inst * R + r indexes everything that
+// belongs to one trajectory (parameters, replicate id, records).
 struct DevState {
     int32_t *u;                 // [nc][L]
     double *phi;                // [L]
-    int64_t L;                  // Nn * R
-    int32_t Nn, R;
+    int64_t L;                  // Np * R, Np = positions (nodes of all instances plus padding)
+    int32_t Np, R;
     int32_t n_days;
-    const int32_t *node_id;     // [Nn] node (as numbered by the caller) at each position
-    const double *coef;         // [R][nt]
-    const double *alpha;        // [R]
-    const double *beta;         // [R][4]
-    const uint32_t *repid;      // [R]
+    int32_t n_inst;
+    int32_t n_nodes;            // nodes of all instances (no padding), for the snapshot layout
+    const int32_t *node_id;     // [Np] node number within its instance, -1 for padding
+    const int32_t *inst;        // [Np] instance of each position
+    const int32_t *inst_off;    // [n_inst] first node of each instance in the concatenated numbering
+    const uint32_t *seed;       // [n_inst] first Philox key word of each instance
+    const double *coef;         // [sets][nt]
+    const double *alpha;        // [sets]
+    const double *beta;         // [sets][4]
+    const uint32_t *repid;      // [sets] second Philox key word
     const int32_t *shift;       // [n_shift_ids][MAXC] compartment offsets
     unsigned long long *status; // first infeasible event, or STATUS_OK
     // daily records
-    int32_t *prevalence;        // [D][R]
-    int64_t *transitions;       // [D][R]
-    int64_t *totals;            // [D][R][nc]
-    int32_t *snap_u;            // [n_record][R][Nn][nc]
-    double *snap_v;             // [n_record][R][Nn]
+    int32_t *prevalence;        // [D][sets]
+    int64_t *transitions;       // [D][sets]
+    int64_t *totals;            // [D][sets][nc]
+    int32_t *snap_u;            // [n_record][R][n_nodes][nc]
+    double *snap_v;             // [n_record][R][n_nodes]
     const int32_t *rec_slot;    // [D] snapshot slot of day d, or -1
 };
 
 struct DevEvents {
-    const int32_t *g;
+    const int32_t *g;           // index of the event within its instance's list (random stream)
+    const int32_t *gm;          // index in the merged list of all instances (error report)
     const int32_t *node;
     const int32_t *dest;
     const int32_t *n;
@@ -73,8 +82,14 @@ struct DevEvents {
     const int32_t *lvl_ptr;     // [D+1]: levels of day d are lvl_ptr[d] .. lvl_ptr[d+1]-1
 };
 
+// Layouts of the day phase: one lane per (node, replicate) with workgroup
+// sums (R == 1), a tile of kTileNodes nodes x 64 replicates per workgroup
+// (R a multiple of 64), or one lane per (node, replicate) with per-lane sums.
+constexpr int kTileNodes = 128;
+enum { LAYOUT_LANES = 0, LAYOUT_TILE = 1, LAYOUT_LANES_ATOMIC = 2 };
+
 // Host-side launchers (episim_device.hip). Each returns a hipError_t as int.
-int launch_day(const Model &m, const DevState &s, int32_t d, int prologue, int ssa, int block,
+int launch_day(const Model &m, const DevState &s, int32_t d, int prologue, int ssa, int layout,
                void *stream);
 int launch_events(const Model &m, const DevState &s, const DevEvents &ev, int32_t d, int64_t begin,
                   int64_t end, void *stream);
@@ -84,6 +99,6 @@ int launch_event_levels(const Model &m, const DevState &s, const DevEvents &ev, 
 // single-workgroup launch
 constexpr int64_t kSmallLevel = 512;
 int launch_persistent(const Model &m, const DevState &s, const DevEvents &ev, int32_t d_begin,
-                      int32_t d_end, int block, void *stream, char *why, int why_len);
+                      int32_t d_end, int layout, void *stream, char *why, int why_len);
 
 }  // namespace episim

@@ -69,6 +69,10 @@ SIGNATURES = {
     "sim_last_error": (C.c_char_p, [C.c_void_p]),
     "sim_plan_levels": (C.c_int, [C.c_int64, _i32p, _i32p, _i32p, _i32p, C.c_int32, _i32p]),
     "sim_kernel_times": (C.c_int, [C.c_void_p, C.c_int32, _f64p, _i64p]),
+    "sim_create_batch": (C.c_int, [C.POINTER(C.POINTER(sim_problem)), C.c_int32, C.POINTER(sim_device_opts),
+                                   C.POINTER(C.c_void_p)]),
+    "sim_workspace_bytes_batch": (C.c_size_t, [C.POINTER(C.POINTER(sim_problem)), C.c_int32,
+                                               C.POINTER(sim_device_opts)]),
 }
 KERNEL_CLASSES = ("day", "events", "close", "persist")
 
@@ -154,17 +158,23 @@ def _torch_cuda():
 
 
 class Simulator:
-    """One handle: a network, R replicates, state on the device."""
+    """One handle: one network (or several packed instances of one model),
+    R replicates each, state on the device."""
 
     def __init__(self, p, *, events_mode=EVENTS_LEVELS, launch=LAUNCH_KERNELS, stream=None,
                  torch_workspace=True, device=0):
-        self.p = p
-        self.R, self.Nn, self.Nc, self.D = p.n_rep, p.n_nodes, p.n_comp, p.n_days
-        self.n_record = 0 if p.record_days is None else len(p.record_days)
+        probs = list(p) if isinstance(p, (list, tuple)) else [p]
+        self.p = probs[0]
+        self.n_inst = len(probs)
+        self.R, self.Nc, self.D = probs[0].n_rep, probs[0].n_comp, probs[0].n_days
+        self.Nn = sum(q.n_nodes for q in probs)
+        self.node_counts = [q.n_nodes for q in probs]
+        self.n_record = 0 if probs[0].record_days is None else len(probs[0].record_days)
         self._h = C.c_void_p()
         self._ws = None
         torch = _torch_cuda()
-        s, keep = _marshal(p)
+        structs, keep = zip(*[_marshal(q) for q in probs])
+        arr = (C.POINTER(sim_problem) * len(structs))(*[C.pointer(st) for st in structs])
         opts = sim_device_opts()
         opts.events_mode = events_mode
         opts.launch = launch
@@ -173,14 +183,14 @@ class Simulator:
             if stream is None:
                 stream = torch.cuda.current_stream().cuda_stream
             if torch_workspace:
-                nbytes = int(lib().sim_workspace_bytes(C.byref(s), C.byref(opts)))
+                nbytes = int(lib().sim_workspace_bytes_batch(arr, len(structs), C.byref(opts)))
                 if nbytes == 0:
                     raise SimError(SIM_EINVAL, "problem rejected (sim_workspace_bytes returned 0)")
                 self._ws = torch.empty(nbytes, dtype=torch.uint8, device=f"cuda:{device}")
                 opts.workspace = self._ws.data_ptr()
                 opts.workspace_bytes = nbytes
         opts.stream = stream if stream is not None else None
-        rc = lib().sim_create(C.byref(s), C.byref(opts), C.byref(self._h))
+        rc = lib().sim_create_batch(arr, len(structs), C.byref(opts), C.byref(self._h))
         del keep
         if rc != SIM_OK:
             raise SimError(rc, lib().sim_last_error(None).decode())
@@ -197,9 +207,11 @@ class Simulator:
         self._check(lib().sim_sync(self._h))
 
     def trajectory(self):
+        """Daily records [D][set] (set = instance * R + replicate) and snapshots."""
         D, R, Nc, Nn, K = self.D, self.R, self.Nc, self.Nn, self.n_record
-        out = dict(prevalence=np.zeros((D, R), np.int32), transitions=np.zeros((D, R), np.int64),
-                   totals=np.zeros((D, R, Nc), np.int64), snap_u=np.zeros((K, R, Nn, Nc), np.int32),
+        S = self.n_inst * R
+        out = dict(prevalence=np.zeros((D, S), np.int32), transitions=np.zeros((D, S), np.int64),
+                   totals=np.zeros((D, S, Nc), np.int64), snap_u=np.zeros((K, R, Nn, Nc), np.int32),
                    snap_v=np.zeros((K, R, Nn), np.float64))
         o = sim_output(_p(out["prevalence"], _i32p), _p(out["transitions"], _i64p), _p(out["totals"], _i64p),
                        _p(out["snap_u"], _i32p), _p(out["snap_v"], _f64p))

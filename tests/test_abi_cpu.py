@@ -178,3 +178,19 @@ def test_workspace_covers_every_events_mode():
     lv = S.workspace_bytes(p, S.EVENTS_LEVELS)
     se = S.workspace_bytes(p, S.EVENTS_SERIAL)
     assert 0 < lv < se
+
+
+def test_batch_rejects_mixed_models():
+    a = synth.config1().truncated(10)
+    b = synth.sise3_network(n_nodes=50, n_days=10, seed=1)
+    structs = [S._marshal(a), S._marshal(b)]
+    arr = (C.POINTER(S.sim_problem) * 2)(*[C.pointer(s) for s, _ in structs])
+    h = C.c_void_p()
+    rc = P.lib().sim_create_batch(arr, 2, None, C.byref(h))
+    assert rc == S.SIM_EINVAL
+    assert "share" in P.lib().sim_last_error(None).decode()
+    c = synth.config1().truncated(10)
+    c.n_days = 12
+    structs = [S._marshal(a), S._marshal(c)]
+    arr = (C.POINTER(S.sim_problem) * 2)(*[C.pointer(s) for s, _ in structs])
+    assert P.lib().sim_workspace_bytes_batch(arr, 2, None) == 0
