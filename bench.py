@@ -67,6 +67,62 @@ def counter_traffic(kernel):
     return int(v) if v else None
 
 
+def batched_leg(P, synth, torch, steps, plain_sample):
+    """Trajectories per second, batched against the plain per-trajectory loop:
+    256 replicates of the 37k-node network over its first 730 days, each with
+    its own (upsilon_1..3, gamma_1..3, beta_1..4) drawn from the prior box, in
+    one handle (replicate tiles), against the same trajectories run one handle
+    and one launch sequence each (timed on plain_sample of them)."""
+    import numpy as np
+    base = synth.config2(n_days=730)
+    R = 256
+    coef, alpha, beta = synth.prior_draws(R, seed=4)
+    rid = np.arange(R, dtype=np.uint32)
+    pb = base.with_replicates(R, coef=coef, alpha=alpha, beta=beta, replicate_id=rid)
+    sim = P.Simulator(pb)
+    u0 = np.tile(pb.u0[None], (R, 1, 1))
+    v0 = np.tile(pb.v0[None], (R, 1))
+    times = []
+    for k in range(steps + 1):
+        sim.set_state(u0, v0, 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.run(0)
+        sim.sync()
+        torch.cuda.synchronize()
+        if k > 0:
+            times.append(time.perf_counter() - t0)
+        print(f"[bench] batched {R} replicates: {(time.perf_counter() - t0) * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    trans = int(sim.trajectory()["transitions"].sum())
+    sim.close()
+    t_batch = sum(times) / len(times)
+    plain = []
+    pick = np.linspace(0, R - 1, plain_sample).astype(int)
+    for r in pick:
+        one = base.with_replicates(1, coef=coef[r:r + 1], alpha=alpha[r:r + 1], beta=beta[r:r + 1],
+                                   replicate_id=rid[r:r + 1])
+        with P.Simulator(one) as s1:
+            s1.run(0)           # warm-up of this handle
+            s1.sync()
+            s1.set_state(one.u0[None], one.v0[None], 0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s1.run(0)
+            s1.sync()
+            torch.cuda.synchronize()
+            plain.append(time.perf_counter() - t0)
+    t_plain = sum(plain) / len(plain)
+    return dict(
+        workload=f"{R} replicates with prior-box parameters of the 37,000-node network, 730 days",
+        replicates_per_s=round(R / t_batch, 3),
+        ms_per_batch=round(t_batch * 1e3, 2),
+        node_days_per_s=round(R * base.n_nodes * base.n_days / t_batch, 1),
+        transitions_per_s=round(trans / t_batch, 1),
+        plain_replicates_per_s=round(1.0 / t_plain, 3),
+        plain_sample=f"{plain_sample} of the {R} trajectories, one handle and one per-day launch sequence each",
+        speedup_vs_plain=round(t_plain / t_batch * R, 2))
+
+
 def cpu_baseline(p, seconds):
     from oracle import oracle as O
     threads = min(os.cpu_count() or 1, 16)
@@ -94,6 +150,8 @@ def main():
     ap.add_argument("--workload", default="sise3-37k", choices=sorted(WORKLOADS))
     ap.add_argument("--launch", default="kernels", choices=["kernels", "persistent"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-replicates leg")
+    ap.add_argument("--plain-sample", type=int, default=6)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (profiler calibration)")
@@ -191,6 +249,10 @@ def main():
                         for k, v in kt.items() if v[1]}
     sim.close()
 
+    batched = None
+    if not args.no_batched and args.workload == "sise3-37k":
+        batched = batched_leg(P, synth, torch, max(1, min(args.steps, 3)), args.plain_sample)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(p, args.cpu_seconds)
@@ -205,7 +267,7 @@ def main():
                     events=p.n_events, launch=args.launch, step="one full-horizon simulation"),
         transitions_per_s=round(trans_per_step * args.steps / total, 1),
         transitions_per_step=trans_per_step,
-        roofline=roofline, kernels=kernel_breakdown, cpu_baseline=cpu)
+        roofline=roofline, kernels=kernel_breakdown, batched=batched, cpu_baseline=cpu)
     print(json.dumps(line), flush=True)
 
 

@@ -286,7 +286,8 @@ def config1(seed=1, **kw):
 
 
 def config2(seed=2, n_nodes=37000, n_days=1461, **kw):
-    """SISe3, 37,000 nodes, 1461 days (about 5.8M events)."""
+    """SISe3, 37,000 nodes, 1461 days (about 5.3M events). A shorter horizon
+    gives the same network and the same events, cut at n_days."""
     return sise3_network(n_nodes=n_nodes, n_days=n_days, seed=seed, **kw)
 
 

@@ -128,6 +128,7 @@ struct Chain {
 template <int NC_, int NT_>
 struct GenericRules {
     static constexpr int NC = NC_, NT = NT_;
+    static constexpr int kPairs = 0;
     using State = Chain<NC, NT>;
     __device__ static __forceinline__ double rate(const Model &m, const State &c, int k) {
         double xr = 0.0;
@@ -168,6 +169,7 @@ struct GenericRules {
 template <int NP>
 struct PairRules {
     static constexpr int NC = 2 * NP, NT = 2 * NP;
+    static constexpr int kPairs = NP;
     using State = Chain<NC, NT>;
     __device__ static __forceinline__ double rate(const Model &, const State &c, int k) {
         return c.cphi[k] * c.xd[k];
@@ -214,6 +216,19 @@ struct PairRules {
     }
 };
 
+// The single-chain walk for paired classes, written so that the division of
+// attempt k (its waiting time) overlaps the choice and the update it does not
+// depend on: the chosen transition is applied first and undone if the
+// attempt lands past the window end (counts are exact integers in binary64,
+// and the running sums are recomputed with the same operations, so the undo
+// restores the same bits). Every lane holds the same state; draws for
+// attempts kbase.. come from lane i = attempt - kbase. Returns when the chain
+// ends.
+template <int NP>
+__device__ __forceinline__ void pairs_walk_uniform(const Model &m, Chain<2 * NP, 2 * NP> &c, uint32_t kbase,
+                                                   uint32_t node, uint32_t day, uint32_t key0, uint32_t key1,
+                                                   unsigned long long *status, int32_t r);
+
 // Inversion of eq:sampling2: the first transition with a positive rate whose
 // running sum reaches target. With target > 0 that is the number of running
 // sums below target (they never decrease, and a transition with rate 0 cannot
@@ -232,6 +247,17 @@ __device__ __forceinline__ int invert(const Model &m, const typename Rules::Stat
             if (trans_on<NT>(m, k) && Rules::rate(m, c, k) > 0.0) j = k;
     }
     return j;
+}
+
+template <int NP>
+__device__ __forceinline__ void pairs_rates_full(Chain<2 * NP, 2 * NP> &c) {
+    double lam = 0.0;
+#pragma unroll
+    for (int k = 0; k < 2 * NP; ++k) {
+        lam = lam + c.cphi[k] * c.xd[k];
+        c.cum[k] = lam;
+    }
+    c.lam = lam;
 }
 
 // One attempt of the direct method with the draw (E, U) = (-log rand_1,
@@ -260,6 +286,59 @@ __device__ __forceinline__ double lane_f64(double v, int lane) {
     const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
     const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+template <int NP>
+__device__ __forceinline__ void pairs_walk_uniform(const Model &m, Chain<2 * NP, 2 * NP> &c, uint32_t kbase,
+                                                   uint32_t node, uint32_t day, uint32_t key0, uint32_t key1,
+                                                   unsigned long long *status, int32_t r) {
+    constexpr int NT = 2 * NP;
+    const uint32_t lane = threadIdx.x & 63u;
+    for (;;) {
+        const Word4 o = philox4x32_10(Word4{kbase + lane, node, day, 0u}, key0, key1);
+        const double e_mine = minus_log(unit_open(o.a, o.b));
+        const double u_mine = unit_open(o.c, o.d);
+        for (int i = 0; i < 64; ++i) {
+            const double E = lane_f64(e_mine, i);
+            const double target = lane_f64(u_mine, i) * c.lam;
+            const double tau = E / c.lam;  // waiting time of this attempt
+            // target > 0 whenever the attempt can fire: target = 0 needs
+            // lambda < 2^-1021, and then tau = E/lambda > 1 since E >= 2^-53,
+            // so such an attempt is undone below before it counts.
+            int j = 0;
+#pragma unroll
+            for (int k = 0; k < NT; ++k) j += c.cum[k] < target ? 1 : 0;
+            j = __builtin_amdgcn_readfirstlane(j);
+            const int p = j >> 1;
+            const double dS = (j & 1) ? 1.0 : -1.0;  // infection takes an S, recovery returns one
+#pragma unroll
+            for (int q = 0; q < NP; ++q) {
+                const double dq = q == p ? dS : 0.0;
+                c.xd[2 * q] = c.xd[2 * q] + dq;
+                c.xd[2 * q + 1] = c.xd[2 * q + 1] - dq;
+            }
+            pairs_rates_full<NP>(c);
+            const double t1 = c.clock + tau;
+            if (!(t1 < 1.0)) {  // past the window: undo the update
+#pragma unroll
+                for (int q = 0; q < NP; ++q) {
+                    const double dq = q == p ? dS : 0.0;
+                    c.xd[2 * q] = c.xd[2 * q] - dq;
+                    c.xd[2 * q + 1] = c.xd[2 * q + 1] + dq;
+                }
+                pairs_rates_full<NP>(c);
+                return;
+            }
+            c.clock = t1;
+            c.fired = c.fired + 1;
+            if (c.fired >= SIM_MAX_FIRED) {
+                if (lane == 0) atomicMin(status, (STATUS_LIMIT_TAG << 32) | (unsigned long long)(uint32_t)r);
+                return;
+            }
+            if (!(c.lam > 0.0)) return;
+        }
+        kbase = kbase + 64;
+    }
 }
 
 // A single live chain, run by the whole wavefront with every lane holding
@@ -331,11 +410,16 @@ __device__ __forceinline__ void run_chains(const Model &m, typename Rules::State
             u.lam = lane_f64(c.lam, h);
             u.clock = lane_f64(c.clock, h);
             u.fired = __builtin_amdgcn_readlane(c.fired, h);
-            chain_uniform<Rules>(m, u, (uint32_t)__builtin_amdgcn_readlane((int)kbase, h),
-                                 (uint32_t)__builtin_amdgcn_readlane((int)node, h), day,
-                                 (uint32_t)__builtin_amdgcn_readlane((int)key0, h),
-                                 (uint32_t)__builtin_amdgcn_readlane((int)key1, h), status,
-                                 __builtin_amdgcn_readlane(r, h));
+            const uint32_t kb = (uint32_t)__builtin_amdgcn_readlane((int)kbase, h);
+            const uint32_t nh = (uint32_t)__builtin_amdgcn_readlane((int)node, h);
+            const uint32_t k0 = (uint32_t)__builtin_amdgcn_readlane((int)key0, h);
+            const uint32_t k1 = (uint32_t)__builtin_amdgcn_readlane((int)key1, h);
+            const int32_t rh = __builtin_amdgcn_readlane(r, h);
+            if constexpr (Rules::kPairs > 0) {
+                pairs_walk_uniform<Rules::kPairs>(m, u, kb, nh, day, k0, k1, status, rh);
+            } else {
+                chain_uniform<Rules>(m, u, kb, nh, day, k0, k1, status, rh);
+            }
             if ((int)lane == h) c = u;
             break;
         }

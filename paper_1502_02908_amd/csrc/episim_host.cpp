@@ -223,8 +223,13 @@ int64_t pad_nodes(int layout, int32_t R) {
 // Positions of one instance's nodes: herds sorted by size (largest first)
 // are dealt one per unit of work in turn, back and forth (snake order), so the
 // longest SSA chains of a day run in different units, start first, and share
-// their unit with the lightest herds of the next round. Returns the number of
-// positions (a multiple of the padding granule); pos_node[pos] = node or -1.
+// their unit with the lightest herds of the next round. With one lane per
+// node, the kSoloHerds largest herds get a wavefront each (the other lanes are
+// padding), so their chains are walked by the whole wavefront from the first
+// attempt. Returns the number of positions (a multiple of the padding
+// granule); pos_node[pos] = node or -1.
+constexpr int64_t kSoloHerds = 128;
+
 int64_t order_nodes(const sim_problem *p, int layout, std::vector<int32_t> *pos_node) {
     const int64_t Nn = p->n_nodes, Nc = p->n_comp;
     std::vector<int64_t> size(Nn, 0);
@@ -234,14 +239,20 @@ int64_t order_nodes(const sim_problem *p, int layout, std::vector<int32_t> *pos_
     for (int64_t i = 0; i < Nn; ++i) rank[i] = (int32_t)i;
     std::stable_sort(rank.begin(), rank.end(), [&](int32_t a, int32_t b) { return size[a] > size[b]; });
     const int64_t G = unit_nodes(layout, p->n_rep), P = pad_nodes(layout, p->n_rep);
-    const int64_t Np = Nn == 0 ? 0 : ((Nn + P - 1) / P) * P;
-    const int64_t U = Np / G;
+    // solo wavefronts only pay off when the rest still fills many wavefronts
+    const int64_t solo = (layout == LAYOUT_LANES && Nn >= 64 * kSoloHerds) ? kSoloHerds : 0;
+    const int64_t rest = Nn - solo;
+    const int64_t body = solo * 64 + rest;
+    const int64_t Np = Nn == 0 ? 0 : ((body + P - 1) / P) * P;
     pos_node->assign(Np, -1);
-    int64_t q = 0;
+    for (int64_t q = 0; q < solo; ++q) (*pos_node)[q * 64] = rank[q];
+    const int64_t base = solo * 64;
+    const int64_t U = (Np - base) / G;
+    int64_t q = solo;
     for (int64_t j = 0; j < G && q < Nn; ++j)
         for (int64_t uu = 0; uu < U && q < Nn; ++uu) {
             const int64_t u = (j & 1) ? U - 1 - uu : uu;
-            (*pos_node)[u * G + j] = rank[q++];
+            (*pos_node)[base + u * G + j] = rank[q++];
         }
     return Np;
 }
