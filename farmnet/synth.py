@@ -312,6 +312,40 @@ def prior_draws(n, seed):
     return coef, np.ones(n), beta
 
 
+SERVING_SIZES = (1000, 37000, 250000)
+
+
+def serving_networks(n_days=1461, sizes=SERVING_SIZES, seeds=(51, 52, 53), **kw):
+    """The pre-generated networks a serving run draws its requests over:
+    config 2's generator at each size, one seed each."""
+    return [sise3_network(n_nodes=n, n_days=n_days, seed=sd, **kw) for n, sd in zip(sizes, seeds)]
+
+
+def serving_requests(n_requests=None, rate=20.0, duration=60.0, n_networks=3, horizon=(365, 1461),
+                     reps=(1, 64), seed=5):
+    """Open-loop request stream: Poisson arrivals at `rate` per second over
+    `duration` seconds (or the first n_requests), each naming a network
+    uniformly, a horizon uniform on [horizon[0], horizon[1]] days, a replicate
+    count uniform on [reps[0], reps[1]], per-replicate parameters from the
+    prior box, and replicate ids (request id * 64 + r) that key its random
+    streams. Returns a list of dicts sorted by arrival time (seconds)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    t = 0.0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if (n_requests is None and t > duration) or (n_requests is not None and len(out) >= n_requests):
+            break
+        i = len(out)
+        n_rep = int(rng.integers(reps[0], reps[1] + 1))
+        coef, alpha, beta = prior_draws(n_rep, seed=int(rng.integers(1 << 31)))
+        out.append(dict(rid=i, arrival=t, net=int(rng.integers(n_networks)),
+                        horizon=int(rng.integers(horizon[0], horizon[1] + 1)), n_rep=n_rep,
+                        coef=coef, alpha=alpha, beta=beta,
+                        replicate_id=(np.uint32(i) * np.uint32(64) + np.arange(n_rep, dtype=np.uint32))))
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Small systems with known laws (test inputs)
 # ---------------------------------------------------------------------------

@@ -206,6 +206,60 @@ int64_t sim_levels(const sim_handle *h, int32_t d, int32_t *max_levels);
 #define SIM_K_PERSIST 3
 int sim_kernel_times(sim_handle *h, int32_t enable, double *ms, int64_t *launches);
 
+/* ---- Slot handles: many requests over one resident network ------------
+ * The paper's fitting workload runs many trajectories, with different rate
+ * parameters, over one event database (Sec. 4.3). A slot handle keeps one
+ * network resident (nodes, initial state, events and their levels) and
+ * n_slots slots of 64 replicate lanes each. Every slot runs its own request
+ * (its replicates, parameters and horizon) from its own day 0, while one
+ * sim_slots_step advances all running slots by one day in shared launches:
+ * the steps of the method (Alg. 1: SSA, then the day's events, then the phi
+ * update) are those of sim_run, so a request's records are bit-identical to a
+ * plain handle of the same network, replicates, parameters and replicate ids
+ * run for the same number of days. Random streams are keyed by the network's
+ * seed and the request's replicate ids, never by the slot.
+ * The network problem's n_rep, rates and replicate ids are not used and
+ * n_record must be 0; events_mode must be SIM_EVENTS_LEVELS. All calls on one
+ * handle must come from one thread. */
+size_t sim_slots_workspace_bytes(const sim_problem *network, int32_t n_slots);
+int sim_slots_create(const sim_problem *network, int32_t n_slots, const sim_device_opts *o, sim_handle **out);
+
+/* Start a request in a slot that is not running (free, or finished and
+ * fetched or abandoned): n_rep in [1, 64] replicates with rate constants
+ * coef[n_rep*Nt], shedding rates alpha[n_rep], decay rates beta[n_rep*4] and
+ * replicate_id[n_rep] (NULL: 0..n_rep-1), for horizon days in [1, D]. The
+ * parameters are copied before the call returns; the slot's lanes are loaded
+ * with (u0, v0) on the stream. Its day 0 runs in the next sim_slots_step. */
+int sim_slot_start(sim_handle *h, int32_t slot, int32_t n_rep, int32_t horizon, const double *coef,
+                   const double *alpha, const double *beta, const uint32_t *replicate_id);
+
+/* Enqueue one day of every running slot (asynchronous). The slots whose
+ * horizon this step completes (their last day closed) are written to
+ * finished[] (room for n_slots) and counted in *n_finished; either may be
+ * NULL. No running slot: nothing is enqueued. */
+int sim_slots_step(sim_handle *h, int32_t *finished, int32_t *n_finished);
+
+/* Number of enqueued steps the device has not finished (never blocks); -1 if
+ * h is not a slot handle. Lets a caller bound how far it runs ahead. */
+int32_t sim_slots_in_flight(sim_handle *h);
+
+/* Enqueue the download of a finished slot's records, days [0, horizon):
+ * prevalence[horizon*n_rep] and transitions[horizon*n_rep] as [d][r],
+ * totals[horizon*n_rep*Nc] as [d][r][c] (any may be NULL). Host buffers from
+ * hipHostMalloc keep the call asynchronous; others make it synchronous. The
+ * buffers must stay valid until sim_slot_query returns other than 1. The
+ * slot is free for sim_slot_start right after this call. */
+int sim_slot_fetch(sim_handle *h, int32_t slot, int32_t *prevalence, int64_t *transitions, int64_t *totals);
+
+/* Collect a fetch (never blocks): 1 while the download is in flight, then
+ * SIM_OK, or the slot's own device-side error (SIM_EINFEASIBLE naming the
+ * merged event index, replicate and day; SIM_ELIMIT). */
+int sim_slot_query(sim_handle *h, int32_t slot);
+
+/* The slot's current state after all enqueued work (synchronises):
+ * u[n_rep*Nn*Nc] as [r][i][c], v[n_rep*Nn] as [r][i]. */
+int sim_slot_state(sim_handle *h, int32_t slot, int32_t *u, double *v);
+
 /* Release all resources. NULL is a no-op. */
 void sim_destroy(sim_handle *h);
 

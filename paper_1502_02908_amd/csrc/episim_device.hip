@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_cooperative_groups.h>
 
+#include <algorithm>
 #include <cstdio>
 
 #include "../../include/episim.h"
@@ -458,10 +459,10 @@ __device__ __forceinline__ void run_chains(const Model &m, typename Rules::State
 // Whether no error has been recorded, read once per workgroup so that every
 // thread takes the same branch (another wavefront of the workgroup may record
 // an error while this one is still starting). Every thread must call it.
-__device__ __forceinline__ bool block_ok(const DevState &s) {
+__device__ __forceinline__ bool block_ok(const unsigned long long *status) {
     __shared__ int ok;
     __syncthreads();
-    if (threadIdx.x == 0) ok = *(volatile unsigned long long *)s.status == STATUS_OK;
+    if (threadIdx.x == 0) ok = *(volatile const unsigned long long *)status == STATUS_OK;
     __syncthreads();
     return ok != 0;
 }
@@ -528,7 +529,7 @@ __device__ void flush_tile(const Model &m, const DevState &s, const Tally<NC> &t
 #pragma unroll
     for (int c = 0; c < NC; ++c) part[wave][lane][2 + c] = t.tot[c];
     __syncthreads();
-    if (wave == 0) {
+    if (wave == 0 && set >= 0) {
         long long v[2 + NC];
 #pragma unroll
         for (int i = 0; i < 2 + NC; ++i) {
@@ -549,37 +550,21 @@ __device__ void flush_tile(const Model &m, const DevState &s, const Tally<NC> &t
     __syncthreads();
 }
 
-// Per-lane records when the lanes of a workgroup belong to different sets.
-template <int NC>
-__device__ __forceinline__ void flush_lane(const Model &m, const DevState &s, const Tally<NC> &t,
-                                           int32_t set, int32_t d_rec, int32_t d_ssa) {
-    const int64_t S = (int64_t)s.n_inst * s.R;
-    if (d_rec >= 0) {
-        const int64_t row = d_rec * S + set;
-        if (t.prev) atomicAdd(&s.prevalence[row], (int32_t)t.prev);
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-            if (comp_on<NC>(m, c) && t.tot[c])
-                atomicAdd((unsigned long long *)&s.totals[row * m.nc + c], (unsigned long long)t.tot[c]);
-    }
-    if (d_ssa >= 0 && t.trans)
-        atomicAdd((unsigned long long *)&s.transitions[d_ssa * S + set], (unsigned long long)t.trans);
-}
-
 // The day phase for the lane l of a wavefront (every lane of the wavefront
-// must call it; lanes with l >= L take part in the wavefront-level steps
-// only): close day d-1 (phi update + record) if prologue, then run the SSA of
-// day d if ssa. Adds the lane's counts to t.
+// must call it; lanes with l >= L or replicate lane r >= r_end take part in
+// the wavefront-level steps only): close day d-1 (phi update + record) if
+// prologue, then run the SSA of day d if ssa. Adds the lane's counts to t.
 template <class Rules>
 __device__ __forceinline__ void day_wave(const Model &m, const DevState &s, int64_t l, int32_t d,
-                                         bool prologue, bool ssa, Tally<Rules::NC> &t) {
+                                         bool prologue, bool ssa, Tally<Rules::NC> &t, int32_t r_end,
+                                         unsigned long long *status) {
     constexpr int NC = Rules::NC, NT = Rules::NT;
-    const int32_t R = s.R;
+    const int32_t R = s.R, RL = s.RL;
     const bool in_range = l < s.L;
-    const int32_t r = !in_range || R == 1 ? 0 : (int32_t)(l % R);
-    const int32_t pos = !in_range ? 0 : (R == 1 ? (int32_t)l : (int32_t)(l / R));
-    const int32_t nid = in_range ? s.node_id[pos] : -1;
-    const bool active = nid >= 0;  // padding positions take part in the wavefront steps only
+    const int32_t r = !in_range || RL == 1 ? 0 : (int32_t)(l % RL);
+    const int32_t pos = !in_range ? 0 : (RL == 1 ? (int32_t)l : (int32_t)(l / RL));
+    const int32_t nid = in_range && r < r_end ? s.node_id[pos] : -1;
+    const bool active = nid >= 0;  // padding positions and idle lanes take part in the wavefront steps only
     const int32_t inst = active ? s.inst[pos] : 0;
     const int32_t set = inst * R + r;
     int32_t x[NC];
@@ -634,7 +619,7 @@ __device__ __forceinline__ void day_wave(const Model &m, const DevState &s, int6
     ch.clock = 0.0;
     ch.fired = 0;
     Rules::rates(m, ch);
-    run_chains<Rules>(m, ch, active, node, (uint32_t)d, key0, key1, s.status, set);
+    run_chains<Rules>(m, ch, active, node, (uint32_t)d, key0, key1, status, set);
     t.trans += ch.fired;
     if (active && ch.fired) {
 #pragma unroll
@@ -647,29 +632,39 @@ template <class Rules>
 __global__ __launch_bounds__(kBlock) void k_day(Model m, DevState s, int32_t d, int32_t prologue,
                                                 int32_t ssa) {
     constexpr int NC = Rules::NC;
-    if (!block_ok(s)) return;
+    if (!block_ok(s.status)) return;
     const int64_t l = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     Tally<NC> t{};
-    day_wave<Rules>(m, s, l, d, prologue != 0, ssa != 0, t);
+    day_wave<Rules>(m, s, l, d, prologue != 0, ssa != 0, t, s.R, s.status);
     const int32_t d_rec = prologue ? d - 1 : -1;
     const int32_t d_ssa = ssa ? d : -1;
-    if (s.R == 1) {
-        // instances are padded to whole workgroups: one set per workgroup
-        flush_block<NC>(m, s, t, s.inst[(int64_t)blockIdx.x * kBlock], d_rec, d_ssa);
-    } else if (l < s.L && s.node_id[l / s.R] >= 0) {
-        flush_lane<NC>(m, s, t, s.inst[l / s.R] * s.R + (int32_t)(l % s.R), d_rec, d_ssa);
-    }
+    // one lane per node; instances are padded to whole workgroups: one set per workgroup
+    flush_block<NC>(m, s, t, s.inst[(int64_t)blockIdx.x * kBlock], d_rec, d_ssa);
 }
 
-// Replicate tiles (R a multiple of 64): workgroup (x, y) takes positions
-// [x * kTileNodes, (x + 1) * kTileNodes) and replicates [64 y, 64 y + 64);
-// wavefront w walks the positions w, w + 4, ... so a lane always holds the
-// same replicate and its counts add up in registers.
+// Replicate tiles (replicate lanes in groups of 64): workgroup (x, y) takes
+// positions [x * kTileNodes, (x + 1) * kTileNodes) and replicate lanes
+// [64 y, 64 y + 64); wavefront w walks the positions w, w + 4, ... so a lane
+// always holds the same replicate and its counts add up in registers.
+// In a slot handle, column y is slot y: d is the handle's step, the slot's own
+// day is d - t0, and the slot's lanes past its replicate count are idle.
 template <class Rules>
 __global__ __launch_bounds__(kBlock) void k_day_tile(Model m, DevState s, int32_t d, int32_t prologue,
                                                      int32_t ssa) {
     constexpr int NC = Rules::NC;
-    if (!block_ok(s)) return;
+    int32_t r_end = s.R;
+    unsigned long long *status = s.status;
+    if (s.slots) {
+        const SlotInfo si = s.slots[blockIdx.y];
+        const int32_t ds = d - si.t0;
+        if (si.t0 < 0 || ds < 0 || ds > si.horizon) return;  // uniform over the workgroup
+        d = ds;
+        prologue = ds > 0;
+        ssa = ds < si.horizon;
+        r_end = (int32_t)blockIdx.y * 64 + si.n_rep;
+        status += blockIdx.y;
+    }
+    if (!block_ok(status)) return;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t pos0 = (int64_t)blockIdx.x * kTileNodes;
     const int32_t r = (int32_t)blockIdx.y * 64 + lane;
@@ -677,10 +672,10 @@ __global__ __launch_bounds__(kBlock) void k_day_tile(Model m, DevState s, int32_
     for (int j = wave; j < kTileNodes; j += kWaves) {
         const int64_t pos = pos0 + j;
         if (pos >= s.Np) break;
-        day_wave<Rules>(m, s, pos * s.R + r, d, prologue != 0, ssa != 0, t);
+        day_wave<Rules>(m, s, pos * s.RL + r, d, prologue != 0, ssa != 0, t, r_end, status);
     }
     // instances are padded to whole tiles: one instance per workgroup
-    flush_tile<NC>(m, s, t, s.inst[pos0] * s.R + r, prologue ? d - 1 : -1, ssa ? d : -1);
+    flush_tile<NC>(m, s, t, r < r_end ? s.inst[pos0] * s.R + r : -1, prologue ? d - 1 : -1, ssa ? d : -1);
 }
 
 // ---------------------------------------------------------------------------
@@ -698,14 +693,14 @@ __device__ __forceinline__ int32_t load_l2(const int32_t *p) {
 
 template <int NC>
 __device__ __forceinline__ void event_one(const Model &m, const DevState &s, const DevEvents &ev,
-                                          int64_t e, int32_t r, int32_t d) {
+                                          int64_t e, int32_t r, int32_t d, unsigned long long *status) {
     const uint32_t meta = ev.meta[e];
     const int kind = (int)(meta & kEvKindMask);
     const uint32_t mask = (meta >> 2) & 0xffu;
     const int sid = (int)((meta >> 10) & 0x3fu) - 1;
     const int32_t node = ev.node[e];
     const int32_t n = ev.n[e];
-    const int64_t ls = (int64_t)node * s.R + r;
+    const int64_t ls = (int64_t)node * s.RL + r;
     if (kind == SIM_ENTER) {
 #pragma unroll
         for (int c = 0; c < NC; ++c)
@@ -726,7 +721,7 @@ __device__ __forceinline__ void event_one(const Model &m, const DevState &s, con
     const int32_t inst = s.inst[node];
     const int32_t set = inst * s.R + r;
     if ((long long)n > tot) {
-        atomicMin(s.status, ((unsigned long long)(uint32_t)ev.gm[e] << 32) | (unsigned long long)(uint32_t)set);
+        atomicMin(status, ((unsigned long long)(uint32_t)ev.gm[e] << 32) | (unsigned long long)(uint32_t)set);
         return;
     }
     int32_t take[NC];
@@ -794,7 +789,7 @@ __device__ __forceinline__ void event_one(const Model &m, const DevState &s, con
     for (int c = 0; c < NC; ++c)
         if ((mask >> c) & 1u) s.u[(int64_t)c * s.L + ls] = x[c];
     if (kind == SIM_EXTERNAL) {
-        const int64_t ld = (int64_t)ev.dest[e] * s.R + r;
+        const int64_t ld = (int64_t)ev.dest[e] * s.RL + r;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             if (take[c]) {
@@ -810,11 +805,11 @@ __global__ __launch_bounds__(kBlock) void k_events(Model m, DevState s, DevEvent
                                                    int64_t begin, int64_t end) {
     if (*(volatile unsigned long long *)s.status != STATUS_OK) return;
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t count = (end - begin) * s.R;
+    const int64_t count = (end - begin) * s.RL;
     if (t >= count) return;
-    const int64_t e = begin + (s.R == 1 ? t : t / s.R);
-    const int32_t r = s.R == 1 ? 0 : (int32_t)(t % s.R);
-    event_one<NC>(m, s, ev, e, r, d);
+    const int64_t e = begin + (s.RL == 1 ? t : t / s.RL);
+    const int32_t r = s.RL == 1 ? 0 : (int32_t)(t % s.RL);
+    if (r < s.R) event_one<NC>(m, s, ev, e, r, d, s.status);
 }
 
 // A run of small levels [lv_begin, lv_end) of day d in one workgroup, with a
@@ -822,15 +817,67 @@ __global__ __launch_bounds__(kBlock) void k_events(Model m, DevState s, DevEvent
 template <int NC>
 __global__ __launch_bounds__(kEvBlock) void k_event_levels(Model m, DevState s, DevEvents ev, int32_t d,
                                                            int32_t lv_begin, int32_t lv_end) {
-    if (!block_ok(s)) return;
+    if (!block_ok(s.status)) return;
     for (int32_t lv = lv_begin; lv < lv_end; ++lv) {
         const int64_t begin = ev.lvl_off[lv], end = ev.lvl_off[lv + 1];
-        const int64_t count = (end - begin) * s.R;
+        const int64_t count = (end - begin) * s.RL;
         for (int64_t t = threadIdx.x; t < count; t += kEvBlock) {
-            const int64_t e = begin + (s.R == 1 ? t : t / s.R);
-            event_one<NC>(m, s, ev, e, s.R == 1 ? 0 : (int32_t)(t % s.R), d);
+            const int64_t e = begin + (s.RL == 1 ? t : t / s.RL);
+            const int32_t r = s.RL == 1 ? 0 : (int32_t)(t % s.RL);
+            if (r < s.R) event_one<NC>(m, s, ev, e, r, d, s.status);
         }
         __syncthreads();
+    }
+}
+
+// Slot handles: level k of each slot's own day, one grid row per slot. With
+// k_end > k + 1 the grid is one workgroup per slot and runs the levels
+// k .. k_end-1 with a workgroup barrier between them.
+template <int NC>
+__global__ __launch_bounds__(kEvBlock) void k_slot_events(Model m, DevState s, DevEvents ev, int32_t step,
+                                                          int32_t k, int32_t k_end) {
+    const SlotInfo si = s.slots[blockIdx.y];
+    const int32_t d = step - si.t0;
+    if (si.t0 < 0 || d < 0 || d >= si.horizon) return;  // uniform over the workgroup
+    unsigned long long *status = s.status + blockIdx.y;
+    if (!block_ok(status)) return;
+    const int32_t lv0 = ev.lvl_ptr[d], lv_day_end = ev.lvl_ptr[d + 1];
+    const int64_t stride = (int64_t)gridDim.x * kEvBlock;
+    for (int32_t kk = k; kk < k_end && lv0 + kk < lv_day_end; ++kk) {
+        const int64_t begin = ev.lvl_off[lv0 + kk], end = ev.lvl_off[lv0 + kk + 1];
+        const int64_t count = (end - begin) * 64;
+        for (int64_t t = (int64_t)blockIdx.x * kEvBlock + threadIdx.x; t < count; t += stride) {
+            const int32_t rr = (int32_t)(t & 63);
+            if (rr < si.n_rep) event_one<NC>(m, s, ev, begin + (t >> 6), (int32_t)blockIdx.y * 64 + rr, d, status);
+        }
+        if (k_end > k + 1) __syncthreads();
+    }
+}
+
+// Start a slot: write its table entry, clear its error word and its records,
+// and load every replicate lane of it with the network's initial state.
+__global__ __launch_bounds__(kBlock) void k_slot_init(DevState s, int32_t nc, const int32_t *u0, const double *v0,
+                                                      int32_t slot, SlotInfo info) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    if (t == 0) {
+        s.slots[slot] = info;
+        s.status[slot] = STATUS_OK;
+    }
+    const int64_t S = s.RL;
+    for (int64_t i = t; i < s.Np * 64; i += stride) {
+        const int64_t pos = i >> 6;
+        const int32_t rr = (int32_t)(i & 63);
+        const int64_t l = pos * s.RL + (int64_t)slot * 64 + rr;
+        const bool live = rr < info.n_rep;
+        for (int c = 0; c < nc; ++c) s.u[(int64_t)c * s.L + l] = live ? u0[(int64_t)c * s.Np + pos] : 0;
+        s.phi[l] = live ? v0[pos] : 0.0;
+    }
+    for (int64_t i = t; i < (int64_t)s.n_days * 64; i += stride) {
+        const int64_t row = (i >> 6) * S + (int64_t)slot * 64 + (i & 63);
+        s.prevalence[row] = 0;
+        s.transitions[row] = 0;
+        for (int c = 0; c < nc; ++c) s.totals[row * nc + c] = 0;
     }
 }
 
@@ -849,11 +896,11 @@ __global__ __launch_bounds__(kBlock) void k_persist(Model m, DevState s, DevEven
         const bool prologue = d > d_begin;
         const bool ssa = d < d_end;
         const int32_t d_rec = prologue ? d - 1 : -1, d_ssa = ssa ? d : -1;
-        if (block_ok(s)) {
+        if (block_ok(s.status)) {
             if (layout == LAYOUT_TILE) {
                 const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
                 const int64_t nx = (s.Np + kTileNodes - 1) / kTileNodes;
-                const int64_t n_tiles = nx * (s.R / 64);
+                const int64_t n_tiles = nx * (s.RL / 64);
                 for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
                     const int64_t pos0 = (tile % nx) * kTileNodes;
                     const int32_t r = (int32_t)(tile / nx) * 64 + lane;
@@ -861,21 +908,17 @@ __global__ __launch_bounds__(kBlock) void k_persist(Model m, DevState s, DevEven
                     for (int j = wave; j < kTileNodes; j += kWaves) {
                         const int64_t pos = pos0 + j;
                         if (pos >= s.Np) break;
-                        day_wave<Rules>(m, s, pos * s.R + r, d, prologue, ssa, t);
+                        day_wave<Rules>(m, s, pos * s.RL + r, d, prologue, ssa, t, s.R, s.status);
                     }
-                    flush_tile<NC>(m, s, t, s.inst[pos0] * s.R + r, d_rec, d_ssa);
+                    flush_tile<NC>(m, s, t, r < s.R ? s.inst[pos0] * s.R + r : -1, d_rec, d_ssa);
                 }
             } else {
                 const int64_t chunks = (s.L + kBlock - 1) / kBlock;
                 for (int64_t chunk = blockIdx.x; chunk < chunks; chunk += gridDim.x) {
                     const int64_t l = chunk * kBlock + threadIdx.x;
                     Tally<NC> t{};
-                    day_wave<Rules>(m, s, l, d, prologue, ssa, t);
-                    if (s.R == 1) {
-                        flush_block<NC>(m, s, t, s.inst[chunk * kBlock], d_rec, d_ssa);
-                    } else if (l < s.L && s.node_id[l / s.R] >= 0) {
-                        flush_lane<NC>(m, s, t, s.inst[l / s.R] * s.R + (int32_t)(l % s.R), d_rec, d_ssa);
-                    }
+                    day_wave<Rules>(m, s, l, d, prologue, ssa, t, s.R, s.status);
+                    flush_block<NC>(m, s, t, s.inst[chunk * kBlock], d_rec, d_ssa);
                 }
             }
         }
@@ -886,26 +929,28 @@ __global__ __launch_bounds__(kBlock) void k_persist(Model m, DevState s, DevEven
         int32_t lv = ev.lvl_ptr[d];
         const int32_t lv_end = ev.lvl_ptr[d + 1];
         while (lv < lv_end) {
-            const int64_t size = (ev.lvl_off[lv + 1] - ev.lvl_off[lv]) * s.R;
+            const int64_t size = (ev.lvl_off[lv + 1] - ev.lvl_off[lv]) * s.RL;
             if (size > kSmallLevel) {
                 const int64_t begin = ev.lvl_off[lv];
                 if (*(volatile unsigned long long *)s.status == STATUS_OK) {
                     for (int64_t t = first; t < size; t += stride) {
-                        const int64_t e = begin + (s.R == 1 ? t : t / s.R);
-                        event_one<NC>(m, s, ev, e, s.R == 1 ? 0 : (int32_t)(t % s.R), d);
+                        const int64_t e = begin + (s.RL == 1 ? t : t / s.RL);
+                        const int32_t r = s.RL == 1 ? 0 : (int32_t)(t % s.RL);
+                        if (r < s.R) event_one<NC>(m, s, ev, e, r, d, s.status);
                     }
                 }
                 ++lv;
             } else {
                 int32_t stop = lv + 1;
-                while (stop < lv_end && (ev.lvl_off[stop + 1] - ev.lvl_off[stop]) * s.R <= kSmallLevel) ++stop;
+                while (stop < lv_end && (ev.lvl_off[stop + 1] - ev.lvl_off[stop]) * s.RL <= kSmallLevel) ++stop;
                 if (blockIdx.x == 0) {
                     for (int32_t k = lv; k < stop; ++k) {
                         const int64_t begin = ev.lvl_off[k];
-                        const int64_t count = (ev.lvl_off[k + 1] - begin) * s.R;
+                        const int64_t count = (ev.lvl_off[k + 1] - begin) * s.RL;
                         for (int64_t t = threadIdx.x; t < count; t += kBlock) {
-                            const int64_t e = begin + (s.R == 1 ? t : t / s.R);
-                            event_one<NC>(m, s, ev, e, s.R == 1 ? 0 : (int32_t)(t % s.R), d);
+                            const int64_t e = begin + (s.RL == 1 ? t : t / s.RL);
+                            const int32_t r = s.RL == 1 ? 0 : (int32_t)(t % s.RL);
+                            if (r < s.R) event_one<NC>(m, s, ev, e, r, d, s.status);
                         }
                         __syncthreads();
                     }
@@ -924,16 +969,17 @@ struct Kernels {
     static void *events() { return (void *)&k_events<Rules::NC>; }
     static void *levels() { return (void *)&k_event_levels<Rules::NC>; }
     static void *persist() { return (void *)&k_persist<Rules>; }
+    static void *slot_events() { return (void *)&k_slot_events<Rules::NC>; }
 };
 
 struct Table {
-    void *day, *events, *persist, *levels, *tile;
+    void *day, *events, *persist, *levels, *tile, *slot_events;
 };
 
 template <class Rules>
 Table table() {
-    return {Kernels<Rules>::day(), Kernels<Rules>::events(), Kernels<Rules>::persist(), Kernels<Rules>::levels(),
-            Kernels<Rules>::tile()};
+    return {Kernels<Rules>::day(),    Kernels<Rules>::events(), Kernels<Rules>::persist(),
+            Kernels<Rules>::levels(), Kernels<Rules>::tile(),   Kernels<Rules>::slot_events()};
 }
 
 Table pick(const Model &m) {
@@ -954,7 +1000,7 @@ int launch_day(const Model &m, const DevState &s, int32_t d, int prologue, int s
     void *args[] = {&mm, &ss, &dd, &pro, &sa};
     if (layout == LAYOUT_TILE) {
         const unsigned nx = (unsigned)((s.Np + kTileNodes - 1) / kTileNodes);
-        return (int)hipLaunchKernel(t.tile, dim3(nx, (unsigned)(s.R / 64)), dim3(kBlock), args, 0,
+        return (int)hipLaunchKernel(t.tile, dim3(nx, (unsigned)(s.RL / 64)), dim3(kBlock), args, 0,
                                     (hipStream_t)stream);
     }
     const unsigned grid = (unsigned)((s.L + kBlock - 1) / kBlock);
@@ -963,7 +1009,7 @@ int launch_day(const Model &m, const DevState &s, int32_t d, int prologue, int s
 
 int launch_events(const Model &m, const DevState &s, const DevEvents &ev, int32_t d, int64_t begin,
                   int64_t end, void *stream) {
-    const int64_t count = (end - begin) * s.R;
+    const int64_t count = (end - begin) * s.RL;
     if (count <= 0) return hipSuccess;
     const Table t = pick(m);
     const unsigned grid = (unsigned)((count + kBlock - 1) / kBlock);
@@ -1003,7 +1049,7 @@ int launch_persistent(const Model &m, const DevState &s, const DevEvents &ev, in
         snprintf(why, why_len, "persistent kernel cannot be resident (occupancy 0)");
         return (int)hipErrorInvalidConfiguration;
     }
-    const int64_t want = layout == LAYOUT_TILE ? ((s.Np + kTileNodes - 1) / kTileNodes) * (s.R / 64)
+    const int64_t want = layout == LAYOUT_TILE ? ((s.Np + kTileNodes - 1) / kTileNodes) * (s.RL / 64)
                                                : (s.L + kBlock - 1) / kBlock;
     int64_t grid = (int64_t)cus * per_cu;
     if (want < grid) grid = want > 0 ? want : 1;
@@ -1014,6 +1060,34 @@ int launch_persistent(const Model &m, const DevState &s, const DevEvents &ev, in
     void *args[] = {&mm, &ss, &ee, &a, &b, &lay};
     return (int)hipLaunchCooperativeKernel(t.persist, dim3((unsigned)grid), dim3(kBlock), args, 0,
                                            (hipStream_t)stream);
+}
+
+int launch_slot_events(const Model &m, const DevState &s, const DevEvents &ev, int32_t step, int32_t k,
+                       int32_t k_end, int64_t max_count, void *stream) {
+    if (k_end <= k || max_count <= 0) return hipSuccess;
+    const Table t = pick(m);
+    const int64_t want = k_end > k + 1 ? 1 : (max_count + kEvBlock - 1) / kEvBlock;
+    const unsigned gx = (unsigned)std::min<int64_t>(want, 4096);
+    Model mm = m;
+    DevState ss = s;
+    DevEvents ee = ev;
+    int32_t a = step, b = k, c = k_end;
+    void *args[] = {&mm, &ss, &ee, &a, &b, &c};
+    return (int)hipLaunchKernel(t.slot_events, dim3(gx, (unsigned)(s.RL / 64)), dim3(kEvBlock), args, 0,
+                                (hipStream_t)stream);
+}
+
+int launch_slot_init(const DevState &s, int32_t nc, const int32_t *u0, const double *v0, int32_t slot,
+                     const SlotInfo &info, void *stream) {
+    const int64_t work = std::max<int64_t>(s.Np * 64, (int64_t)s.n_days * 64);
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((work + kBlock - 1) / kBlock, 8192));
+    DevState ss = s;
+    int32_t n = nc, sl = slot;
+    const int32_t *a = u0;
+    const double *b = v0;
+    SlotInfo in = info;
+    void *args[] = {&ss, &n, &a, &b, &sl, &in};
+    return (int)hipLaunchKernel((void *)&k_slot_init, dim3(grid), dim3(kBlock), args, 0, (hipStream_t)stream);
 }
 
 }  // namespace episim

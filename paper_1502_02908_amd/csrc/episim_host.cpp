@@ -24,6 +24,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <new>
 #include <string>
 #include <vector>
@@ -102,6 +103,20 @@ uint32_t column_mask(const sim_problem *p, int32_t s) {
     return m;
 }
 
+// Rate constants, shedding rates and decay rates of R trajectories.
+int check_params(int Nt, int64_t R, const double *coef, const double *alpha, const double *beta, std::string *err) {
+    for (int64_t i = 0; i < R * Nt; ++i)
+        if (!(coef[i] >= 0.0) || !std::isfinite(coef[i])) return *err = "coef must be finite and >= 0", SIM_EINVAL;
+    for (int64_t r = 0; r < R; ++r) {
+        if (!(alpha[r] >= 0.0) || !std::isfinite(alpha[r])) return *err = "alpha must be finite and >= 0", SIM_EINVAL;
+        for (int q = 0; q < 4; ++q) {
+            const double b = beta[r * 4 + q];
+            if (!(b >= 0.0 && b <= 1.0)) return *err = "beta must be in [0, 1]", SIM_EINVAL;
+        }
+    }
+    return SIM_OK;
+}
+
 // Full validation of one problem statement (the contract in episim.h).
 int validate(const sim_problem *p, std::string *err) {
     if (!p) return *err = "problem is NULL", SIM_EINVAL;
@@ -133,15 +148,7 @@ int validate(const sim_problem *p, std::string *err) {
             if (s > 127) return *err = fmt("S[%d,%d] too large", c, k), SIM_EINVAL;
         }
     }
-    for (int64_t i = 0; i < (int64_t)R * Nt; ++i)
-        if (!(p->coef[i] >= 0.0) || !std::isfinite(p->coef[i])) return *err = "coef must be finite and >= 0", SIM_EINVAL;
-    for (int r = 0; r < R; ++r) {
-        if (!(p->alpha[r] >= 0.0) || !std::isfinite(p->alpha[r])) return *err = "alpha must be finite and >= 0", SIM_EINVAL;
-        for (int q = 0; q < 4; ++q) {
-            const double b = p->beta[r * 4 + q];
-            if (!(b >= 0.0 && b <= 1.0)) return *err = "beta must be in [0, 1]", SIM_EINVAL;
-        }
-    }
+    if (int rc = check_params(Nt, R, p->coef, p->alpha, p->beta, err)) return rc;
     const uint32_t all = (Nc == 32) ? ~0u : ((1u << Nc) - 1u);
     if ((p->phi_I_mask & ~all) || (p->phi_N_mask & ~all)) return *err = "phi masks name a missing compartment", SIM_EINVAL;
     if (p->n_select < 0 || p->n_shift < 0 || p->n_shift > MAX_SHIFT_IDS)
@@ -203,22 +210,15 @@ int same_model(const sim_problem *a, const sim_problem *b, std::string *err) {
     return SIM_OK;
 }
 
-int choose_layout(int32_t R) {
-    if (R == 1) return LAYOUT_LANES;
-    if (R % 64 == 0) return LAYOUT_TILE;
-    return LAYOUT_LANES_ATOMIC;
-}
+int choose_layout(int32_t R) { return R == 1 ? LAYOUT_LANES : LAYOUT_TILE; }
+
+// Lanes per position: one, or the replicate count rounded up to whole
+// wavefronts (replicate lanes r >= R idle).
+int32_t lane_stride(int32_t R) { return R == 1 ? 1 : (int32_t)(((int64_t)R + 63) / 64 * 64); }
 
 // Nodes of one unit of work and the padding granule of an instance.
-int64_t unit_nodes(int layout, int32_t R) {
-    if (layout == LAYOUT_TILE) return kTileNodes;
-    return std::max<int64_t>(1, 64 / R);
-}
-int64_t pad_nodes(int layout, int32_t R) {
-    if (layout == LAYOUT_TILE) return kTileNodes;
-    if (layout == LAYOUT_LANES) return 256;  // one workgroup
-    return std::max<int64_t>(1, 64 / R);
-}
+int64_t unit_nodes(int layout) { return layout == LAYOUT_TILE ? kTileNodes : 64; }
+int64_t pad_nodes(int layout) { return layout == LAYOUT_TILE ? kTileNodes : 256; /* one workgroup */ }
 
 // Positions of one instance's nodes: herds sorted by size (largest first)
 // are dealt one per unit of work in turn, back and forth (snake order), so the
@@ -238,7 +238,7 @@ int64_t order_nodes(const sim_problem *p, int layout, std::vector<int32_t> *pos_
     std::vector<int32_t> rank(Nn);
     for (int64_t i = 0; i < Nn; ++i) rank[i] = (int32_t)i;
     std::stable_sort(rank.begin(), rank.end(), [&](int32_t a, int32_t b) { return size[a] > size[b]; });
-    const int64_t G = unit_nodes(layout, p->n_rep), P = pad_nodes(layout, p->n_rep);
+    const int64_t G = unit_nodes(layout), P = pad_nodes(layout);
     // solo wavefronts only pay off when the rest still fills many wavefronts
     const int64_t solo = (layout == LAYOUT_LANES && Nn >= 64 * kSoloHerds) ? kSoloHerds : 0;
     const int64_t rest = Nn - solo;
@@ -260,13 +260,15 @@ int64_t order_nodes(const sim_problem *p, int layout, std::vector<int32_t> *pos_
 // Device buffer layout of one handle.
 struct Layout {
     size_t u, phi, node_id, inst, inst_off, seed, coef, alpha, beta, repid, shift, status, ev_g, ev_gm, ev_node,
-        ev_dest, ev_n, ev_meta, lvl_off, lvl_ptr, prevalence, transitions, totals, snap_u, snap_v, rec_slot, total;
+        ev_dest, ev_n, ev_meta, lvl_off, lvl_ptr, prevalence, transitions, totals, snap_u, snap_v, rec_slot, slots,
+        u0, v0, total;
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-Layout layout_for(int64_t Np, int64_t n_nodes, int64_t n_inst, int64_t Nc, int64_t Nt, int64_t R, int64_t D,
-                  int64_t n_events, int64_t n_shift_ids, int64_t n_levels, int64_t n_record) {
+Layout layout_for(int64_t Np, int64_t n_nodes, int64_t n_inst, int64_t Nc, int64_t Nt, int64_t R, int64_t RL,
+                  int64_t D, int64_t n_events, int64_t n_shift_ids, int64_t n_levels, int64_t n_record,
+                  int64_t n_slots) {
     Layout l{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -274,7 +276,7 @@ Layout layout_for(int64_t Np, int64_t n_nodes, int64_t n_inst, int64_t Nc, int64
         off = align_up(off + std::max<size_t>(bytes, 1));
         return at;
     };
-    const int64_t L = Np * R, S = n_inst * R;
+    const int64_t L = Np * RL, S = n_inst * R;
     l.u = take(sizeof(int32_t) * Nc * L);
     l.phi = take(sizeof(double) * L);
     l.node_id = take(sizeof(int32_t) * Np);
@@ -286,7 +288,7 @@ Layout layout_for(int64_t Np, int64_t n_nodes, int64_t n_inst, int64_t Nc, int64
     l.beta = take(sizeof(double) * S * 4);
     l.repid = take(sizeof(uint32_t) * S);
     l.shift = take(sizeof(int32_t) * MAXC * std::max<int64_t>(n_shift_ids, 1));
-    l.status = take(sizeof(unsigned long long));
+    l.status = take(sizeof(unsigned long long) * std::max<int64_t>(n_slots, 1));
     l.ev_g = take(sizeof(int32_t) * n_events);
     l.ev_gm = take(sizeof(int32_t) * n_events);
     l.ev_node = take(sizeof(int32_t) * n_events);
@@ -301,13 +303,17 @@ Layout layout_for(int64_t Np, int64_t n_nodes, int64_t n_inst, int64_t Nc, int64
     l.snap_u = take(sizeof(int32_t) * n_record * R * n_nodes * Nc);
     l.snap_v = take(sizeof(double) * n_record * R * n_nodes);
     l.rec_slot = take(sizeof(int32_t) * D);
+    // slot handles: the slot table and the network's initial state by position
+    l.slots = take(sizeof(SlotInfo) * n_slots);
+    l.u0 = take(n_slots ? sizeof(int32_t) * Nc * Np : 0);
+    l.v0 = take(n_slots ? sizeof(double) * Np : 0);
     l.total = off;
     return l;
 }
 
 // Everything a handle uploads, built on the host from one or more problems.
 struct Packed {
-    int32_t n_inst = 0, R = 0, D = 0, Nc = 0, Nt = 0, n_record = 0, layout = 0;
+    int32_t n_inst = 0, R = 0, RL = 0, D = 0, Nc = 0, Nt = 0, n_record = 0, layout = 0, n_slots = 0;
     int64_t Np = 0, n_nodes = 0, n_events = 0, n_levels = 0;
     std::vector<int32_t> node_id, inst, inst_off, inst_pos0;
     std::vector<uint32_t> seed, repid;
@@ -321,7 +327,10 @@ struct Packed {
     std::vector<int32_t> rec_slot;
 };
 
-int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, Packed *pk, std::string *err) {
+// n_slots > 0 builds a slot handle of one network: n_slots columns of 64
+// replicate lanes, parameters supplied later slot by slot.
+int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, Packed *pk, std::string *err,
+                 int32_t n_slots = 0) {
     if (n < 1 || !ps) return *err = "no problems", SIM_EINVAL;
     for (int32_t k = 0; k < n; ++k) {
         int rc = validate(ps[k], err);
@@ -334,13 +343,18 @@ int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, P
     if (events_mode != SIM_EVENTS_LEVELS && events_mode != SIM_EVENTS_SERIAL)
         return *err = "unknown events_mode", SIM_EINVAL;
     const sim_problem *p0 = ps[0];
+    if (n_slots < 0 || (n_slots > 0 && n != 1)) return *err = "a slot handle holds one network", SIM_EINVAL;
+    if (n_slots > 0 && p0->n_record > 0) return *err = "slot handles keep no snapshots (n_record must be 0)", SIM_EINVAL;
+    if ((int64_t)n_slots * 64 > 65535 * 64) return *err = "too many slots", SIM_EINVAL;
     pk->n_inst = n;
-    pk->R = p0->n_rep;
+    pk->n_slots = n_slots;
+    pk->R = n_slots > 0 ? 64 * n_slots : p0->n_rep;
     pk->D = p0->n_days;
     pk->Nc = p0->n_comp;
     pk->Nt = p0->n_trans;
     pk->n_record = p0->n_record;
-    pk->layout = choose_layout(pk->R);
+    pk->layout = n_slots > 0 ? LAYOUT_TILE : choose_layout(pk->R);
+    pk->RL = lane_stride(pk->R);
     const int32_t R = pk->R;
     // positions
     std::vector<std::vector<int32_t>> pos_node(n);
@@ -353,7 +367,7 @@ int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, P
         pk->n_nodes += ps[k]->n_nodes;
         pk->n_events += ps[k]->n_events;
     }
-    if (pk->Np * (int64_t)R > INT32_MAX) return *err = "positions x replicates must stay below 2^31", SIM_EINVAL;
+    if (pk->Np * (int64_t)pk->RL > INT32_MAX) return *err = "positions x replicate lanes must stay below 2^31", SIM_EINVAL;
     if (pk->n_events > INT32_MAX) return *err = "too many events", SIM_EINVAL;
     pk->node_id.assign(pk->Np, -1);
     pk->inst.assign(pk->Np, 0);
@@ -377,6 +391,7 @@ int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, P
     for (int32_t k = 0; k < n; ++k) {
         const sim_problem *p = ps[k];
         pk->seed[k] = p->seed;
+        if (n_slots > 0) break;  // a slot's parameters come with its request
         std::memcpy(&pk->coef[(size_t)k * R * pk->Nt], p->coef, sizeof(double) * R * pk->Nt);
         std::memcpy(&pk->alpha[(size_t)k * R], p->alpha, sizeof(double) * R);
         std::memcpy(&pk->beta[(size_t)k * R * 4], p->beta, sizeof(double) * R * 4);
@@ -443,14 +458,14 @@ int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, P
 }
 
 Layout layout_of(const Packed &pk, const sim_problem *p0) {
-    return layout_for(pk.Np, pk.n_nodes, pk.n_inst, pk.Nc, pk.Nt, pk.R, pk.D, pk.n_events, p0->n_shift, pk.n_levels,
-                      pk.n_record);
+    return layout_for(pk.Np, pk.n_nodes, pk.n_inst, pk.Nc, pk.Nt, pk.R, pk.RL, pk.D, pk.n_events, p0->n_shift,
+                      pk.n_levels, pk.n_record, pk.n_slots);
 }
 
 }  // namespace
 
 struct sim_handle {
-    int32_t Nc = 0, Nt = 0, R = 0, D = 0, n_record = 0, n_inst = 0, layout = 0;
+    int32_t Nc = 0, Nt = 0, R = 0, RL = 0, D = 0, n_record = 0, n_inst = 0, layout = 0;
     int64_t Np = 0, L = 0, n_nodes = 0;
     Model model{};
     DevState st{};
@@ -477,6 +492,20 @@ struct sim_handle {
     std::vector<Mark> marks;
     double ms[4] = {0, 0, 0, 0};
     int64_t launches[4] = {0, 0, 0, 0};
+    // slot handles
+    struct Slot {
+        int state = 0;  // SLOT_FREE, SLOT_RUNNING, SLOT_DONE
+        int32_t t0 = -1, n_rep = 0, horizon = 0;
+        hipEvent_t staged = nullptr;   // parameter upload of the last start
+        hipEvent_t fetched = nullptr;  // result download of the last fetch
+        bool fetch_pending = false;
+    };
+    int32_t n_slots = 0;
+    int32_t step = 0;
+    std::vector<Slot> slots;
+    std::deque<hipEvent_t> in_flight;  // one event per enqueued step, oldest first
+    char *stage = nullptr;              // pinned: per slot, parameters then the error word
+    size_t stage_stride = 0;
 };
 
 namespace {
@@ -525,7 +554,58 @@ int collect_marks(sim_handle *h) {
     return SIM_OK;
 }
 
-int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, sim_handle **out) {
+enum { SLOT_FREE = 0, SLOT_RUNNING = 1, SLOT_DONE = 2 };
+
+// Levels of at most this many (event, lane) pairs in every slot run together,
+// one workgroup per slot.
+constexpr int64_t kSlotSmallLevel = 4096;
+
+// Bytes of one slot's parameter staging: coef, alpha, beta, replicate ids, error word.
+size_t stage_bytes(int Nt) {
+    return align_up(sizeof(double) * 64 * (Nt + 1 + 4) + sizeof(uint32_t) * 64 + sizeof(unsigned long long));
+}
+
+// Second half of creating a slot handle: the network's initial state by
+// position (copied into a slot's lanes when it starts), zero lanes, an empty
+// slot table and the pinned staging area.
+// The pinned word a fetch copies a slot's error word into (the end of its staging).
+unsigned long long *error_word(sim_handle *h, int32_t slot) {
+    return reinterpret_cast<unsigned long long *>(h->stage + (size_t)(slot + 1) * h->stage_stride) - 1;
+}
+
+int create_slots(sim_handle *h, const sim_problem *p, sim_handle **out) {
+    std::string &err = g_create_error;
+    const Layout &l = h->lay;
+    std::vector<int32_t> u0((size_t)h->Nc * h->Np, 0);
+    std::vector<double> v0(h->Np, 0.0);
+    for (int64_t i = 0; i < h->n_nodes; ++i) {
+        const int64_t pos = h->lane_of[i];
+        for (int c = 0; c < h->Nc; ++c) u0[(size_t)c * h->Np + pos] = p->u0[i * h->Nc + c];
+        v0[pos] = p->v0[i];
+    }
+    std::vector<SlotInfo> table(h->n_slots, SlotInfo{-1, 0, 0, 0});
+    int rc = check_device(hipMemcpy(at<char>(h->ws, l.u0), u0.data(), sizeof(int32_t) * u0.size(), hipMemcpyHostToDevice), &err, "upload u0");
+    if (!rc) rc = check_device(hipMemcpy(at<char>(h->ws, l.v0), v0.data(), sizeof(double) * v0.size(), hipMemcpyHostToDevice), &err, "upload v0");
+    if (!rc) rc = check_device(hipMemcpy(h->st.slots, table.data(), sizeof(SlotInfo) * table.size(), hipMemcpyHostToDevice), &err, "upload slots");
+    if (!rc && h->L > 0) rc = check_device(hipMemset(h->st.u, 0, sizeof(int32_t) * h->Nc * h->L), &err, "clear u");
+    if (!rc && h->L > 0) rc = check_device(hipMemset(h->st.phi, 0, sizeof(double) * h->L), &err, "clear phi");
+    h->stage_stride = stage_bytes(h->Nt);
+    if (!rc) rc = check_device(hipHostMalloc((void **)&h->stage, h->stage_stride * h->n_slots, hipHostMallocDefault), &err, "pinned staging");
+    h->slots.assign(h->n_slots, sim_handle::Slot{});
+    for (auto &sl : h->slots) {
+        if (!rc) rc = check_device(hipEventCreateWithFlags(&sl.staged, hipEventDisableTiming), &err, "event");
+        if (!rc) rc = check_device(hipEventCreateWithFlags(&sl.fetched, hipEventDisableTiming), &err, "event");
+    }
+    if (rc) {
+        sim_destroy(h);
+        return rc;
+    }
+    *out = h;
+    return SIM_OK;
+}
+
+int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, sim_handle **out,
+           int32_t n_slots = 0) {
     g_create_error.clear();
     if (!out) return g_create_error = "out is NULL", SIM_EINVAL;
     *out = nullptr;
@@ -534,7 +614,8 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
     if (opts.launch != SIM_LAUNCH_KERNELS && opts.launch != SIM_LAUNCH_PERSISTENT)
         return g_create_error = "unknown launch mode", SIM_EINVAL;
     Packed pk;
-    int rc = build_packed(ps, n, opts.events_mode, &pk, &g_create_error);
+    if (n_slots > 0 && opts.events_mode != SIM_EVENTS_LEVELS) return g_create_error = "slot handles run event levels", SIM_EINVAL;
+    int rc = build_packed(ps, n, opts.events_mode, &pk, &g_create_error, n_slots);
     if (rc != SIM_OK) return rc;
     const sim_problem *p = ps[0];
 
@@ -543,12 +624,14 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
     h->Nc = pk.Nc;
     h->Nt = pk.Nt;
     h->R = pk.R;
+    h->RL = pk.RL;
+    h->n_slots = pk.n_slots;
     h->D = pk.D;
     h->n_record = pk.n_record;
     h->n_inst = pk.n_inst;
     h->layout = pk.layout;
     h->Np = pk.Np;
-    h->L = pk.Np * pk.R;
+    h->L = pk.Np * pk.RL;
     h->n_nodes = pk.n_nodes;
     h->stream = (hipStream_t)opts.stream;
     h->launch = opts.launch;
@@ -620,6 +703,7 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
     s.L = h->L;
     s.Np = (int32_t)h->Np;
     s.R = h->R;
+    s.RL = h->RL;
     s.n_days = h->D;
     s.n_inst = h->n_inst;
     s.n_nodes = (int32_t)h->n_nodes;
@@ -639,6 +723,7 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
     s.snap_u = at<int32_t>(h->ws, l.snap_u);
     s.snap_v = at<double>(h->ws, l.snap_v);
     s.rec_slot = at<int32_t>(h->ws, l.rec_slot);
+    s.slots = h->n_slots ? at<SlotInfo>(h->ws, l.slots) : nullptr;
     DevEvents &ev = h->ev;
     ev.g = at<int32_t>(h->ws, l.ev_g);
     ev.gm = at<int32_t>(h->ws, l.ev_gm);
@@ -670,7 +755,6 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
         {(void *)s.beta, pk.beta.data(), sizeof(double) * S * 4},
         {(void *)s.repid, pk.repid.data(), sizeof(uint32_t) * S},
         {(void *)s.shift, shift.data(), sizeof(int32_t) * shift.size()},
-        {(void *)s.status, &ok, sizeof ok},
         {(void *)ev.g, pk.eg.data(), sizeof(int32_t) * E},
         {(void *)ev.gm, pk.egm.data(), sizeof(int32_t) * E},
         {(void *)ev.node, pk.enode.data(), sizeof(int32_t) * E},
@@ -690,17 +774,20 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
         }
     }
     rc = check_device(hipMemset(at<char>(h->ws, l.prevalence), 0, l.rec_slot - l.prevalence), &err, "clear records");
+    for (int32_t j = 0; !rc && j < std::max(h->n_slots, 1); ++j)
+        rc = check_device(hipMemcpy(s.status + j, &ok, sizeof ok, hipMemcpyHostToDevice), &err, "upload status");
     if (rc) {
         sim_destroy(h);
         return rc;
     }
+    if (h->n_slots > 0) return create_slots(h, ps[0], out);
     // initial state: every replicate of an instance starts from its (u0, v0); padding holds zeros
     std::vector<int32_t> u((size_t)h->Nc * h->L, 0);
     std::vector<double> v(h->L, 0.0);
     for (int32_t k = 0; k < n; ++k)
         for (int64_t i = 0; i < ps[k]->n_nodes; ++i)
             for (int r = 0; r < h->R; ++r) {
-                const int64_t lane = (int64_t)h->lane_of[pk.inst_off[k] + i] * h->R + r;
+                const int64_t lane = (int64_t)h->lane_of[pk.inst_off[k] + i] * h->RL + r;
                 for (int c = 0; c < h->Nc; ++c) u[(size_t)c * h->L + lane] = ps[k]->u0[i * h->Nc + c];
                 v[lane] = ps[k]->v0[i];
             }
@@ -757,6 +844,7 @@ int sim_create_batch(const sim_problem *const *problems, int32_t n_problems, con
 int sim_run(sim_handle *h, int32_t n_days) {
     if (!h) return SIM_EINVAL;
     h->err.clear();
+    if (h->n_slots) return h->err = "a slot handle advances with sim_slots_step", SIM_ESTATE;
     if (n_days < 0) return h->err = "n_days < 0", SIM_EINVAL;
     if (n_days == 0) n_days = h->D - h->day;
     if (h->day + n_days > h->D) return h->err = fmt("run of %d days from day %d passes the horizon %d", n_days, h->day, h->D), SIM_ESTATE;
@@ -809,6 +897,7 @@ int sim_sync(sim_handle *h) {
     if (!h) return SIM_EINVAL;
     int rc = check_device(hipStreamSynchronize(h->stream), &h->err, "synchronize");
     if (rc) return rc;
+    if (h->n_slots) return SIM_OK;  // errors are reported per slot by sim_slot_query
     unsigned long long st = 0;
     rc = check_device(hipMemcpy(&st, h->st.status, sizeof st, hipMemcpyDeviceToHost), &h->err, "status");
     if (rc) return rc;
@@ -832,6 +921,7 @@ int sim_sync(sim_handle *h) {
 
 int sim_trajectory(sim_handle *h, sim_output *out) {
     if (!h || !out) return SIM_EINVAL;
+    if (h->n_slots) return h->err = "a slot handle returns results with sim_slot_fetch", SIM_ESTATE;
     int rc = sim_sync(h);
     if (rc) return rc;
     const size_t DS = (size_t)h->D * h->n_inst * h->R;
@@ -856,6 +946,7 @@ int sim_trajectory(sim_handle *h, sim_output *out) {
 
 int sim_get_state(sim_handle *h, int32_t *u, double *v, int32_t *day) {
     if (!h) return SIM_EINVAL;
+    if (h->n_slots) return h->err = "a slot handle returns state with sim_slot_state", SIM_ESTATE;
     int rc = sim_sync(h);
     if (rc) return rc;
     if (day) *day = h->day;
@@ -867,7 +958,7 @@ int sim_get_state(sim_handle *h, int32_t *u, double *v, int32_t *day) {
     if (rc) return rc;
     for (int r = 0; r < h->R; ++r)
         for (int64_t i = 0; i < h->n_nodes; ++i) {
-            const int64_t lane = (int64_t)h->lane_of[i] * h->R + r;
+            const int64_t lane = (int64_t)h->lane_of[i] * h->RL + r;
             if (u)
                 for (int c = 0; c < h->Nc; ++c) u[((size_t)r * h->n_nodes + i) * h->Nc + c] = du[(size_t)c * h->L + lane];
             if (v) v[(size_t)r * h->n_nodes + i] = dv[lane];
@@ -878,6 +969,7 @@ int sim_get_state(sim_handle *h, int32_t *u, double *v, int32_t *day) {
 int sim_set_state(sim_handle *h, const int32_t *u, const double *v, int32_t day) {
     if (!h || !u || !v) return SIM_EINVAL;
     h->err.clear();
+    if (h->n_slots) return h->err = "a slot handle takes state with sim_slot_start", SIM_ESTATE;
     if (day < 0 || day > h->D) return h->err = "day out of range", SIM_ESTATE;
     int rc = check_device(hipStreamSynchronize(h->stream), &h->err, "synchronize");
     if (rc) return rc;
@@ -885,7 +977,7 @@ int sim_set_state(sim_handle *h, const int32_t *u, const double *v, int32_t day)
     std::vector<double> dv(h->L, 0.0);
     for (int r = 0; r < h->R; ++r)
         for (int64_t i = 0; i < h->n_nodes; ++i) {
-            const int64_t lane = (int64_t)h->lane_of[i] * h->R + r;
+            const int64_t lane = (int64_t)h->lane_of[i] * h->RL + r;
             for (int c = 0; c < h->Nc; ++c) {
                 const int32_t x = u[((size_t)r * h->n_nodes + i) * h->Nc + c];
                 if (x < 0) return h->err = "negative count in state", SIM_EINVAL;
@@ -942,8 +1034,234 @@ void sim_destroy(sim_handle *h) {
         (void)hipEventDestroy(m.b);
     }
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : h->in_flight) (void)hipEventDestroy(e);
+    for (auto &sl : h->slots) {
+        if (sl.staged) (void)hipEventDestroy(sl.staged);
+        if (sl.fetched) (void)hipEventDestroy(sl.fetched);
+    }
+    if (h->stage) (void)hipHostFree(h->stage);
     if (h->own_ws && h->ws) (void)hipFree(h->ws);
     delete h;
+}
+
+size_t sim_slots_workspace_bytes(const sim_problem *network, int32_t n_slots) {
+    std::string err;
+    Packed pk;
+    if (n_slots < 1 || build_packed(&network, 1, SIM_EVENTS_LEVELS, &pk, &err, n_slots) != SIM_OK) return 0;
+    return layout_of(pk, network).total;
+}
+
+int sim_slots_create(const sim_problem *network, int32_t n_slots, const sim_device_opts *opts, sim_handle **out) {
+    if (n_slots < 1) {
+        g_create_error = "n_slots must be >= 1";
+        if (out) *out = nullptr;
+        return SIM_EINVAL;
+    }
+    return create(&network, 1, opts, out, n_slots);
+}
+
+int sim_slot_start(sim_handle *h, int32_t slot, int32_t n_rep, int32_t horizon, const double *coef,
+                   const double *alpha, const double *beta, const uint32_t *replicate_id) {
+    if (!h) return SIM_EINVAL;
+    h->err.clear();
+    if (!h->n_slots) return h->err = "not a slot handle", SIM_ESTATE;
+    if (slot < 0 || slot >= h->n_slots) return h->err = fmt("slot %d out of range", slot), SIM_EINVAL;
+    sim_handle::Slot &sl = h->slots[slot];
+    if (sl.state == SLOT_RUNNING) return h->err = fmt("slot %d is running", slot), SIM_ESTATE;
+    if (n_rep < 1 || n_rep > 64) return h->err = "n_rep must be in [1, 64]", SIM_EINVAL;
+    if (horizon < 1 || horizon > h->D) return h->err = fmt("horizon must be in [1, %d]", h->D), SIM_EINVAL;
+    if (!coef || !alpha || !beta) return h->err = "a parameter array is NULL", SIM_EINVAL;
+    if (int rc = check_params(h->Nt, n_rep, coef, alpha, beta, &h->err)) return rc;
+    // the staging of this slot is reused once its previous upload has run
+    int rc = check_device(hipEventSynchronize(sl.staged), &h->err, "staging");
+    if (rc) return rc;
+    char *st = h->stage + (size_t)slot * h->stage_stride;
+    double *sc = reinterpret_cast<double *>(st), *sa = sc + 64 * h->Nt, *sb = sa + 64;
+    uint32_t *sr = reinterpret_cast<uint32_t *>(sb + 64 * 4);
+    std::memcpy(sc, coef, sizeof(double) * n_rep * h->Nt);
+    std::memcpy(sa, alpha, sizeof(double) * n_rep);
+    std::memcpy(sb, beta, sizeof(double) * n_rep * 4);
+    for (int32_t r = 0; r < n_rep; ++r) sr[r] = replicate_id ? replicate_id[r] : (uint32_t)r;
+    const int64_t set0 = (int64_t)slot * 64;
+    DevState &s = h->st;
+    struct Up {
+        void *dst;
+        const void *src;
+        size_t bytes;
+    } ups[] = {
+        {(void *)(s.coef + set0 * h->Nt), sc, sizeof(double) * n_rep * h->Nt},
+        {(void *)(s.alpha + set0), sa, sizeof(double) * n_rep},
+        {(void *)(s.beta + set0 * 4), sb, sizeof(double) * n_rep * 4},
+        {(void *)(s.repid + set0), sr, sizeof(uint32_t) * n_rep},
+    };
+    for (const Up &up : ups) {
+        rc = check_device(hipMemcpyAsync(up.dst, up.src, up.bytes, hipMemcpyHostToDevice, h->stream), &h->err, "upload parameters");
+        if (rc) return rc;
+    }
+    rc = check_device(hipEventRecord(sl.staged, h->stream), &h->err, "event");
+    if (rc) return rc;
+    const SlotInfo info{h->step, n_rep, horizon, 0};
+    rc = check_device((hipError_t)launch_slot_init(s, h->Nc, at<int32_t>(h->ws, h->lay.u0), at<double>(h->ws, h->lay.v0),
+                                                   slot, info, h->stream), &h->err, "slot start");
+    if (rc) return rc;
+    sl.state = SLOT_RUNNING;
+    sl.t0 = h->step;
+    sl.n_rep = n_rep;
+    sl.horizon = horizon;
+    return SIM_OK;
+}
+
+int sim_slots_step(sim_handle *h, int32_t *finished, int32_t *n_finished) {
+    if (!h) return SIM_EINVAL;
+    h->err.clear();
+    if (!h->n_slots) return h->err = "not a slot handle", SIM_ESTATE;
+    if (n_finished) *n_finished = 0;
+    const int32_t T = h->step;
+    // the levels of every running slot's day
+    int32_t k_max = 0;
+    bool any = false;
+    for (const auto &sl : h->slots) {
+        if (sl.state != SLOT_RUNNING) continue;
+        any = true;
+        const int32_t d = T - sl.t0;
+        if (d < sl.horizon) k_max = std::max(k_max, h->lvl_ptr[d + 1] - h->lvl_ptr[d]);
+    }
+    if (!any) return SIM_OK;
+    std::vector<int64_t> size(k_max, 0);  // largest (event, lane) count of level k over the slots
+    for (const auto &sl : h->slots) {
+        if (sl.state != SLOT_RUNNING) continue;
+        const int32_t d = T - sl.t0;
+        if (d >= sl.horizon) continue;
+        for (int32_t k = 0; k < h->lvl_ptr[d + 1] - h->lvl_ptr[d]; ++k) {
+            const int32_t lv = h->lvl_ptr[d] + k;
+            size[k] = std::max(size[k], (h->lvl_off[lv + 1] - h->lvl_off[lv]) * 64);
+        }
+    }
+    hipError_t e = timed(h, SIM_K_DAY, [&] { return launch_day(h->model, h->st, T, 1, 1, LAYOUT_TILE, h->stream); });
+    if (e != hipSuccess) return h->err = fmt("day kernel: %s", hipGetErrorString(e)), SIM_EDEVICE;
+    // big levels get a launch of their own; runs of small ones one workgroup per slot
+    int32_t k = 0;
+    while (k < k_max) {
+        int32_t stop = k + 1;
+        if (size[k] <= kSlotSmallLevel)
+            while (stop < k_max && size[stop] <= kSlotSmallLevel) ++stop;
+        const int32_t a = k;
+        e = timed(h, SIM_K_EVENTS, [&] {
+            return launch_slot_events(h->model, h->st, h->ev, T, a, stop, size[a], h->stream);
+        });
+        if (e != hipSuccess) return h->err = fmt("event kernel: %s", hipGetErrorString(e)), SIM_EDEVICE;
+        k = stop;
+    }
+    hipEvent_t done = take_event(h);
+    if (!done) return h->err = "event", SIM_EDEVICE;
+    int rc = check_device(hipEventRecord(done, h->stream), &h->err, "event");
+    if (rc) return rc;
+    h->in_flight.push_back(done);
+    h->step = T + 1;
+    int32_t nf = 0;
+    for (int32_t j = 0; j < h->n_slots; ++j) {
+        auto &sl = h->slots[j];
+        if (sl.state == SLOT_RUNNING && T - sl.t0 == sl.horizon) {
+            sl.state = SLOT_DONE;
+            if (finished) finished[nf] = j;
+            ++nf;
+        }
+    }
+    if (n_finished) *n_finished = nf;
+    return SIM_OK;
+}
+
+int32_t sim_slots_in_flight(sim_handle *h) {
+    if (!h || !h->n_slots) return -1;
+    while (!h->in_flight.empty() && hipEventQuery(h->in_flight.front()) == hipSuccess) {
+        h->ev_pool.push_back(h->in_flight.front());
+        h->in_flight.pop_front();
+    }
+    return (int32_t)h->in_flight.size();
+}
+
+int sim_slot_fetch(sim_handle *h, int32_t slot, int32_t *prevalence, int64_t *transitions, int64_t *totals) {
+    if (!h) return SIM_EINVAL;
+    h->err.clear();
+    if (!h->n_slots) return h->err = "not a slot handle", SIM_ESTATE;
+    if (slot < 0 || slot >= h->n_slots) return h->err = fmt("slot %d out of range", slot), SIM_EINVAL;
+    sim_handle::Slot &sl = h->slots[slot];
+    if (sl.state != SLOT_DONE) return h->err = fmt("slot %d has no finished run to fetch", slot), SIM_ESTATE;
+    if (sl.fetch_pending) return h->err = fmt("slot %d: the previous fetch has not been collected", slot), SIM_ESTATE;
+    const size_t S = (size_t)h->RL, n = (size_t)sl.n_rep, H = (size_t)sl.horizon, c0 = (size_t)slot * 64, Nc = h->Nc;
+    const DevState &s = h->st;
+    hipError_t e = hipSuccess;
+    if (prevalence)
+        e = hipMemcpy2DAsync(prevalence, n * sizeof(int32_t), s.prevalence + c0, S * sizeof(int32_t), n * sizeof(int32_t), H,
+                             hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess && transitions)
+        e = hipMemcpy2DAsync(transitions, n * sizeof(int64_t), s.transitions + c0, S * sizeof(int64_t), n * sizeof(int64_t), H,
+                             hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess && totals)
+        e = hipMemcpy2DAsync(totals, n * Nc * sizeof(int64_t), s.totals + c0 * Nc, S * Nc * sizeof(int64_t),
+                             n * Nc * sizeof(int64_t), H, hipMemcpyDeviceToHost, h->stream);
+    unsigned long long *word = error_word(h, slot);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(word, s.status + slot, sizeof *word, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipEventRecord(sl.fetched, h->stream);
+    if (e != hipSuccess) return check_device(e, &h->err, "fetch");
+    sl.state = SLOT_FREE;
+    sl.fetch_pending = true;
+    return SIM_OK;
+}
+
+int sim_slot_query(sim_handle *h, int32_t slot) {
+    if (!h) return SIM_EINVAL;
+    if (!h->n_slots) return h->err = "not a slot handle", SIM_ESTATE;
+    if (slot < 0 || slot >= h->n_slots) return h->err = fmt("slot %d out of range", slot), SIM_EINVAL;
+    sim_handle::Slot &sl = h->slots[slot];
+    if (!sl.fetch_pending) return h->err = fmt("slot %d has no fetch to collect", slot), SIM_ESTATE;
+    const hipError_t q = hipEventQuery(sl.fetched);
+    if (q == hipErrorNotReady) return 1;
+    if (q != hipSuccess) return check_device(q, &h->err, "query");
+    sl.fetch_pending = false;
+    const unsigned long long st = *error_word(h, slot);
+    if (st == STATUS_OK) return SIM_OK;
+    const long long rep = (long long)((st & 0xffffffffull) % 64);
+    if ((st >> 32) == STATUS_LIMIT_TAG) {
+        h->err = fmt("slot %d: a node exceeded %d SSA transitions in one day (replicate %lld)", slot, SIM_MAX_FIRED, rep);
+        return SIM_ELIMIT;
+    }
+    const int64_t gm = (int64_t)(st >> 32);
+    const int32_t day = gm < (int64_t)h->ev_day.size() ? h->ev_day[gm] : -1;
+    h->err = fmt("slot %d: infeasible event %lld (replicate %lld) on day %d: it asks for more individuals than the "
+                 "selected compartments hold", slot, (long long)gm, rep, day);
+    return SIM_EINFEASIBLE;
+}
+
+int sim_slot_state(sim_handle *h, int32_t slot, int32_t *u, double *v) {
+    if (!h) return SIM_EINVAL;
+    h->err.clear();
+    if (!h->n_slots) return h->err = "not a slot handle", SIM_ESTATE;
+    if (slot < 0 || slot >= h->n_slots) return h->err = fmt("slot %d out of range", slot), SIM_EINVAL;
+    const sim_handle::Slot &sl = h->slots[slot];
+    if (sl.n_rep == 0) return h->err = fmt("slot %d never started", slot), SIM_ESTATE;
+    int rc = check_device(hipStreamSynchronize(h->stream), &h->err, "synchronize");
+    if (rc) return rc;
+    const size_t n = (size_t)sl.n_rep, Np = (size_t)h->Np, c0 = (size_t)slot * 64;
+    std::vector<int32_t> du((size_t)h->Nc * Np * n);
+    std::vector<double> dv(Np * n);
+    for (int c = 0; c < h->Nc && !rc; ++c)
+        rc = check_device(hipMemcpy2D(du.data() + (size_t)c * Np * n, n * sizeof(int32_t), h->st.u + (size_t)c * h->L + c0,
+                                      (size_t)h->RL * sizeof(int32_t), n * sizeof(int32_t), Np, hipMemcpyDeviceToHost),
+                          &h->err, "download u");
+    if (!rc)
+        rc = check_device(hipMemcpy2D(dv.data(), n * sizeof(double), h->st.phi + c0, (size_t)h->RL * sizeof(double),
+                                      n * sizeof(double), Np, hipMemcpyDeviceToHost), &h->err, "download v");
+    if (rc) return rc;
+    for (size_t r = 0; r < n; ++r)
+        for (int64_t i = 0; i < h->n_nodes; ++i) {
+            const size_t pos = (size_t)h->lane_of[i];
+            if (u)
+                for (int c = 0; c < h->Nc; ++c) u[(r * h->n_nodes + i) * h->Nc + c] = du[((size_t)c * Np + pos) * n + r];
+            if (v) v[r * h->n_nodes + i] = dv[pos * n + r];
+        }
+    return SIM_OK;
 }
 
 const char *sim_last_error(const sim_handle *h) {

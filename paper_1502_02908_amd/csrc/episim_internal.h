@@ -2,7 +2,7 @@
 // kernels (episim_device.hip) of the library. Not part of the public ABI.
 //
 // Device data layout (one handle = one network, R replicate trajectories):
-//   lane l = pos * R + r (replicate fastest), L = Nn * R lanes, where pos is
+//   lane l = pos * RL + r (replicate fastest), L = Np * RL lanes, where pos is
 //   the node's position: nodes are reordered so that the largest herds (the
 //   longest SSA chains) sit in different wavefronts, largest first;
 //   node_id[pos] gives the caller's numbering (used for the random streams)
@@ -41,14 +41,24 @@ struct Model {
     int32_t S[MAXC][MAXT];      // S[c][k]
 };
 
+// One slot of a slot handle: the handle step at which the slot's day 0 runs
+// (-1: never started), its replicate count (lanes 64 slot .. 64 slot + n_rep - 1)
+// and its horizon in days.
+struct SlotInfo {
+    int32_t t0, n_rep, horizon, pad;
+};
+
 // A handle holds n_inst instances (networks) of one model, each run with the
 // same number R of replicates; "set" = inst * R + r indexes everything that
-// belongs to one trajectory (parameters, replicate id, records).
+// belongs to one trajectory (parameters, replicate id, records). A slot
+// handle holds one network and RL / 64 slots with R = RL sets; each slot runs
+// its own request at its own day.
 struct DevState {
     int32_t *u;                 // [nc][L]
     double *phi;                // [L]
-    int64_t L;                  // Np * R, Np = positions (nodes of all instances plus padding)
-    int32_t Np, R;
+    int64_t L;                  // Np * RL, Np = positions (nodes of all instances plus padding)
+    int32_t Np, R;              // R replicates per instance
+    int32_t RL;                 // lane stride per position: R, or R rounded up to 64 (lanes r >= R are idle)
     int32_t n_days;
     int32_t n_inst;
     int32_t n_nodes;            // nodes of all instances (no padding), for the snapshot layout
@@ -61,7 +71,8 @@ struct DevState {
     const double *beta;         // [sets][4]
     const uint32_t *repid;      // [sets] second Philox key word
     const int32_t *shift;       // [n_shift_ids][MAXC] compartment offsets
-    unsigned long long *status; // first infeasible event, or STATUS_OK
+    unsigned long long *status; // first infeasible event, or STATUS_OK ([RL / 64] in a slot handle)
+    SlotInfo *slots;            // [RL / 64] slot table of a slot handle, null otherwise
     // daily records
     int32_t *prevalence;        // [D][sets]
     int64_t *transitions;       // [D][sets]
@@ -82,11 +93,11 @@ struct DevEvents {
     const int32_t *lvl_ptr;     // [D+1]: levels of day d are lvl_ptr[d] .. lvl_ptr[d+1]-1
 };
 
-// Layouts of the day phase: one lane per (node, replicate) with workgroup
-// sums (R == 1), a tile of kTileNodes nodes x 64 replicates per workgroup
-// (R a multiple of 64), or one lane per (node, replicate) with per-lane sums.
+// Layouts of the day phase: one lane per node with workgroup sums (R == 1),
+// or tiles of kTileNodes nodes x 64 replicate lanes per workgroup (R > 1,
+// lane stride RL a multiple of 64).
 constexpr int kTileNodes = 128;
-enum { LAYOUT_LANES = 0, LAYOUT_TILE = 1, LAYOUT_LANES_ATOMIC = 2 };
+enum { LAYOUT_LANES = 0, LAYOUT_TILE = 1 };
 
 // Host-side launchers (episim_device.hip). Each returns a hipError_t as int.
 int launch_day(const Model &m, const DevState &s, int32_t d, int prologue, int ssa, int layout,
@@ -98,6 +109,10 @@ int launch_event_levels(const Model &m, const DevState &s, const DevEvents &ev, 
 // levels of at most this many (event, replicate) pairs are grouped into one
 // single-workgroup launch
 constexpr int64_t kSmallLevel = 512;
+int launch_slot_events(const Model &m, const DevState &s, const DevEvents &ev, int32_t step, int32_t k,
+                       int32_t k_end, int64_t max_count, void *stream);
+int launch_slot_init(const DevState &s, int32_t nc, const int32_t *u0, const double *v0, int32_t slot,
+                     const SlotInfo &info, void *stream);
 int launch_persistent(const Model &m, const DevState &s, const DevEvents &ev, int32_t d_begin,
                       int32_t d_end, int layout, void *stream, char *why, int why_len);
 

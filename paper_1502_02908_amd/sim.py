@@ -73,6 +73,15 @@ SIGNATURES = {
                                    C.POINTER(C.c_void_p)]),
     "sim_workspace_bytes_batch": (C.c_size_t, [C.POINTER(C.POINTER(sim_problem)), C.c_int32,
                                                C.POINTER(sim_device_opts)]),
+    "sim_slots_workspace_bytes": (C.c_size_t, [C.POINTER(sim_problem), C.c_int32]),
+    "sim_slots_create": (C.c_int, [C.POINTER(sim_problem), C.c_int32, C.POINTER(sim_device_opts),
+                                   C.POINTER(C.c_void_p)]),
+    "sim_slot_start": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, _f64p, _f64p, _f64p, _u32p]),
+    "sim_slots_step": (C.c_int, [C.c_void_p, _i32p, _i32p]),
+    "sim_slots_in_flight": (C.c_int32, [C.c_void_p]),
+    "sim_slot_fetch": (C.c_int, [C.c_void_p, C.c_int32, _i32p, _i64p, _i64p]),
+    "sim_slot_query": (C.c_int, [C.c_void_p, C.c_int32]),
+    "sim_slot_state": (C.c_int, [C.c_void_p, C.c_int32, _i32p, _f64p]),
 }
 KERNEL_CLASSES = ("day", "events", "close", "persist")
 
@@ -248,6 +257,127 @@ class Simulator:
             lib().sim_destroy(self._h)
             self._h = C.c_void_p()
         self._ws = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ptr(x, t):
+    """Pointer to a numpy array or a torch CPU tensor (None -> NULL)."""
+    if x is None:
+        return None
+    if hasattr(x, "data_ptr"):
+        return C.cast(C.c_void_p(x.data_ptr()), t)
+    return x.ctypes.data_as(t)
+
+
+class SlotHandle:
+    """One resident network with n_slots slots of up to 64 replicates; each
+    slot runs its own request from its own day 0 and one step() advances every
+    running slot by a day in shared launches (include/episim.h, slot handles)."""
+
+    def __init__(self, network, n_slots, *, stream=None, torch_workspace=True, device=0):
+        self.p = network
+        self.n_slots, self.Nc, self.Nt, self.D = int(n_slots), network.n_comp, network.n_trans, network.n_days
+        self.Nn = network.n_nodes
+        self._h = C.c_void_p()
+        self._ws = None
+        self._keep = {}
+        torch = _torch_cuda()
+        st, keep = _marshal(network)
+        opts = sim_device_opts()
+        if torch is not None:
+            torch.cuda.set_device(device)
+            if stream is None:
+                stream = torch.cuda.current_stream().cuda_stream
+            if torch_workspace:
+                nbytes = int(lib().sim_slots_workspace_bytes(C.byref(st), self.n_slots))
+                if nbytes == 0:
+                    raise SimError(SIM_EINVAL, "network rejected (sim_slots_workspace_bytes returned 0)")
+                self._ws = torch.empty(nbytes, dtype=torch.uint8, device=f"cuda:{device}")
+                opts.workspace = self._ws.data_ptr()
+                opts.workspace_bytes = nbytes
+        opts.stream = stream if stream is not None else None
+        rc = lib().sim_slots_create(C.byref(st), self.n_slots, C.byref(opts), C.byref(self._h))
+        del keep
+        if rc != SIM_OK:
+            raise SimError(rc, lib().sim_last_error(None).decode())
+
+    @staticmethod
+    def workspace_bytes(network, n_slots):
+        st, keep = _marshal(network)
+        return int(lib().sim_slots_workspace_bytes(C.byref(st), int(n_slots)))
+
+    def _check(self, rc):
+        if rc != SIM_OK:
+            raise SimError(rc, lib().sim_last_error(self._h).decode())
+
+    def start(self, slot, horizon, coef, alpha, beta, replicate_id=None):
+        coef = np.ascontiguousarray(coef, np.float64).reshape(-1, self.Nt)
+        n = coef.shape[0]
+        alpha = np.ascontiguousarray(alpha, np.float64).reshape(n)
+        beta = np.ascontiguousarray(beta, np.float64).reshape(n, 4)
+        rid = None if replicate_id is None else np.ascontiguousarray(replicate_id, np.uint32).reshape(n)
+        self._check(lib().sim_slot_start(self._h, int(slot), n, int(horizon), _p(coef, _f64p), _p(alpha, _f64p),
+                                         _p(beta, _f64p), None if rid is None else _p(rid, _u32p)))
+
+    def step(self):
+        """Advance every running slot by one day; returns the slots that finished."""
+        fin = np.zeros(self.n_slots, np.int32)
+        nf = C.c_int32()
+        self._check(lib().sim_slots_step(self._h, _p(fin, _i32p), C.byref(nf)))
+        return fin[:nf.value].tolist()
+
+    def in_flight(self):
+        return int(lib().sim_slots_in_flight(self._h))
+
+    def fetch(self, slot, prevalence=None, transitions=None, totals=None):
+        """Enqueue the download of a finished slot's records into the given
+        buffers (numpy arrays or torch CPU tensors; pinned ones keep it
+        asynchronous). They are kept alive until query() collects them."""
+        self._keep[slot] = (prevalence, transitions, totals)
+        self._check(lib().sim_slot_fetch(self._h, int(slot), _ptr(prevalence, _i32p), _ptr(transitions, _i64p),
+                                         _ptr(totals, _i64p)))
+
+    def query(self, slot):
+        """True once the fetch of slot has landed; raises the slot's own error."""
+        rc = lib().sim_slot_query(self._h, int(slot))
+        if rc == 1:
+            return False
+        self._keep.pop(slot, None)
+        self._check(rc)
+        return True
+
+    def state(self, slot, n_rep):
+        u = np.zeros((n_rep, self.Nn, self.Nc), np.int32)
+        v = np.zeros((n_rep, self.Nn), np.float64)
+        self._check(lib().sim_slot_state(self._h, int(slot), _p(u, _i32p), _p(v, _f64p)))
+        return u, v
+
+    def kernel_times(self, enable):
+        ms = np.zeros(4)
+        n = np.zeros(4, np.int64)
+        self._check(lib().sim_kernel_times(self._h, int(enable), _p(ms, _f64p), _p(n, _i64p)))
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_CLASSES)}
+
+    def sync(self):
+        self._check(lib().sim_sync(self._h))
+
+    def close(self):
+        if self._h:
+            lib().sim_destroy(self._h)
+            self._h = C.c_void_p()
+        self._ws = None
+        self._keep = {}
 
     def __enter__(self):
         return self

@@ -194,3 +194,23 @@ def test_batch_rejects_mixed_models():
     structs = [S._marshal(a), S._marshal(c)]
     arr = (C.POINTER(S.sim_problem) * 2)(*[C.pointer(s) for s, _ in structs])
     assert P.lib().sim_workspace_bytes_batch(arr, 2, None) == 0
+
+
+def test_slot_handle_sizing_and_rejects():
+    net = synth.sise3_network(n_nodes=300, n_days=40, seed=4, age_days=(5, 15))
+    one, four = S.SlotHandle.workspace_bytes(net, 1), S.SlotHandle.workspace_bytes(net, 4)
+    assert 0 < one < four
+    # per slot: 64 lanes of state over the padded positions, records of every day
+    per = (four - one) / 3
+    assert per >= 64 * net.n_nodes * (net.n_comp * 4 + 8) + 64 * net.n_days * (4 + 8 + 8 * net.n_comp)
+    assert S.SlotHandle.workspace_bytes(net, 0) == 0
+    rec = synth.sise3_network(n_nodes=300, n_days=40, seed=4, age_days=(5, 15))
+    rec.record_days = np.array([3], np.int32)
+    assert S.SlotHandle.workspace_bytes(rec, 2) == 0
+    s, keep = S._marshal(rec)
+    h = C.c_void_p()
+    assert P.lib().sim_slots_create(C.byref(s), 2, None, C.byref(h)) == S.SIM_EINVAL
+    assert "snapshots" in P.lib().sim_last_error(None).decode()
+    s, keep = S._marshal(net)
+    assert P.lib().sim_slots_create(C.byref(s), 0, None, C.byref(h)) == S.SIM_EINVAL
+    assert not h.value
