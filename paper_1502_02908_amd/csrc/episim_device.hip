@@ -217,18 +217,11 @@ struct PairRules {
     }
 };
 
-// The single-chain walk for paired classes, written so that the division of
-// attempt k (its waiting time) overlaps the choice and the update it does not
-// depend on: the chosen transition is applied first and undone if the
-// attempt lands past the window end (counts are exact integers in binary64,
-// and the running sums are recomputed with the same operations, so the undo
-// restores the same bits). Every lane holds the same state; draws for
-// attempts kbase.. come from lane i = attempt - kbase. Returns when the chain
-// ends.
+// The single-chain walk for paired classes (defined below).
 template <int NP>
-__device__ __forceinline__ void pairs_walk_uniform(const Model &m, Chain<2 * NP, 2 * NP> &c, uint32_t kbase,
-                                                   uint32_t node, uint32_t day, uint32_t key0, uint32_t key1,
-                                                   unsigned long long *status, int32_t r);
+__device__ __forceinline__ void pairs_walk_block(const Model &m, Chain<2 * NP, 2 * NP> &c, uint32_t kbase,
+                                                 uint32_t node, uint32_t day, uint32_t key0, uint32_t key1,
+                                                 unsigned long long *status, int32_t r);
 
 // Inversion of eq:sampling2: the first transition with a positive rate whose
 // running sum reaches target. With target > 0 that is the number of running
@@ -289,55 +282,109 @@ __device__ __forceinline__ double lane_f64(double v, int lane) {
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// One chain walked by the whole wavefront, 64 attempts per round, for paired
+// classes. Attempt kbase + i belongs to lane i; its draws do not depend on the
+// state, but the transition it picks (eq:sampling2) and its waiting time
+// (eq:sampling) depend on the state the attempts before it leave. Each lane
+// first assumes the round's starting state, then recomputes its state from the
+// transitions the lanes below it picked (a ballot per transition and a count of
+// the set bits below the lane) and its own pick from that state, until no pick
+// changes. Lane i is settled after i + 1 passes whatever the guesses were, so
+// the result is the one attempt-by-attempt walk gives; with many individuals
+// the rates barely move and one or two passes settle every lane. The waiting
+// times then follow in parallel, and only the clock is summed attempt by
+// attempt in order (binary64 addition rounds each partial sum). The attempts
+// whose sum stays below the window end fire; they form a prefix of the lanes
+// because the clock never decreases. Every lane holds the same chain state.
+// Counts are exact integers in binary64 and the rates, running sums, targets
+// and waiting times are the same functions of the same state as in a walk
+// attempt by attempt, so the bits agree.
 template <int NP>
-__device__ __forceinline__ void pairs_walk_uniform(const Model &m, Chain<2 * NP, 2 * NP> &c, uint32_t kbase,
-                                                   uint32_t node, uint32_t day, uint32_t key0, uint32_t key1,
-                                                   unsigned long long *status, int32_t r) {
+__device__ __forceinline__ void pairs_walk_block(const Model &m, Chain<2 * NP, 2 * NP> &c, uint32_t kbase,
+                                                 uint32_t node, uint32_t day, uint32_t key0, uint32_t key1,
+                                                 unsigned long long *status, int32_t r) {
     constexpr int NT = 2 * NP;
     const uint32_t lane = threadIdx.x & 63u;
+    const unsigned long long below = (1ull << lane) - 1ull;
     for (;;) {
         const Word4 o = philox4x32_10(Word4{kbase + lane, node, day, 0u}, key0, key1);
-        const double e_mine = minus_log(unit_open(o.a, o.b));
-        const double u_mine = unit_open(o.c, o.d);
-        for (int i = 0; i < 64; ++i) {
-            const double E = lane_f64(e_mine, i);
-            const double target = lane_f64(u_mine, i) * c.lam;
-            const double tau = E / c.lam;  // waiting time of this attempt
-            // target > 0 whenever the attempt can fire: target = 0 needs
-            // lambda < 2^-1021, and then tau = E/lambda > 1 since E >= 2^-53,
-            // so such an attempt is undone below before it counts.
-            int j = 0;
+        const double E = minus_log(unit_open(o.a, o.b));
+        const double U = unit_open(o.c, o.d);
+        // guess: every attempt sees the round's starting state
+        int j = 0;
+        {
+            const double target = U * c.lam;
 #pragma unroll
             for (int k = 0; k < NT; ++k) j += c.cum[k] < target ? 1 : 0;
-            j = __builtin_amdgcn_readfirstlane(j);
-            const int p = j >> 1;
-            const double dS = (j & 1) ? 1.0 : -1.0;  // infection takes an S, recovery returns one
+        }
+        double lam = c.lam;
+        for (int pass = 0; pass < 64; ++pass) {
+            double x[NT];
 #pragma unroll
             for (int q = 0; q < NP; ++q) {
-                const double dq = q == p ? dS : 0.0;
-                c.xd[2 * q] = c.xd[2 * q] + dq;
-                c.xd[2 * q + 1] = c.xd[2 * q + 1] - dq;
+                const int inf = __popcll(__ballot(j == 2 * q) & below);
+                const int rec = __popcll(__ballot(j == 2 * q + 1) & below);
+                const double dS = (double)(rec - inf);
+                x[2 * q] = c.xd[2 * q] + dS;
+                x[2 * q + 1] = c.xd[2 * q + 1] - dS;
             }
-            pairs_rates_full<NP>(c);
-            const double t1 = c.clock + tau;
-            if (!(t1 < 1.0)) {  // past the window: undo the update
+            double cum[NT];
+            double l = 0.0;
 #pragma unroll
-                for (int q = 0; q < NP; ++q) {
-                    const double dq = q == p ? dS : 0.0;
-                    c.xd[2 * q] = c.xd[2 * q] - dq;
-                    c.xd[2 * q + 1] = c.xd[2 * q + 1] + dq;
-                }
-                pairs_rates_full<NP>(c);
-                return;
+            for (int k = 0; k < NT; ++k) {
+                l = l + c.cphi[k] * x[k];
+                cum[k] = l;
             }
-            c.clock = t1;
-            c.fired = c.fired + 1;
-            if (c.fired >= SIM_MAX_FIRED) {
-                if (lane == 0) atomicMin(status, (STATUS_LIMIT_TAG << 32) | (unsigned long long)(uint32_t)r);
-                return;
-            }
-            if (!(c.lam > 0.0)) return;
+            // target > 0 whenever the attempt can fire: target = 0 needs
+            // lambda < 2^-1021, and then tau = E/lambda > 1 since E >= 2^-53
+            const double target = U * l;
+            int jn = 0;
+#pragma unroll
+            for (int k = 0; k < NT; ++k) jn += cum[k] < target ? 1 : 0;
+            const bool changed = __ballot(jn != j) != 0ull;
+            j = jn;
+            lam = l;
+            if (!changed) break;
         }
+        const double tau = E / lam;  // lambda = 0: tau = inf, never fires
+        // the clock, attempt by attempt; most rounds end below the window end
+        double t = c.clock;
+#pragma unroll 16
+        for (int i = 0; i < 64; ++i) t = t + lane_f64(tau, i);
+        int A = 64;
+        double clock = t;
+        if (!(t < 1.0)) {
+            double s = c.clock, mine = 0.0;
+#pragma unroll 16
+            for (int i = 0; i < 64; ++i) {
+                s = s + lane_f64(tau, i);
+                if ((int)lane == i) mine = s;
+            }
+            A = __popcll(__ballot(mine < 1.0));
+            clock = A > 0 ? lane_f64(mine, A - 1) : c.clock;
+        }
+        bool limit = false;
+        if (c.fired + A >= SIM_MAX_FIRED) {
+            A = SIM_MAX_FIRED - c.fired;
+            limit = true;
+        }
+        const unsigned long long fired = A >= 64 ? ~0ull : ((1ull << A) - 1ull);
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            const int inf = __popcll(__ballot(j == 2 * q) & fired);
+            const int rec = __popcll(__ballot(j == 2 * q + 1) & fired);
+            const double dS = (double)(rec - inf);
+            c.xd[2 * q] = c.xd[2 * q] + dS;
+            c.xd[2 * q + 1] = c.xd[2 * q + 1] - dS;
+        }
+        if (A > 0 && !limit) c.clock = clock;
+        c.fired = c.fired + A;
+        pairs_rates_full<NP>(c);
+        if (limit) {
+            if (lane == 0) atomicMin(status, (STATUS_LIMIT_TAG << 32) | (unsigned long long)(uint32_t)r);
+            return;
+        }
+        if (A < 64 || !(c.lam > 0.0)) return;
         kbase = kbase + 64;
     }
 }
@@ -417,7 +464,7 @@ __device__ __forceinline__ void run_chains(const Model &m, typename Rules::State
             const uint32_t k1 = (uint32_t)__builtin_amdgcn_readlane((int)key1, h);
             const int32_t rh = __builtin_amdgcn_readlane(r, h);
             if constexpr (Rules::kPairs > 0) {
-                pairs_walk_uniform<Rules::kPairs>(m, u, kb, nh, day, k0, k1, status, rh);
+                pairs_walk_block<Rules::kPairs>(m, u, kb, nh, day, k0, k1, status, rh);
             } else {
                 chain_uniform<Rules>(m, u, kb, nh, day, k0, k1, status, rh);
             }
