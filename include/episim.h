@@ -266,14 +266,19 @@ void sim_destroy(sim_handle *h);
 /* Text of the last error of h, or of the calling thread's last sim_create if h is NULL. */
 const char *sim_last_error(const sim_handle *h);
 
-/* Host-only dependency pass, exposed for testing without a GPU: assigns each
- * event its level (1-based) within its day such that any two events of one
- * day that touch a common node, at least one of them drawing individuals
- * there, are in increasing levels in list order, while additions to one
- * node may share a level. level_out[n_events]. Returns SIM_OK or SIM_EINVAL. */
+/* Host-only dependency pass, exposed for testing without a GPU. Groups the
+ * events into tasks and assigns each task a level (1-based) within its day:
+ * a task is one external transfer, or a run of enter / exit / internal
+ * events of one node with no external transfer touching that node between
+ * them in list order; one thread applies a task's events in list order.
+ * Any two events of one day that touch a common node, at least one of them
+ * drawing individuals there, are in one task or in increasing levels in list
+ * order, while additions to one node may share a level. level_out[n_events]
+ * and task_out[n_events] (task numbers in order of their first event; may be
+ * NULL). Returns SIM_OK or SIM_EINVAL. */
 int sim_plan_levels(int64_t n_events, const int32_t *ev_day, const int32_t *ev_kind,
                     const int32_t *ev_node, const int32_t *ev_dest, int32_t n_nodes,
-                    int32_t *level_out);
+                    int32_t *level_out, int32_t *task_out);
 
 #ifdef __cplusplus
 }

@@ -738,6 +738,47 @@ __device__ __forceinline__ int32_t load_l2(const int32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Draw n of the tot individuals in the compartments of mask from x without
+// replacement (Sec. 3.2): draw q picks the individual at a uniform position
+// in [0, remaining) of the selected compartments in ascending order, from the
+// Philox block (q / 2, g, d, 1). Removes them from x and counts them in take.
+template <int NC>
+__device__ __forceinline__ void draw_individuals(int32_t *x, int32_t *take, uint32_t mask, int32_t n, long long tot,
+                                                 uint32_t g, int32_t d, uint32_t key0, uint32_t key1) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) take[c] = 0;
+    Word4 o{0, 0, 0, 0};
+    for (int32_t q = 0; q < n; ++q) {
+        uint64_t bits;
+        if ((q & 1) == 0) {
+            o = philox4x32_10(Word4{(uint32_t)q >> 1, g, (uint32_t)d, 1u}, key0, key1);
+            bits = ((uint64_t)o.b << 32) | o.a;
+        } else {
+            bits = ((uint64_t)o.d << 32) | o.c;
+        }
+        uint64_t pick = __umul64hi(bits, (uint64_t)tot);  // uniform on [0, tot)
+        int chosen = -1;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            if (chosen < 0 && ((mask >> c) & 1u)) {
+                if (pick < (uint64_t)x[c]) {
+                    chosen = c;
+                } else {
+                    pick -= (uint64_t)x[c];
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            if (c == chosen) {
+                x[c] -= 1;
+                take[c] += 1;
+            }
+        }
+        tot -= 1;
+    }
+}
+
 template <int NC>
 __device__ __forceinline__ void event_one(const Model &m, const DevState &s, const DevEvents &ev,
                                           int64_t e, int32_t r, int32_t d, unsigned long long *status) {
@@ -772,40 +813,7 @@ __device__ __forceinline__ void event_one(const Model &m, const DevState &s, con
         return;
     }
     int32_t take[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) take[c] = 0;
-    const uint32_t key0 = s.seed[inst];
-    const uint32_t key1 = s.repid[set];
-    Word4 o{0, 0, 0, 0};
-    for (int32_t q = 0; q < n; ++q) {
-        uint64_t bits;
-        if ((q & 1) == 0) {
-            o = philox4x32_10(Word4{(uint32_t)q >> 1, g, (uint32_t)d, 1u}, key0, key1);
-            bits = ((uint64_t)o.b << 32) | o.a;
-        } else {
-            bits = ((uint64_t)o.d << 32) | o.c;
-        }
-        uint64_t pick = __umul64hi(bits, (uint64_t)tot);  // uniform on [0, tot)
-        int chosen = -1;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            if (chosen < 0 && ((mask >> c) & 1u)) {
-                if (pick < (uint64_t)x[c]) {
-                    chosen = c;
-                } else {
-                    pick -= (uint64_t)x[c];
-                }
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            if (c == chosen) {
-                x[c] -= 1;
-                take[c] += 1;
-            }
-        }
-        tot -= 1;
-    }
+    draw_individuals<NC>(x, take, mask, n, tot, g, d, s.seed[inst], s.repid[set]);
     if (kind == SIM_INTERNAL) {
         int32_t y[NC];
 #pragma unroll
@@ -847,6 +855,73 @@ __device__ __forceinline__ void event_one(const Model &m, const DevState &s, con
     }
 }
 
+// One task (replicate lane r): a single event, or a run of one node's enter /
+// exit / internal events in list order. A run that draws has its node to
+// itself within its level (every other event touching the node is in another
+// level), so its counts stay in registers from the first event to the last;
+// a run of additions only may share the node with other additions and adds
+// atomically, event by event.
+template <int NC>
+__device__ __forceinline__ void event_task(const Model &m, const DevState &s, const DevEvents &ev, int64_t t,
+                                           int32_t r, int32_t d, unsigned long long *status) {
+    const int64_t e0 = ev.task_off[t], e1 = ev.task_off[t + 1];
+    bool draws = false;
+    if (e1 - e0 > 1)
+        for (int64_t e = e0; e < e1; ++e) draws = draws || (int)(ev.meta[e] & kEvKindMask) != SIM_ENTER;
+    if (!draws) {
+        for (int64_t e = e0; e < e1; ++e) event_one<NC>(m, s, ev, e, r, d, status);
+        return;
+    }
+    const int32_t node = ev.node[e0];
+    const int64_t ls = (int64_t)node * s.RL + r;
+    int32_t x[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) x[c] = comp_on<NC>(m, c) ? load_l2(&s.u[(int64_t)c * s.L + ls]) : 0;
+    const int32_t inst = s.inst[node];
+    const int32_t set = inst * s.R + r;
+    const uint32_t key0 = s.seed[inst], key1 = s.repid[set];
+    uint32_t touched = 0;
+    for (int64_t e = e0; e < e1; ++e) {
+        const uint32_t meta = ev.meta[e];
+        const int kind = (int)(meta & kEvKindMask);
+        const uint32_t mask = (meta >> 2) & 0xffu;
+        const int32_t n = ev.n[e];
+        touched |= mask;
+        if (kind == SIM_ENTER) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                if ((mask >> c) & 1u) x[c] += n;
+            continue;
+        }
+        long long tot = 0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if ((mask >> c) & 1u) tot += x[c];
+        if ((long long)n > tot) {
+            atomicMin(status, ((unsigned long long)(uint32_t)ev.gm[e] << 32) | (unsigned long long)(uint32_t)set);
+            break;
+        }
+        int32_t take[NC];
+        draw_individuals<NC>(x, take, mask, n, tot, (uint32_t)ev.g[e], d, key0, key1);
+        if (kind == SIM_INTERNAL) {
+            const int sid = (int)((meta >> 10) & 0x3fu) - 1;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                if (take[c]) {
+                    const int to = sid >= 0 ? c + s.shift[sid * MAXC + c] : c;
+#pragma unroll
+                    for (int cc = 0; cc < NC; ++cc)
+                        if (cc == to) x[cc] += take[c];
+                    touched |= 1u << to;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+        if ((touched >> c) & 1u) s.u[(int64_t)c * s.L + ls] = x[c];
+}
+
 template <int NC>
 __global__ __launch_bounds__(kBlock) void k_events(Model m, DevState s, DevEvents ev, int32_t d,
                                                    int64_t begin, int64_t end) {
@@ -856,7 +931,7 @@ __global__ __launch_bounds__(kBlock) void k_events(Model m, DevState s, DevEvent
     if (t >= count) return;
     const int64_t e = begin + (s.RL == 1 ? t : t / s.RL);
     const int32_t r = s.RL == 1 ? 0 : (int32_t)(t % s.RL);
-    if (r < s.R) event_one<NC>(m, s, ev, e, r, d, s.status);
+    if (r < s.R) event_task<NC>(m, s, ev, e, r, d, s.status);
 }
 
 // A run of small levels [lv_begin, lv_end) of day d in one workgroup, with a
@@ -871,7 +946,7 @@ __global__ __launch_bounds__(kEvBlock) void k_event_levels(Model m, DevState s, 
         for (int64_t t = threadIdx.x; t < count; t += kEvBlock) {
             const int64_t e = begin + (s.RL == 1 ? t : t / s.RL);
             const int32_t r = s.RL == 1 ? 0 : (int32_t)(t % s.RL);
-            if (r < s.R) event_one<NC>(m, s, ev, e, r, d, s.status);
+            if (r < s.R) event_task<NC>(m, s, ev, e, r, d, s.status);
         }
         __syncthreads();
     }
@@ -895,7 +970,7 @@ __global__ __launch_bounds__(kEvBlock) void k_slot_events(Model m, DevState s, D
         const int64_t count = (end - begin) * 64;
         for (int64_t t = (int64_t)blockIdx.x * kEvBlock + threadIdx.x; t < count; t += stride) {
             const int32_t rr = (int32_t)(t & 63);
-            if (rr < si.n_rep) event_one<NC>(m, s, ev, begin + (t >> 6), (int32_t)blockIdx.y * 64 + rr, d, status);
+            if (rr < si.n_rep) event_task<NC>(m, s, ev, begin + (t >> 6), (int32_t)blockIdx.y * 64 + rr, d, status);
         }
         if (k_end > k + 1) __syncthreads();
     }
@@ -983,7 +1058,7 @@ __global__ __launch_bounds__(kBlock) void k_persist(Model m, DevState s, DevEven
                     for (int64_t t = first; t < size; t += stride) {
                         const int64_t e = begin + (s.RL == 1 ? t : t / s.RL);
                         const int32_t r = s.RL == 1 ? 0 : (int32_t)(t % s.RL);
-                        if (r < s.R) event_one<NC>(m, s, ev, e, r, d, s.status);
+                        if (r < s.R) event_task<NC>(m, s, ev, e, r, d, s.status);
                     }
                 }
                 ++lv;
@@ -997,7 +1072,7 @@ __global__ __launch_bounds__(kBlock) void k_persist(Model m, DevState s, DevEven
                         for (int64_t t = threadIdx.x; t < count; t += kBlock) {
                             const int64_t e = begin + (s.RL == 1 ? t : t / s.RL);
                             const int32_t r = s.RL == 1 ? 0 : (int32_t)(t % s.RL);
-                            if (r < s.R) event_one<NC>(m, s, ev, e, r, d, s.status);
+                            if (r < s.R) event_task<NC>(m, s, ev, e, r, d, s.status);
                         }
                         __syncthreads();
                     }

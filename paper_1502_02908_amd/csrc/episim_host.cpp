@@ -7,10 +7,15 @@
 // rules 2(b) and 3(b)), applied at node granularity: within a day, an event
 // that draws individuals from a node must follow every earlier event touching
 // that node, and an event that adds to a node must follow every earlier draw
-// from it; additions to one node commute. Each event gets the smallest level
-// meeting these rules, so one level runs fully in parallel and levels run in
-// order. The levels are computed once per handle and reused by every run and
-// replicate, as the paper reuses its re-arranged lists across runs.
+// from it; additions to one node commute. A run of events that touch one node
+// only (enter, exit, internal transfer), with no external transfer touching
+// that node between them in list order, forms one task: one thread applies it
+// in list order with the counts held in registers, as the paper's private
+// events of a sub-domain run inside its own task (Sec. 3.6). Every task gets
+// the smallest level meeting the rules, so one level runs fully in parallel
+// and levels run in order. Tasks and levels are computed once per handle and
+// reused by every run and replicate, as the paper reuses its re-arranged lists
+// across runs.
 //
 // A handle holds one or more instances (networks) of one model. Instances are
 // packed into one range of node positions, each padded to whole wavefronts /
@@ -49,44 +54,70 @@ std::string fmt(const char *f, ...) {
 
 bool is_sampler(int kind) { return kind == SIM_EXIT || kind == SIM_INTERNAL || kind == SIM_EXTERNAL; }
 
-// Level of every event within its day; events must already be sorted by day.
-// Records the number of levels of each day in day_levels (resized to n_days).
+// Task and level of every event within its day; events must already be
+// sorted by day. Tasks are numbered in order of their first event. Records
+// the number of levels of each day in day_levels (resized to n_days).
 void plan_levels(int64_t n, const int32_t *day, const int32_t *kind, const int32_t *node,
-                 const int32_t *dest, int32_t n_nodes, int32_t *level,
+                 const int32_t *dest, int32_t n_nodes, int32_t *level, int32_t *task,
                  std::vector<int32_t> *day_levels, int32_t n_days) {
-    // last level at which a node was touched at all / drawn from, valid for
-    // the day stored in stamp (so nothing is cleared between days)
-    std::vector<int32_t> stamp(n_nodes, -1), last_any(n_nodes, 0), last_draw(n_nodes, 0);
+    // per node, valid for the day stored in stamp (nothing is cleared between
+    // days): the last level at which it was touched at all / drawn from, and
+    // the task of single-node events still open at it with the values of
+    // those two before the task began
+    std::vector<int32_t> stamp(n_nodes, -1), last_any(n_nodes, 0), last_draw(n_nodes, 0), open(n_nodes, -1),
+        base_any(n_nodes, 0), base_draw(n_nodes, 0);
+    std::vector<char> open_draws(n_nodes, 0);
+    std::vector<int32_t> task_level;
     if (day_levels) day_levels->assign(n_days > 0 ? n_days : 0, 0);
     auto touch = [&](int32_t x, int32_t d) {
         if (stamp[x] != d) {
             stamp[x] = d;
             last_any[x] = 0;
             last_draw[x] = 0;
+            open[x] = -1;
         }
     };
     for (int64_t e = 0; e < n; ++e) {
         const int32_t d = day[e];
-        int32_t L = 1;
         const int32_t src = node[e];
-        const bool draws = is_sampler(kind[e]);
-        // the node an event adds to: ENTER adds at its node, EXTERNAL at dest
-        const int32_t add = kind[e] == SIM_ENTER ? src : (kind[e] == SIM_EXTERNAL ? dest[e] : -1);
-        if (draws) {
-            touch(src, d);
-            L = std::max(L, last_any[src] + 1);
+        touch(src, d);
+        if (kind[e] != SIM_EXTERNAL) {
+            // enter, exit, internal: one node; joins the node's open task
+            const bool draws = is_sampler(kind[e]);
+            int32_t t = open[src];
+            if (t < 0) {
+                t = (int32_t)task_level.size();
+                base_any[src] = last_any[src];
+                base_draw[src] = last_draw[src];
+                task_level.push_back(1 + (draws ? base_any[src] : base_draw[src]));
+                open[src] = t;
+                open_draws[src] = draws;
+            } else if (draws && !open_draws[src]) {
+                // a draw after additions only: the task must now follow every
+                // earlier event at the node (nothing else has used its level)
+                task_level[t] = std::max(task_level[t], 1 + base_any[src]);
+                open_draws[src] = 1;
+            }
+            task[e] = t;
+            last_any[src] = std::max(base_any[src], task_level[t]);
+            last_draw[src] = open_draws[src] ? task_level[t] : base_draw[src];
+            continue;
         }
-        if (add >= 0) {
-            touch(add, d);
-            L = std::max(L, last_draw[add] + 1);
-        }
-        level[e] = L;
-        if (draws) {
-            last_any[src] = std::max(last_any[src], L);
-            last_draw[src] = L;
-        }
-        if (add >= 0) last_any[add] = std::max(last_any[add], L);
-        if (day_levels) (*day_levels)[d] = std::max((*day_levels)[d], L);
+        // external transfer: draws at src, adds at dest; a task of its own
+        const int32_t dst = dest[e];
+        touch(dst, d);
+        open[src] = -1;
+        open[dst] = -1;
+        const int32_t L = std::max(last_any[src] + 1, last_draw[dst] + 1);
+        task[e] = (int32_t)task_level.size();
+        task_level.push_back(L);
+        last_any[src] = std::max(last_any[src], L);
+        last_draw[src] = L;
+        last_any[dst] = std::max(last_any[dst], L);
+    }
+    for (int64_t e = 0; e < n; ++e) {
+        level[e] = task_level[task[e]];
+        if (day_levels) (*day_levels)[day[e]] = std::max((*day_levels)[day[e]], level[e]);
     }
 }
 
@@ -260,15 +291,15 @@ int64_t order_nodes(const sim_problem *p, int layout, std::vector<int32_t> *pos_
 // Device buffer layout of one handle.
 struct Layout {
     size_t u, phi, node_id, inst, inst_off, seed, coef, alpha, beta, repid, shift, status, ev_g, ev_gm, ev_node,
-        ev_dest, ev_n, ev_meta, lvl_off, lvl_ptr, prevalence, transitions, totals, snap_u, snap_v, rec_slot, slots,
+        ev_dest, ev_n, ev_meta, task_off, lvl_off, lvl_ptr, prevalence, transitions, totals, snap_u, snap_v, rec_slot, slots,
         u0, v0, total;
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 Layout layout_for(int64_t Np, int64_t n_nodes, int64_t n_inst, int64_t Nc, int64_t Nt, int64_t R, int64_t RL,
-                  int64_t D, int64_t n_events, int64_t n_shift_ids, int64_t n_levels, int64_t n_record,
-                  int64_t n_slots) {
+                  int64_t D, int64_t n_events, int64_t n_shift_ids, int64_t n_levels, int64_t n_tasks,
+                  int64_t n_record, int64_t n_slots) {
     Layout l{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -295,6 +326,7 @@ Layout layout_for(int64_t Np, int64_t n_nodes, int64_t n_inst, int64_t Nc, int64
     l.ev_dest = take(sizeof(int32_t) * n_events);
     l.ev_n = take(sizeof(int32_t) * n_events);
     l.ev_meta = take(sizeof(uint32_t) * n_events);
+    l.task_off = take(sizeof(int32_t) * (n_tasks + 1));
     l.lvl_off = take(sizeof(int64_t) * (n_levels + 1));
     l.lvl_ptr = take(sizeof(int32_t) * (D + 1));
     l.prevalence = take(sizeof(int32_t) * D * S);
@@ -323,7 +355,9 @@ struct Packed {
     std::vector<int32_t> eg, egm, enode, edest, en, ev_inst, ev_local;
     std::vector<uint32_t> emeta;
     std::vector<int32_t> lvl_ptr;
-    std::vector<int64_t> lvl_off;
+    std::vector<int64_t> lvl_off;   // task offsets of each level
+    std::vector<int32_t> task_off;  // event offsets of each task
+    int64_t n_tasks = 0;
     std::vector<int32_t> rec_slot;
 };
 
@@ -418,21 +452,42 @@ int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, P
                 }
             }
     }
-    std::vector<int32_t> level(E), day_levels;
+    std::vector<int32_t> level(E), task(E), day_levels;
     if (events_mode == SIM_EVENTS_SERIAL) {
         day_levels.assign(pk->D, 0);
-        for (int64_t e = 0; e < E; ++e) level[e] = ++day_levels[mday[e]];
+        for (int64_t e = 0; e < E; ++e) {
+            level[e] = ++day_levels[mday[e]];
+            task[e] = (int32_t)e;
+        }
     } else {
         plan_levels(E, mday.data(), mkind.data(), mnode.data(), mdest.data(), (int32_t)std::max<int64_t>(pk->Np, 1),
-                    level.data(), &day_levels, pk->D);
+                    level.data(), task.data(), &day_levels, pk->D);
     }
     pk->lvl_ptr.assign(pk->D + 1, 0);
     for (int32_t d = 0; d < pk->D; ++d) pk->lvl_ptr[d + 1] = pk->lvl_ptr[d] + day_levels[d];
     pk->n_levels = pk->lvl_ptr[pk->D];
+    // tasks in execution order: by level, then by first event; a task's
+    // events stay together in list order
+    int64_t n_tasks = 0;
+    for (int64_t e = 0; e < E; ++e) n_tasks = std::max<int64_t>(n_tasks, (int64_t)task[e] + 1);
+    pk->n_tasks = n_tasks;
+    std::vector<int64_t> task_glv(n_tasks, 0), task_n(n_tasks, 0), tslot(n_tasks, 0);
+    for (int64_t e = 0; e < E; ++e) {
+        task_glv[task[e]] = pk->lvl_ptr[mday[e]] + level[e] - 1;
+        task_n[task[e]]++;
+    }
     pk->lvl_off.assign(pk->n_levels + 1, 0);
-    for (int64_t e = 0; e < E; ++e) pk->lvl_off[pk->lvl_ptr[mday[e]] + level[e]]++;
+    for (int64_t t = 0; t < n_tasks; ++t) pk->lvl_off[task_glv[t] + 1]++;
     for (int64_t i = 0; i < pk->n_levels; ++i) pk->lvl_off[i + 1] += pk->lvl_off[i];
-    std::vector<int64_t> fill(pk->lvl_off.begin(), pk->lvl_off.end() - 1);
+    {
+        std::vector<int64_t> next(pk->lvl_off.begin(), pk->lvl_off.end() - 1);
+        for (int64_t t = 0; t < n_tasks; ++t) tslot[t] = next[task_glv[t]]++;
+    }
+    pk->task_off.assign(n_tasks + 1, 0);
+    for (int64_t t = 0; t < n_tasks; ++t) pk->task_off[tslot[t] + 1] = (int32_t)task_n[t];
+    for (int64_t i = 0; i < n_tasks; ++i) pk->task_off[i + 1] += pk->task_off[i];
+    std::vector<int64_t> fill(n_tasks);
+    for (int64_t t = 0; t < n_tasks; ++t) fill[t] = pk->task_off[tslot[t]];
     pk->eg.resize(E);
     pk->egm.resize(E);
     pk->enode.resize(E);
@@ -444,7 +499,7 @@ int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, P
     for (int64_t e = 0; e < E; ++e) {
         const sim_problem *p = ps[minst[e]];
         const int64_t le = mlocal[e];
-        const int64_t pos = fill[pk->lvl_ptr[mday[e]] + level[e] - 1]++;
+        const int64_t pos = fill[task[e]]++;
         pk->eg[pos] = (int32_t)le;
         pk->egm[pos] = (int32_t)e;
         pk->enode[pos] = mnode[e];
@@ -459,7 +514,7 @@ int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, P
 
 Layout layout_of(const Packed &pk, const sim_problem *p0) {
     return layout_for(pk.Np, pk.n_nodes, pk.n_inst, pk.Nc, pk.Nt, pk.R, pk.RL, pk.D, pk.n_events, p0->n_shift,
-                      pk.n_levels, pk.n_record, pk.n_slots);
+                      pk.n_levels, pk.n_tasks, pk.n_record, pk.n_slots);
 }
 
 }  // namespace
@@ -473,7 +528,7 @@ struct sim_handle {
     std::vector<int32_t> lane_of;   // position of each concatenated node
     std::vector<int32_t> node_id;   // node number within its instance per position (-1: padding)
     std::vector<int32_t> ev_inst, ev_local, ev_day;  // merged event index -> instance, local index, day
-    std::vector<int64_t> lvl_off;   // host copy of the level boundaries
+    std::vector<int64_t> lvl_off;   // host copy of the level boundaries (task offsets)
     std::vector<int32_t> lvl_ptr;   // [D+1]
     Layout lay{};
     void *ws = nullptr;
@@ -556,7 +611,7 @@ int collect_marks(sim_handle *h) {
 
 enum { SLOT_FREE = 0, SLOT_RUNNING = 1, SLOT_DONE = 2 };
 
-// Levels of at most this many (event, lane) pairs in every slot run together,
+// Levels of at most this many (task, lane) pairs in every slot run together,
 // one workgroup per slot.
 constexpr int64_t kSlotSmallLevel = 4096;
 
@@ -731,6 +786,7 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
     ev.dest = at<int32_t>(h->ws, l.ev_dest);
     ev.n = at<int32_t>(h->ws, l.ev_n);
     ev.meta = at<uint32_t>(h->ws, l.ev_meta);
+    ev.task_off = at<int32_t>(h->ws, l.task_off);
     ev.lvl_off = at<int64_t>(h->ws, l.lvl_off);
     ev.lvl_ptr = at<int32_t>(h->ws, l.lvl_ptr);
 
@@ -761,6 +817,7 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
         {(void *)ev.dest, pk.edest.data(), sizeof(int32_t) * E},
         {(void *)ev.n, pk.en.data(), sizeof(int32_t) * E},
         {(void *)ev.meta, pk.emeta.data(), sizeof(uint32_t) * E},
+        {(void *)ev.task_off, pk.task_off.data(), sizeof(int32_t) * (pk.n_tasks + 1)},
         {(void *)ev.lvl_off, pk.lvl_off.data(), sizeof(int64_t) * (pk.n_levels + 1)},
         {(void *)ev.lvl_ptr, pk.lvl_ptr.data(), sizeof(int32_t) * (h->D + 1)},
         {(void *)s.rec_slot, pk.rec_slot.data(), sizeof(int32_t) * h->D},
@@ -808,7 +865,8 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
 extern "C" {
 
 int sim_plan_levels(int64_t n_events, const int32_t *ev_day, const int32_t *ev_kind,
-                    const int32_t *ev_node, const int32_t *ev_dest, int32_t n_nodes, int32_t *level_out) {
+                    const int32_t *ev_node, const int32_t *ev_dest, int32_t n_nodes, int32_t *level_out,
+                    int32_t *task_out) {
     if (n_events < 0 || n_nodes < 0 || (n_events > 0 && (!ev_day || !ev_kind || !ev_node || !ev_dest || !level_out)))
         return SIM_EINVAL;
     int32_t max_day = -1;
@@ -819,7 +877,9 @@ int sim_plan_levels(int64_t n_events, const int32_t *ev_day, const int32_t *ev_k
             return SIM_EINVAL;
         max_day = std::max(max_day, ev_day[e]);
     }
-    plan_levels(n_events, ev_day, ev_kind, ev_node, ev_dest, n_nodes, level_out, nullptr, max_day + 1);
+    std::vector<int32_t> task(task_out ? 0 : n_events);
+    plan_levels(n_events, ev_day, ev_kind, ev_node, ev_dest, n_nodes, level_out, task_out ? task_out : task.data(),
+                nullptr, max_day + 1);
     return SIM_OK;
 }
 
@@ -870,7 +930,7 @@ int sim_run(sim_handle *h, int32_t n_days) {
             int32_t lv = h->lvl_ptr[d];
             const int32_t lv_end = h->lvl_ptr[d + 1];
             while (lv < lv_end) {
-                const int64_t size = (h->lvl_off[lv + 1] - h->lvl_off[lv]) * h->R;
+                const int64_t size = (h->lvl_off[lv + 1] - h->lvl_off[lv]) * h->RL;
                 if (size > kSmallLevel) {
                     e = timed(h, SIM_K_EVENTS, [&] {
                         return launch_events(h->model, h->st, h->ev, d, h->lvl_off[lv], h->lvl_off[lv + 1], h->stream);
@@ -878,7 +938,7 @@ int sim_run(sim_handle *h, int32_t n_days) {
                     ++lv;
                 } else {
                     int32_t stop = lv + 1;
-                    while (stop < lv_end && (h->lvl_off[stop + 1] - h->lvl_off[stop]) * h->R <= kSmallLevel) ++stop;
+                    while (stop < lv_end && (h->lvl_off[stop + 1] - h->lvl_off[stop]) * h->RL <= kSmallLevel) ++stop;
                     const int32_t a = lv;
                     e = timed(h, SIM_K_EVENTS, [&] { return launch_event_levels(h->model, h->st, h->ev, d, a, stop, h->stream); });
                     lv = stop;
@@ -1127,14 +1187,14 @@ int sim_slots_step(sim_handle *h, int32_t *finished, int32_t *n_finished) {
         if (d < sl.horizon) k_max = std::max(k_max, h->lvl_ptr[d + 1] - h->lvl_ptr[d]);
     }
     if (!any) return SIM_OK;
-    std::vector<int64_t> size(k_max, 0);  // largest (event, lane) count of level k over the slots
+    std::vector<int64_t> size(k_max, 0);  // largest (task, lane) count of level k over the slots
     for (const auto &sl : h->slots) {
         if (sl.state != SLOT_RUNNING) continue;
         const int32_t d = T - sl.t0;
         if (d >= sl.horizon) continue;
         for (int32_t k = 0; k < h->lvl_ptr[d + 1] - h->lvl_ptr[d]; ++k) {
             const int32_t lv = h->lvl_ptr[d] + k;
-            size[k] = std::max(size[k], (h->lvl_off[lv + 1] - h->lvl_off[lv]) * 64);
+            size[k] = std::max(size[k], (h->lvl_off[lv + 1] - h->lvl_off[lv]) * 64);  // tasks x lanes
         }
     }
     hipError_t e = timed(h, SIM_K_DAY, [&] { return launch_day(h->model, h->st, T, 1, 1, LAYOUT_TILE, h->stream); });

@@ -9,9 +9,10 @@
 //   u[c * L + l]        int32 compartment counts, compartment-major (SoA) so
 //                       that a wavefront's loads of one compartment coalesce
 //   phi[l]              binary64 environmental infectious pressure
-//   events              SoA in execution order (day, then level, then list
-//                       order), 20 bytes per event: global index g, node,
-//                       dest, n, packed meta (kind, select mask, shift id)
+//   events              SoA in execution order (day, then level, then task,
+//                       then list order), 24 bytes per event: global index g,
+//                       merged index, node, dest, n, packed meta (kind,
+//                       select mask, shift id)
 #pragma once
 #include <cstdint>
 
@@ -89,7 +90,8 @@ struct DevEvents {
     const int32_t *dest;
     const int32_t *n;
     const uint32_t *meta;
-    const int64_t *lvl_off;     // level boundaries into the arrays above
+    const int32_t *task_off;    // task boundaries into the arrays above (a task's events in list order)
+    const int64_t *lvl_off;     // level boundaries into the tasks
     const int32_t *lvl_ptr;     // [D+1]: levels of day d are lvl_ptr[d] .. lvl_ptr[d+1]-1
 };
 

@@ -67,7 +67,7 @@ SIGNATURES = {
     "sim_levels": (C.c_int64, [C.c_void_p, C.c_int32, _i32p]),
     "sim_destroy": (None, [C.c_void_p]),
     "sim_last_error": (C.c_char_p, [C.c_void_p]),
-    "sim_plan_levels": (C.c_int, [C.c_int64, _i32p, _i32p, _i32p, _i32p, C.c_int32, _i32p]),
+    "sim_plan_levels": (C.c_int, [C.c_int64, _i32p, _i32p, _i32p, _i32p, C.c_int32, _i32p, _i32p]),
     "sim_kernel_times": (C.c_int, [C.c_void_p, C.c_int32, _f64p, _i64p]),
     "sim_create_batch": (C.c_int, [C.POINTER(C.POINTER(sim_problem)), C.c_int32, C.POINTER(sim_device_opts),
                                    C.POINTER(C.c_void_p)]),
@@ -148,14 +148,17 @@ def workspace_bytes(p, events_mode=EVENTS_LEVELS):
     return int(lib().sim_workspace_bytes(C.byref(s), C.byref(o)))
 
 
-def plan_levels(ev_day, ev_kind, ev_node, ev_dest, n_nodes):
-    """Host dependency pass (no GPU needed): the level of each event within its day."""
+def plan_levels(ev_day, ev_kind, ev_node, ev_dest, n_nodes, tasks=False):
+    """Host dependency pass (no GPU needed): the level of each event within its
+    day, and with tasks=True also the task of each event."""
     a = [np.ascontiguousarray(x, dtype=np.int32) for x in (ev_day, ev_kind, ev_node, ev_dest)]
     out = np.zeros(len(a[0]), np.int32)
-    rc = lib().sim_plan_levels(len(out), *[_p(x, _i32p) for x in a], int(n_nodes), _p(out, _i32p))
+    task = np.zeros(len(a[0]), np.int32)
+    rc = lib().sim_plan_levels(len(out), *[_p(x, _i32p) for x in a], int(n_nodes), _p(out, _i32p),
+                               _p(task, _i32p))
     if rc != SIM_OK:
         raise SimError(rc, "sim_plan_levels rejected its input")
-    return out
+    return (out, task) if tasks else out
 
 
 def _torch_cuda():

@@ -107,24 +107,45 @@ def touches(kind, node, dest):
     return {node}, {node}, set()
 
 
-def check_levels(day, kind, node, dest, level):
-    """No two events of a level conflict; conflicting pairs keep list order; and
-    every level is as small as the rules allow (each event's level is one more
-    than the largest level it must follow)."""
+def check_levels(day, kind, node, dest, level, task):
+    """Tasks are single external transfers or maximal runs of one node's
+    single-node events with no external transfer touching the node in
+    between; a task's events share a level; events of different tasks that
+    conflict keep list order across levels; and every task's level is as small
+    as the rules allow (one more than the largest level it must follow)."""
     n = len(day)
     for d in np.unique(day):
         idx = np.flatnonzero(day == d)
         info = [touches(kind[i], node[i], dest[i] if kind[i] == EXTERNAL else -1) for i in idx]
+        # task shape
+        for t in np.unique(task[idx]):
+            mine = idx[task[idx] == t]
+            assert len(set(level[mine])) == 1
+            if len(mine) > 1:
+                assert (kind[mine] != EXTERNAL).all() and len(set(node[mine])) == 1
+        # maximal runs: walk the events touching each node in list order
+        last = {}
+        for a, i in enumerate(idx):
+            nodes, _, _ = info[a]
+            for x in nodes:
+                prev = last.get(x)
+                if prev is not None:
+                    both_local = kind[prev] != EXTERNAL and kind[i] != EXTERNAL
+                    assert (task[prev] == task[i]) == both_local, (prev, i)
+                last[x] = i
+        # order and minimality
+        need = {}
         for a in range(len(idx)):
-            need = 0
             _, draw_a, add_a = info[a]
             for b in range(a):
+                if task[idx[b]] == task[idx[a]]:
+                    continue
                 _, draw_b, add_b = info[b]
-                conflict = bool(draw_a & (draw_b | add_b)) or bool(add_a & draw_b)
-                if conflict:
+                if bool(draw_a & (draw_b | add_b)) or bool(add_a & draw_b):
                     assert level[idx[b]] < level[idx[a]]
-                    need = max(need, level[idx[b]])
-            assert level[idx[a]] == need + 1
+                    need[task[idx[a]]] = max(need.get(task[idx[a]], 0), level[idx[b]])
+        for a in range(len(idx)):
+            assert level[idx[a]] == need.get(task[idx[a]], 0) + 1
 
 
 def random_events(rng, n_nodes, n_events, n_days):
@@ -141,8 +162,8 @@ def test_levels_random_lists(seed):
     rng = np.random.default_rng(seed)
     n_nodes = [3, 5, 20, 50, 8, 2][seed]
     day, kind, node, dest = random_events(rng, n_nodes, 300, 4)
-    level = P.plan_levels(day, kind, node, dest, n_nodes)
-    check_levels(day, kind, node, dest, level)
+    level, task = P.plan_levels(day, kind, node, dest, n_nodes, tasks=True)
+    check_levels(day, kind, node, dest, level, task)
 
 
 def test_levels_hub_additions_share_a_level():
@@ -160,10 +181,28 @@ def test_levels_hub_additions_share_a_level():
 
 def test_levels_on_generated_network():
     p = synth.sise3_network(n_nodes=2000, n_days=60, seed=9)
-    level = P.plan_levels(p.ev_day, p.ev_kind, p.ev_node, p.ev_dest, p.n_nodes)
+    level, task = P.plan_levels(p.ev_day, p.ev_kind, p.ev_node, p.ev_dest, p.n_nodes, tasks=True)
     sub = p.ev_day < 3
-    check_levels(p.ev_day[sub], p.ev_kind[sub], p.ev_node[sub], p.ev_dest[sub], level[sub])
+    check_levels(p.ev_day[sub], p.ev_kind[sub], p.ev_node[sub], p.ev_dest[sub], level[sub], task[sub])
     assert level.max() < 20
+    assert len(np.unique(task)) < len(task)
+
+
+def test_single_node_runs_form_one_task():
+    # node 0: enter, exit, internal, exit -> one task at level 1; a move out of
+    # node 0 follows it; the next exit at node 0 starts a new task after the move
+    kind = np.array([ENTER, EXIT, INTERNAL, EXIT, EXTERNAL, EXIT, ENTER])
+    node = np.array([0, 0, 0, 0, 0, 0, 1])
+    dest = np.array([-1, -1, -1, -1, 1, -1, -1])
+    level, task = P.plan_levels(np.zeros(7), kind, node, dest, 2, tasks=True)
+    assert level.tolist() == [1, 1, 1, 1, 2, 3, 1]
+    assert task.tolist() == [0, 0, 0, 0, 1, 2, 3]
+    # additions only, then a draw: the task moves past every earlier event at the node
+    kind = np.array([EXTERNAL, EXTERNAL, ENTER, EXIT])
+    node = np.array([1, 2, 0, 0])
+    dest = np.array([0, 0, -1, -1])
+    level, task = P.plan_levels(np.zeros(4), kind, node, dest, 3, tasks=True)
+    assert level.tolist() == [1, 1, 2, 2] and task[2] == task[3]
 
 
 def test_plan_levels_rejects_bad_input():
