@@ -26,6 +26,7 @@ namespace episim {
 namespace {
 
 constexpr int kBlock = 256;
+static_assert(kBlock == kLaneUnit, "a workgroup of one-lane-per-node kernels is one unit");
 constexpr int kWaves = kBlock / 64;
 constexpr int kEvKindMask = 3;
 constexpr int kEvBlock = 1024;  // workgroup that runs a group of small event levels
@@ -97,6 +98,16 @@ __device__ __forceinline__ int season(int64_t t) {
     if (y < 0) y += 365;
     return y <= 91 ? 0 : (y <= 182 ? 1 : (y <= 273 ? 2 : 3));
 }
+
+// Loads of the state in the event phase are plain loads, so that the
+// compartments of one node are fetched together. They see the last writes
+// because a launch starts with clean caches, and because every kernel that
+// runs several levels, or events after the SSA, follows its barrier with
+// fresh_l1(): additions are device-scope atomics done in L2, which the CU's
+// L1 does not see, so the acquire drops the L1 lines before the next level.
+__device__ __forceinline__ int32_t load_state(const int32_t *p) { return *p; }
+
+__device__ __forceinline__ void fresh_l1() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 
 template <int NC>
 __device__ __forceinline__ bool comp_on(const Model &m, int c) {
@@ -675,8 +686,31 @@ __device__ __forceinline__ void day_wave(const Model &m, const DevState &s, int6
     }
 }
 
+template <int NC>
+__device__ __forceinline__ void event_task(const Model &m, const DevState &s, const DevEvents &ev, int64_t t,
+                                           int32_t r, int32_t d, unsigned long long *status);
+
+// The private tasks of one unit (a workgroup's positions) on day d, right after
+// its SSA: lane_of_pair maps the pairs (task, lane) of the workgroup, nl lanes
+// per position starting at r0, lanes r >= r_end idle. The SSA results of the
+// unit must be visible to the whole workgroup (a workgroup barrier first).
+template <int NC>
+__device__ __forceinline__ void private_tasks(const Model &m, const DevState &s, const DevEvents &ev, int32_t d,
+                                              int64_t unit, int64_t n_units, int32_t r0, int32_t nl, int32_t r_end,
+                                              unsigned long long *status) {
+    fresh_l1();
+    const int64_t k = (int64_t)d * n_units + unit;
+    const int64_t t0 = ev.priv_off[k], t1 = ev.priv_off[k + 1];
+    const int64_t count = (t1 - t0) * nl;
+    for (int64_t i = threadIdx.x; i < count; i += kBlock) {
+        const int64_t t = t0 + (nl == 1 ? i : i / nl);
+        const int32_t r = r0 + (nl == 1 ? 0 : (int32_t)(i % nl));
+        if (r < r_end) event_task<NC>(m, s, ev, t, r, d, status);
+    }
+}
+
 template <class Rules>
-__global__ __launch_bounds__(kBlock) void k_day(Model m, DevState s, int32_t d, int32_t prologue,
+__global__ __launch_bounds__(kBlock) void k_day(Model m, DevState s, DevEvents ev, int32_t d, int32_t prologue,
                                                 int32_t ssa) {
     constexpr int NC = Rules::NC;
     if (!block_ok(s.status)) return;
@@ -687,6 +721,7 @@ __global__ __launch_bounds__(kBlock) void k_day(Model m, DevState s, int32_t d, 
     const int32_t d_ssa = ssa ? d : -1;
     // one lane per node; instances are padded to whole workgroups: one set per workgroup
     flush_block<NC>(m, s, t, s.inst[(int64_t)blockIdx.x * kBlock], d_rec, d_ssa);
+    if (ssa) private_tasks<NC>(m, s, ev, d, blockIdx.x, s.Np / kLaneUnit, 0, 1, 1, s.status);
 }
 
 // Replicate tiles (replicate lanes in groups of 64): workgroup (x, y) takes
@@ -696,8 +731,8 @@ __global__ __launch_bounds__(kBlock) void k_day(Model m, DevState s, int32_t d, 
 // In a slot handle, column y is slot y: d is the handle's step, the slot's own
 // day is d - t0, and the slot's lanes past its replicate count are idle.
 template <class Rules>
-__global__ __launch_bounds__(kBlock) void k_day_tile(Model m, DevState s, int32_t d, int32_t prologue,
-                                                     int32_t ssa) {
+__global__ __launch_bounds__(kBlock) void k_day_tile(Model m, DevState s, DevEvents ev, int32_t d,
+                                                     int32_t prologue, int32_t ssa) {
     constexpr int NC = Rules::NC;
     int32_t r_end = s.R;
     unsigned long long *status = s.status;
@@ -723,6 +758,8 @@ __global__ __launch_bounds__(kBlock) void k_day_tile(Model m, DevState s, int32_
     }
     // instances are padded to whole tiles: one instance per workgroup
     flush_tile<NC>(m, s, t, r < r_end ? s.inst[pos0] * s.R + r : -1, prologue ? d - 1 : -1, ssa ? d : -1);
+    if (ssa)
+        private_tasks<NC>(m, s, ev, d, blockIdx.x, s.Np / kTileNodes, (int32_t)blockIdx.y * 64, 64, r_end, status);
 }
 
 // ---------------------------------------------------------------------------
@@ -731,63 +768,89 @@ __global__ __launch_bounds__(kBlock) void k_day_tile(Model m, DevState s, int32_
 // only added to, so draws use plain loads/stores and additions commute
 // (integer atomics).
 // ---------------------------------------------------------------------------
-// Loads of the state in the event phase go to L2 (relaxed atomic loads at
-// device scope), where the additions of earlier levels were made, so a
-// workgroup that runs several levels back to back never reads a stale line.
-__device__ __forceinline__ int32_t load_l2(const int32_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+
 
 // Draw n of the tot individuals in the compartments of mask from x without
 // replacement (Sec. 3.2): draw q picks the individual at a uniform position
 // in [0, remaining) of the selected compartments in ascending order, from the
 // Philox block (q / 2, g, d, 1). Removes them from x and counts them in take.
+// pre, when given, holds the first kPreDraws draws (computed ahead in parallel).
+constexpr int kPreDraws = 4;
+
 template <int NC>
 __device__ __forceinline__ void draw_individuals(int32_t *x, int32_t *take, uint32_t mask, int32_t n, long long tot,
-                                                 uint32_t g, int32_t d, uint32_t key0, uint32_t key1) {
+                                                 uint32_t g, int32_t d, uint32_t key0, uint32_t key1,
+                                                 const uint64_t *pre = nullptr) {
+    long long cum[NC];  // running sums of the selected compartments, ascending
+    long long run = 0;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) take[c] = 0;
+    for (int c = 0; c < NC; ++c) {
+        take[c] = 0;
+        run += ((mask >> c) & 1u) ? x[c] : 0;
+        cum[c] = run;
+    }
     Word4 o{0, 0, 0, 0};
     for (int32_t q = 0; q < n; ++q) {
         uint64_t bits;
-        if ((q & 1) == 0) {
+        if (pre && q < kPreDraws) {
+            bits = pre[q];
+        } else if ((q & 1) == 0) {
             o = philox4x32_10(Word4{(uint32_t)q >> 1, g, (uint32_t)d, 1u}, key0, key1);
             bits = ((uint64_t)o.b << 32) | o.a;
         } else {
             bits = ((uint64_t)o.d << 32) | o.c;
         }
-        uint64_t pick = __umul64hi(bits, (uint64_t)tot);  // uniform on [0, tot)
-        int chosen = -1;
+        const uint64_t pick = __umul64hi(bits, (uint64_t)tot);  // uniform on [0, tot)
+        // the compartment holding individual `pick` in ascending order is the
+        // number of running sums at or below it (a compartment outside the
+        // mask, or empty, repeats the sum before it and is passed over)
+        int chosen = 0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) chosen += (uint64_t)cum[c] <= pick ? 1 : 0;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            if (chosen < 0 && ((mask >> c) & 1u)) {
-                if (pick < (uint64_t)x[c]) {
-                    chosen = c;
-                } else {
-                    pick -= (uint64_t)x[c];
-                }
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            if (c == chosen) {
-                x[c] -= 1;
-                take[c] += 1;
-            }
+            const int hit = c == chosen ? 1 : 0;
+            x[c] -= hit;
+            take[c] += hit;
+            cum[c] -= c >= chosen ? 1 : 0;
         }
         tot -= 1;
     }
 }
 
+// What one event needs besides the state: its packed kind / mask / shift,
+// node, destination, count, Philox counter word g, merged index gm (error
+// report) and the instance of its node.
+struct EvDesc {
+    uint32_t meta, smap;
+    int32_t node, dest, n, g, gm, inst;
+};
+
+// Compartment that an individual drawn from compartment c lands in (internal
+// and external transfers): 4 bits per source compartment of the event's map.
+__device__ __forceinline__ int shifted(uint32_t smap, int c) { return (int)((smap >> (4 * c)) & 0xFu); }
+
+__device__ __forceinline__ EvDesc load_desc(const DevState &s, const DevEvents &ev, int64_t e) {
+    EvDesc q;
+    q.meta = ev.meta[e];
+    q.smap = ev.smap[e];
+    q.node = ev.node[e];
+    q.dest = ev.dest[e];
+    q.n = ev.n[e];
+    q.g = ev.g[e];
+    q.gm = ev.gm[e];
+    q.inst = s.inst[q.node];
+    return q;
+}
+
 template <int NC>
-__device__ __forceinline__ void event_one(const Model &m, const DevState &s, const DevEvents &ev,
-                                          int64_t e, int32_t r, int32_t d, unsigned long long *status) {
-    const uint32_t meta = ev.meta[e];
+__device__ __forceinline__ void event_apply(const Model &m, const DevState &s, const EvDesc &q, int32_t r, int32_t d,
+                                            unsigned long long *status) {
+    const uint32_t meta = q.meta;
     const int kind = (int)(meta & kEvKindMask);
     const uint32_t mask = (meta >> 2) & 0xffu;
-    const int sid = (int)((meta >> 10) & 0x3fu) - 1;
-    const int32_t node = ev.node[e];
-    const int32_t n = ev.n[e];
+    const int32_t node = q.node;
+    const int32_t n = q.n;
     const int64_t ls = (int64_t)node * s.RL + r;
     if (kind == SIM_ENTER) {
 #pragma unroll
@@ -801,15 +864,15 @@ __device__ __forceinline__ void event_one(const Model &m, const DevState &s, con
     for (int c = 0; c < NC; ++c) {
         x[c] = 0;
         if ((mask >> c) & 1u) {
-            x[c] = load_l2(&s.u[(int64_t)c * s.L + ls]);
+            x[c] = load_state(&s.u[(int64_t)c * s.L + ls]);
             tot += x[c];
         }
     }
-    const uint32_t g = (uint32_t)ev.g[e];
-    const int32_t inst = s.inst[node];
+    const uint32_t g = (uint32_t)q.g;
+    const int32_t inst = q.inst;
     const int32_t set = inst * s.R + r;
     if ((long long)n > tot) {
-        atomicMin(status, ((unsigned long long)(uint32_t)ev.gm[e] << 32) | (unsigned long long)(uint32_t)set);
+        atomicMin(status, ((unsigned long long)(uint32_t)q.gm << 32) | (unsigned long long)(uint32_t)set);
         return;
     }
     int32_t take[NC];
@@ -822,12 +885,12 @@ __device__ __forceinline__ void event_one(const Model &m, const DevState &s, con
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             if (take[c]) {
-                const int to = sid >= 0 ? c + s.shift[sid * MAXC + c] : c;
+                const int to = shifted(q.smap, c);
 #pragma unroll
                 for (int cc = 0; cc < NC; ++cc) {
                     if (cc == to) {
                         if (!((touched >> cc) & 1u)) {
-                            y[cc] = load_l2(&s.u[(int64_t)cc * s.L + ls]);
+                            y[cc] = load_state(&s.u[(int64_t)cc * s.L + ls]);
                             touched |= 1u << cc;
                         }
                         y[cc] += take[c];
@@ -844,15 +907,21 @@ __device__ __forceinline__ void event_one(const Model &m, const DevState &s, con
     for (int c = 0; c < NC; ++c)
         if ((mask >> c) & 1u) s.u[(int64_t)c * s.L + ls] = x[c];
     if (kind == SIM_EXTERNAL) {
-        const int64_t ld = (int64_t)ev.dest[e] * s.RL + r;
+        const int64_t ld = (int64_t)q.dest * s.RL + r;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             if (take[c]) {
-                const int to = sid >= 0 ? c + s.shift[sid * MAXC + c] : c;
+                const int to = shifted(q.smap, c);
                 atomicAdd(&s.u[(int64_t)to * s.L + ld], take[c]);
             }
         }
     }
+}
+
+template <int NC>
+__device__ __forceinline__ void event_one(const Model &m, const DevState &s, const DevEvents &ev,
+                                          int64_t e, int32_t r, int32_t d, unsigned long long *status) {
+    event_apply<NC>(m, s, load_desc(s, ev, e), r, d, status);
 }
 
 // One task (replicate lane r): a single event, or a run of one node's enter /
@@ -876,7 +945,7 @@ __device__ __forceinline__ void event_task(const Model &m, const DevState &s, co
     const int64_t ls = (int64_t)node * s.RL + r;
     int32_t x[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) x[c] = comp_on<NC>(m, c) ? load_l2(&s.u[(int64_t)c * s.L + ls]) : 0;
+    for (int c = 0; c < NC; ++c) x[c] = comp_on<NC>(m, c) ? load_state(&s.u[(int64_t)c * s.L + ls]) : 0;
     const int32_t inst = s.inst[node];
     const int32_t set = inst * s.R + r;
     const uint32_t key0 = s.seed[inst], key1 = s.repid[set];
@@ -904,11 +973,11 @@ __device__ __forceinline__ void event_task(const Model &m, const DevState &s, co
         int32_t take[NC];
         draw_individuals<NC>(x, take, mask, n, tot, (uint32_t)ev.g[e], d, key0, key1);
         if (kind == SIM_INTERNAL) {
-            const int sid = (int)((meta >> 10) & 0x3fu) - 1;
+            const uint32_t smap = ev.smap[e];
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 if (take[c]) {
-                    const int to = sid >= 0 ? c + s.shift[sid * MAXC + c] : c;
+                    const int to = shifted(smap, c);
 #pragma unroll
                     for (int cc = 0; cc < NC; ++cc)
                         if (cc == to) x[cc] += take[c];
@@ -936,19 +1005,168 @@ __global__ __launch_bounds__(kBlock) void k_events(Model m, DevState s, DevEvent
 
 // A run of small levels [lv_begin, lv_end) of day d in one workgroup, with a
 // workgroup barrier between levels (the levels' order is all that links them).
+// The descriptors of all its tasks (contiguous in execution order) are staged
+// in LDS first, so each level then waits on one round trip for the state
+// only; a task of several events keeps to its own loads.
+constexpr int kGroupCap = 1024;
+
 template <int NC>
 __global__ __launch_bounds__(kEvBlock) void k_event_levels(Model m, DevState s, DevEvents ev, int32_t d,
                                                            int32_t lv_begin, int32_t lv_end) {
     if (!block_ok(s.status)) return;
+    __shared__ EvDesc sh_desc[kGroupCap];
+    __shared__ int32_t sh_multi[kGroupCap];
+    const int64_t tb = ev.lvl_off[lv_begin], te = ev.lvl_off[lv_end];
+    const bool staged = te - tb <= kGroupCap;
+    if (staged) {
+        for (int64_t i = threadIdx.x; i < te - tb; i += kEvBlock) {
+            const int64_t e0 = ev.task_off[tb + i], e1 = ev.task_off[tb + i + 1];
+            sh_multi[i] = e1 - e0 > 1;
+            if (e1 - e0 == 1) sh_desc[i] = load_desc(s, ev, e0);
+        }
+        __syncthreads();
+    }
     for (int32_t lv = lv_begin; lv < lv_end; ++lv) {
         const int64_t begin = ev.lvl_off[lv], end = ev.lvl_off[lv + 1];
         const int64_t count = (end - begin) * s.RL;
         for (int64_t t = threadIdx.x; t < count; t += kEvBlock) {
-            const int64_t e = begin + (s.RL == 1 ? t : t / s.RL);
+            const int64_t k = begin + (s.RL == 1 ? t : t / s.RL);
             const int32_t r = s.RL == 1 ? 0 : (int32_t)(t % s.RL);
-            if (r < s.R) event_task<NC>(m, s, ev, e, r, d, s.status);
+            if (r >= s.R) continue;
+            if (staged && !sh_multi[k - tb])
+                event_apply<NC>(m, s, sh_desc[k - tb], r, d, s.status);
+            else
+                event_task<NC>(m, s, ev, k, r, d, s.status);
         }
         __syncthreads();
+        fresh_l1();
+    }
+}
+
+// A day's levels in LDS (one lane per node): the nodes its level tasks touch
+// are loaded into slots once, every level updates the slots (draws with plain
+// LDS loads and stores, since a node drawn from is alone in its level;
+// additions with LDS atomics, which commute), and the slots are written back
+// once. Same draws and order as the global-memory path.
+template <int NC>
+__device__ __forceinline__ void slot_event(const Model &m, const DevState &s, const DevEvents &ev, uint32_t meta,
+                                           uint32_t smap, int32_t n, uint32_t g, int32_t e, int32_t *xs, int32_t *xd,
+                                           uint32_t key0, uint32_t key1, int32_t set, int32_t d,
+                                           unsigned long long *status, const uint64_t *pre) {
+    const int kind = (int)(meta & kEvKindMask);
+    const uint32_t mask = (meta >> 2) & 0xffu;
+    if (kind == SIM_ENTER) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if ((mask >> c) & 1u) __hip_atomic_fetch_add(&xs[c], n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        return;
+    }
+    int32_t x[NC];
+    long long tot = 0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        x[c] = ((mask >> c) & 1u) ? xs[c] : 0;
+        tot += x[c];
+    }
+    if ((long long)n > tot) {
+        atomicMin(status, ((unsigned long long)(uint32_t)ev.gm[e] << 32) | (unsigned long long)(uint32_t)set);
+        return;
+    }
+    int32_t take[NC];
+    draw_individuals<NC>(x, take, mask, n, tot, g, d, key0, key1, pre);
+    if (kind == SIM_INTERNAL) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if ((mask >> c) & 1u) xs[c] = x[c];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            if (take[c]) {
+                const int to = shifted(smap, c);
+                xs[to] += take[c];
+            }
+        }
+        return;
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+        if ((mask >> c) & 1u) xs[c] = x[c];
+    if (kind == SIM_EXTERNAL) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            if (take[c]) {
+                const int to = shifted(smap, c);
+                __hip_atomic_fetch_add(&xd[to], take[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
+    }
+}
+
+// The day's level events are contiguous (e0 .. e0 + ne - 1, by level, then
+// task); the launch carries the day's offsets so that staging is one round
+// trip for the event fields, slot keys and level bounds, and one more for the
+// slots' counts.
+template <int NC>
+__global__ __launch_bounds__(kEvBlock) void k_event_day(Model m, DevState s, DevEvents ev, int32_t d, int32_t lv0,
+                                                        int32_t nl, int32_t s0, int32_t ns, int64_t e0,
+                                                        int32_t ne) {
+    __shared__ int32_t sh_u[kDaySlotCap * NC];
+    __shared__ uint32_t sh_k0[kDaySlotCap], sh_k1[kDaySlotCap];
+    __shared__ int32_t sh_set[kDaySlotCap];
+    __shared__ int32_t sh_n[kDayEventCap], sh_g[kDayEventCap];
+    __shared__ uint32_t sh_meta[kDayEventCap], sh_smap[kDayEventCap];
+    __shared__ int16_t sh_ss[kDayEventCap], sh_sd[kDayEventCap];
+    __shared__ int32_t sh_lv[kDayLevelCap + 1];
+    __shared__ uint64_t sh_pre[kDayEventCap * kPreDraws];
+    for (int i = threadIdx.x; i <= nl; i += kEvBlock) sh_lv[i] = (int32_t)(ev.lvl_ev_off[lv0 + i] - e0);
+    for (int i = threadIdx.x; i < ne; i += kEvBlock) {
+        sh_meta[i] = ev.meta[e0 + i];
+        sh_smap[i] = ev.smap[e0 + i];
+        sh_n[i] = ev.n[e0 + i];
+        sh_g[i] = ev.g[e0 + i];
+        sh_ss[i] = (int16_t)ev.slot_src[e0 + i];
+        sh_sd[i] = (int16_t)ev.slot_dst[e0 + i];
+    }
+    for (int i = threadIdx.x; i < ns; i += kEvBlock) {
+        const int32_t pos = ev.slot_pos[s0 + i];
+        sh_k0[i] = ev.slot_key[3 * (s0 + i)];
+        sh_k1[i] = ev.slot_key[3 * (s0 + i) + 1];
+        sh_set[i] = (int32_t)ev.slot_key[3 * (s0 + i) + 2];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) sh_u[i * NC + c] = comp_on<NC>(m, c) ? load_state(&s.u[(int64_t)c * s.L + pos]) : 0;
+    }
+    __syncthreads();
+    if (*(volatile unsigned long long *)s.status != STATUS_OK) return;  // same value in every thread here
+    // the first draws of every event do not depend on the state: all at once
+    for (int i = threadIdx.x; i < ne * (kPreDraws / 2); i += kEvBlock) {
+        const int j = i / (kPreDraws / 2), b = i % (kPreDraws / 2);
+        if ((int)(sh_meta[j] & kEvKindMask) == SIM_ENTER || 2 * b >= sh_n[j]) continue;
+        const int32_t ss = sh_ss[j];
+        const Word4 o = philox4x32_10(Word4{(uint32_t)b, (uint32_t)sh_g[j], (uint32_t)d, 1u}, sh_k0[ss], sh_k1[ss]);
+        sh_pre[j * kPreDraws + 2 * b] = ((uint64_t)o.b << 32) | o.a;
+        sh_pre[j * kPreDraws + 2 * b + 1] = ((uint64_t)o.d << 32) | o.c;
+    }
+    __syncthreads();
+    for (int32_t k = 0; k < nl; ++k) {
+        for (int32_t i = sh_lv[k] + threadIdx.x; i < sh_lv[k + 1]; i += kEvBlock) {
+            if (sh_meta[i] & kMetaCont) continue;  // applied with its task's first event
+            const int32_t ss = sh_ss[i];
+            int32_t *xs = &sh_u[ss * NC];
+            int32_t *xd = sh_sd[i] >= 0 ? &sh_u[sh_sd[i] * NC] : xs;
+            // one event, or a run of one node's events in list order
+            int32_t j = i;
+            do {
+                slot_event<NC>(m, s, ev, sh_meta[j], sh_smap[j], sh_n[j], (uint32_t)sh_g[j], (int32_t)(e0 + j), xs, xd, sh_k0[ss],
+                               sh_k1[ss], sh_set[ss], d, s.status, &sh_pre[j * kPreDraws]);
+                ++j;
+            } while (j < sh_lv[k + 1] && (sh_meta[j] & kMetaCont));
+        }
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < ns; i += kEvBlock) {
+        const int32_t pos = ev.slot_pos[s0 + i];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (comp_on<NC>(m, c)) s.u[(int64_t)c * s.L + pos] = sh_u[i * NC + c];
     }
 }
 
@@ -972,7 +1190,10 @@ __global__ __launch_bounds__(kEvBlock) void k_slot_events(Model m, DevState s, D
             const int32_t rr = (int32_t)(t & 63);
             if (rr < si.n_rep) event_task<NC>(m, s, ev, begin + (t >> 6), (int32_t)blockIdx.y * 64 + rr, d, status);
         }
-        if (k_end > k + 1) __syncthreads();
+        if (k_end > k + 1) {
+            __syncthreads();
+            fresh_l1();
+        }
     }
 }
 
@@ -1033,6 +1254,8 @@ __global__ __launch_bounds__(kBlock) void k_persist(Model m, DevState s, DevEven
                         day_wave<Rules>(m, s, pos * s.RL + r, d, prologue, ssa, t, s.R, s.status);
                     }
                     flush_tile<NC>(m, s, t, r < s.R ? s.inst[pos0] * s.R + r : -1, d_rec, d_ssa);
+                    if (ssa)
+                        private_tasks<NC>(m, s, ev, d, tile % nx, nx, (int32_t)(tile / nx) * 64, 64, s.R, s.status);
                 }
             } else {
                 const int64_t chunks = (s.L + kBlock - 1) / kBlock;
@@ -1041,11 +1264,13 @@ __global__ __launch_bounds__(kBlock) void k_persist(Model m, DevState s, DevEven
                     Tally<NC> t{};
                     day_wave<Rules>(m, s, l, d, prologue, ssa, t, s.R, s.status);
                     flush_block<NC>(m, s, t, s.inst[chunk * kBlock], d_rec, d_ssa);
+                    if (ssa) private_tasks<NC>(m, s, ev, d, chunk, s.Np / kLaneUnit, 0, 1, 1, s.status);
                 }
             }
         }
         if (!ssa) break;
         grid.sync();
+        fresh_l1();
         // big levels are spread over the grid; a run of small levels is done
         // by workgroup 0 alone; one grid barrier follows either
         int32_t lv = ev.lvl_ptr[d];
@@ -1075,11 +1300,14 @@ __global__ __launch_bounds__(kBlock) void k_persist(Model m, DevState s, DevEven
                             if (r < s.R) event_task<NC>(m, s, ev, e, r, d, s.status);
                         }
                         __syncthreads();
+                        fresh_l1();
                     }
                 }
                 lv = stop;
             }
             grid.sync();
+            fresh_l1();
+        fresh_l1();
         }
     }
 }
@@ -1092,16 +1320,18 @@ struct Kernels {
     static void *levels() { return (void *)&k_event_levels<Rules::NC>; }
     static void *persist() { return (void *)&k_persist<Rules>; }
     static void *slot_events() { return (void *)&k_slot_events<Rules::NC>; }
+    static void *event_day() { return (void *)&k_event_day<Rules::NC>; }
 };
 
 struct Table {
-    void *day, *events, *persist, *levels, *tile, *slot_events;
+    void *day, *events, *persist, *levels, *tile, *slot_events, *event_day;
 };
 
 template <class Rules>
 Table table() {
     return {Kernels<Rules>::day(),    Kernels<Rules>::events(), Kernels<Rules>::persist(),
-            Kernels<Rules>::levels(), Kernels<Rules>::tile(),   Kernels<Rules>::slot_events()};
+            Kernels<Rules>::levels(), Kernels<Rules>::tile(),   Kernels<Rules>::slot_events(),
+            Kernels<Rules>::event_day()};
 }
 
 Table pick(const Model &m) {
@@ -1112,14 +1342,15 @@ Table pick(const Model &m) {
 
 }  // namespace
 
-int launch_day(const Model &m, const DevState &s, int32_t d, int prologue, int ssa, int layout,
-               void *stream) {
+int launch_day(const Model &m, const DevState &s, const DevEvents &ev, int32_t d, int prologue, int ssa,
+               int layout, void *stream) {
     if (s.L == 0) return hipSuccess;
     const Table t = pick(m);
     Model mm = m;
     DevState ss = s;
+    DevEvents ee = ev;
     int32_t dd = d, pro = prologue, sa = ssa;
-    void *args[] = {&mm, &ss, &dd, &pro, &sa};
+    void *args[] = {&mm, &ss, &ee, &dd, &pro, &sa};
     if (layout == LAYOUT_TILE) {
         const unsigned nx = (unsigned)((s.Np + kTileNodes - 1) / kTileNodes);
         return (int)hipLaunchKernel(t.tile, dim3(nx, (unsigned)(s.RL / 64)), dim3(kBlock), args, 0,
@@ -1197,6 +1428,18 @@ int launch_slot_events(const Model &m, const DevState &s, const DevEvents &ev, i
     void *args[] = {&mm, &ss, &ee, &a, &b, &c};
     return (int)hipLaunchKernel(t.slot_events, dim3(gx, (unsigned)(s.RL / 64)), dim3(kEvBlock), args, 0,
                                 (hipStream_t)stream);
+}
+
+int launch_event_day(const Model &m, const DevState &s, const DevEvents &ev, int32_t d, int32_t lv0, int32_t nl,
+                     int32_t s0, int32_t ns, int64_t e0, int64_t ne, void *stream) {
+    const Table t = pick(m);
+    Model mm = m;
+    DevState ss = s;
+    DevEvents ee = ev;
+    int32_t dd = d, a = lv0, b = nl, c = s0, n = ns, k = (int32_t)ne;
+    int64_t e = e0;
+    void *args[] = {&mm, &ss, &ee, &dd, &a, &b, &c, &n, &e, &k};
+    return (int)hipLaunchKernel(t.event_day, dim3(1), dim3(kEvBlock), args, 0, (hipStream_t)stream);
 }
 
 int launch_slot_init(const DevState &s, int32_t nc, const int32_t *u0, const double *v0, int32_t slot,

@@ -249,7 +249,7 @@ int32_t lane_stride(int32_t R) { return R == 1 ? 1 : (int32_t)(((int64_t)R + 63)
 
 // Nodes of one unit of work and the padding granule of an instance.
 int64_t unit_nodes(int layout) { return layout == LAYOUT_TILE ? kTileNodes : 64; }
-int64_t pad_nodes(int layout) { return layout == LAYOUT_TILE ? kTileNodes : 256; /* one workgroup */ }
+int64_t pad_nodes(int layout) { return unit_positions(layout); /* one workgroup */ }
 
 // Positions of one instance's nodes: herds sorted by size (largest first)
 // are dealt one per unit of work in turn, back and forth (snake order), so the
@@ -290,8 +290,8 @@ int64_t order_nodes(const sim_problem *p, int layout, std::vector<int32_t> *pos_
 
 // Device buffer layout of one handle.
 struct Layout {
-    size_t u, phi, node_id, inst, inst_off, seed, coef, alpha, beta, repid, shift, status, ev_g, ev_gm, ev_node,
-        ev_dest, ev_n, ev_meta, task_off, lvl_off, lvl_ptr, prevalence, transitions, totals, snap_u, snap_v, rec_slot, slots,
+    size_t u, phi, node_id, inst, inst_off, seed, coef, alpha, beta, repid, status, ev_g, ev_gm, ev_node,
+        ev_dest, ev_n, ev_meta, ev_smap, task_off, priv_off, day_slot_off, slot_pos, slot_key, lvl_ev_off, ev_slot_src, ev_slot_dst, lvl_off, lvl_ptr, prevalence, transitions, totals, snap_u, snap_v, rec_slot, slots,
         u0, v0, total;
 };
 
@@ -299,7 +299,7 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 Layout layout_for(int64_t Np, int64_t n_nodes, int64_t n_inst, int64_t Nc, int64_t Nt, int64_t R, int64_t RL,
                   int64_t D, int64_t n_events, int64_t n_shift_ids, int64_t n_levels, int64_t n_tasks,
-                  int64_t n_record, int64_t n_slots) {
+                  int64_t n_units, int64_t n_day_slots, int64_t n_record, int64_t n_slots) {
     Layout l{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -318,7 +318,6 @@ Layout layout_for(int64_t Np, int64_t n_nodes, int64_t n_inst, int64_t Nc, int64
     l.alpha = take(sizeof(double) * S);
     l.beta = take(sizeof(double) * S * 4);
     l.repid = take(sizeof(uint32_t) * S);
-    l.shift = take(sizeof(int32_t) * MAXC * std::max<int64_t>(n_shift_ids, 1));
     l.status = take(sizeof(unsigned long long) * std::max<int64_t>(n_slots, 1));
     l.ev_g = take(sizeof(int32_t) * n_events);
     l.ev_gm = take(sizeof(int32_t) * n_events);
@@ -326,7 +325,15 @@ Layout layout_for(int64_t Np, int64_t n_nodes, int64_t n_inst, int64_t Nc, int64
     l.ev_dest = take(sizeof(int32_t) * n_events);
     l.ev_n = take(sizeof(int32_t) * n_events);
     l.ev_meta = take(sizeof(uint32_t) * n_events);
+    l.ev_smap = take(sizeof(uint32_t) * n_events);
     l.task_off = take(sizeof(int32_t) * (n_tasks + 1));
+    l.priv_off = take(sizeof(int32_t) * (D * n_units + 1));
+    l.day_slot_off = take(sizeof(int32_t) * (D + 1));
+    l.slot_pos = take(sizeof(int32_t) * n_day_slots);
+    l.slot_key = take(sizeof(uint32_t) * 3 * n_day_slots);
+    l.lvl_ev_off = take(sizeof(int64_t) * (n_levels + 1));
+    l.ev_slot_src = take(sizeof(int32_t) * n_events);
+    l.ev_slot_dst = take(sizeof(int32_t) * n_events);
     l.lvl_off = take(sizeof(int64_t) * (n_levels + 1));
     l.lvl_ptr = take(sizeof(int32_t) * (D + 1));
     l.prevalence = take(sizeof(int32_t) * D * S);
@@ -353,11 +360,15 @@ struct Packed {
     std::vector<int32_t> lane_of;  // [n_nodes] position of each concatenated node
     // merged events in execution order and their levels
     std::vector<int32_t> eg, egm, enode, edest, en, ev_inst, ev_local;
-    std::vector<uint32_t> emeta;
+    std::vector<uint32_t> emeta, esmap;
     std::vector<int32_t> lvl_ptr;
     std::vector<int64_t> lvl_off;   // task offsets of each level
     std::vector<int32_t> task_off;  // event offsets of each task
-    int64_t n_tasks = 0;
+    std::vector<int32_t> priv_off;  // private tasks of (day, unit)
+    std::vector<int32_t> day_slot_off, slot_pos, ev_slot_src, ev_slot_dst;  // days run in LDS
+    std::vector<uint32_t> slot_key;     // per slot: Philox key (seed, replicate id) and set of its node
+    std::vector<int64_t> lvl_ev_off;    // event offsets of each level
+    int64_t n_tasks = 0, n_units = 0;
     std::vector<int32_t> rec_slot;
 };
 
@@ -463,25 +474,57 @@ int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, P
         plan_levels(E, mday.data(), mkind.data(), mnode.data(), mdest.data(), (int32_t)std::max<int64_t>(pk->Np, 1),
                     level.data(), task.data(), &day_levels, pk->D);
     }
-    pk->lvl_ptr.assign(pk->D + 1, 0);
-    for (int32_t d = 0; d < pk->D; ++d) pk->lvl_ptr[d + 1] = pk->lvl_ptr[d] + day_levels[d];
-    pk->n_levels = pk->lvl_ptr[pk->D];
-    // tasks in execution order: by level, then by first event; a task's
-    // events stay together in list order
     int64_t n_tasks = 0;
     for (int64_t e = 0; e < E; ++e) n_tasks = std::max<int64_t>(n_tasks, (int64_t)task[e] + 1);
     pk->n_tasks = n_tasks;
+    // Private tasks: a level-1 run of one node's single-node events touches
+    // only that node, and nothing else touches it before the run in list
+    // order, so it runs in the node's unit of the day kernel right after the
+    // SSA. The levels left are renumbered from 1 (a day whose level 1 held
+    // only private tasks loses it).
+    std::vector<char> priv(n_tasks, 0), ext1(pk->D, 0);
+    if (events_mode == SIM_EVENTS_LEVELS) {
+        for (int64_t e = 0; e < E; ++e)
+            if (level[e] == 1) {
+                if (mkind[e] == SIM_EXTERNAL)
+                    ext1[mday[e]] = 1;
+                else
+                    priv[task[e]] = 1;
+            }
+        for (int64_t e = 0; e < E; ++e)
+            if (!priv[task[e]] && !ext1[mday[e]]) level[e] -= 1;
+        for (int32_t d = 0; d < pk->D; ++d)
+            if (!ext1[d] && day_levels[d] > 0) day_levels[d] -= 1;
+    }
+    pk->lvl_ptr.assign(pk->D + 1, 0);
+    for (int32_t d = 0; d < pk->D; ++d) pk->lvl_ptr[d + 1] = pk->lvl_ptr[d] + day_levels[d];
+    pk->n_levels = pk->lvl_ptr[pk->D];
+    // tasks in execution order: level tasks by level, then by first event;
+    // then private tasks by day, unit and first event; a task's events stay
+    // together in list order
+    const int64_t U = pk->Np / unit_positions(pk->layout);
+    pk->n_units = U;
     std::vector<int64_t> task_glv(n_tasks, 0), task_n(n_tasks, 0), tslot(n_tasks, 0);
     for (int64_t e = 0; e < E; ++e) {
-        task_glv[task[e]] = pk->lvl_ptr[mday[e]] + level[e] - 1;
+        task_glv[task[e]] = priv[task[e]] ? (int64_t)mday[e] * U + mnode[e] / unit_positions(pk->layout)
+                                          : pk->lvl_ptr[mday[e]] + level[e] - 1;
         task_n[task[e]]++;
     }
     pk->lvl_off.assign(pk->n_levels + 1, 0);
-    for (int64_t t = 0; t < n_tasks; ++t) pk->lvl_off[task_glv[t] + 1]++;
+    pk->priv_off.assign((size_t)pk->D * U + 1, 0);
+    for (int64_t t = 0; t < n_tasks; ++t) {
+        if (priv[t])
+            pk->priv_off[task_glv[t] + 1]++;
+        else
+            pk->lvl_off[task_glv[t] + 1]++;
+    }
     for (int64_t i = 0; i < pk->n_levels; ++i) pk->lvl_off[i + 1] += pk->lvl_off[i];
+    pk->priv_off[0] = (int32_t)pk->lvl_off[pk->n_levels];
+    for (size_t i = 0; i + 1 < pk->priv_off.size(); ++i) pk->priv_off[i + 1] += pk->priv_off[i];
     {
         std::vector<int64_t> next(pk->lvl_off.begin(), pk->lvl_off.end() - 1);
-        for (int64_t t = 0; t < n_tasks; ++t) tslot[t] = next[task_glv[t]]++;
+        std::vector<int64_t> pnext(pk->priv_off.begin(), pk->priv_off.end() - 1);
+        for (int64_t t = 0; t < n_tasks; ++t) tslot[t] = priv[t] ? pnext[task_glv[t]]++ : next[task_glv[t]]++;
     }
     pk->task_off.assign(n_tasks + 1, 0);
     for (int64_t t = 0; t < n_tasks; ++t) pk->task_off[tslot[t] + 1] = (int32_t)task_n[t];
@@ -494,6 +537,7 @@ int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, P
     pk->edest.resize(E);
     pk->en.resize(E);
     pk->emeta.resize(E);
+    pk->esmap.resize(E);
     pk->ev_inst = minst;
     pk->ev_local = mlocal;
     for (int64_t e = 0; e < E; ++e) {
@@ -506,6 +550,55 @@ int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, P
         pk->edest[pos] = mdest[e];
         pk->en[pos] = p->ev_n[le];
         pk->emeta[pos] = meta_pack(p->ev_kind[le], column_mask(p, p->ev_select[le]), p->ev_shift[le]);
+        uint32_t smap = 0;
+        for (int c = 0; c < pk->Nc; ++c) {
+            const int32_t sid = p->ev_shift[le];
+            const int to = sid >= 0 ? c + p->N[(size_t)c * p->n_shift + sid] : c;
+            smap |= (uint32_t)(to & 0xF) << (4 * c);
+        }
+        pk->esmap[pos] = smap;
+        if (pos != pk->task_off[tslot[task[e]]]) pk->emeta[pos] |= kMetaCont;
+    }
+    pk->lvl_ev_off.resize(pk->n_levels + 1);
+    for (int64_t i = 0; i <= pk->n_levels; ++i) pk->lvl_ev_off[i] = pk->task_off[pk->lvl_off[i]];
+    // Days whose level tasks fit one workgroup with one lane per node run in
+    // LDS: the distinct nodes their events touch get slots, loaded once,
+    // updated by every level and written back once.
+    pk->day_slot_off.assign(pk->D + 1, 0);
+    pk->ev_slot_src.assign(E, -1);
+    pk->ev_slot_dst.assign(E, -1);
+    if (pk->RL == 1 && events_mode == SIM_EVENTS_LEVELS && n_slots == 0) {
+        std::vector<int32_t> stamp(pk->Np, -1), slot_of(pk->Np, 0);
+        for (int32_t d = 0; d < pk->D; ++d) {
+            const int64_t tb = pk->lvl_off[pk->lvl_ptr[d]], te = pk->lvl_off[pk->lvl_ptr[d + 1]];
+            const size_t start = pk->slot_pos.size();
+            bool ok = te > tb && pk->task_off[te] - pk->task_off[tb] <= kDayEventCap &&
+                      pk->lvl_ptr[d + 1] - pk->lvl_ptr[d] <= kDayLevelCap;
+            auto slot = [&](int32_t pos) {
+                if (stamp[pos] != d) {
+                    stamp[pos] = d;
+                    slot_of[pos] = (int32_t)(pk->slot_pos.size() - start);
+                    pk->slot_pos.push_back(pos);
+                    const int32_t inst = pk->inst[pos];
+                    pk->slot_key.push_back(pk->seed[inst]);
+                    pk->slot_key.push_back(pk->repid[(size_t)inst * pk->R]);
+                    pk->slot_key.push_back((uint32_t)(inst * pk->R));
+                }
+                return slot_of[pos];
+            };
+            for (int64_t t = tb; ok && t < te; ++t)
+                for (int64_t e = pk->task_off[t]; e < pk->task_off[t + 1]; ++e) {
+                    pk->ev_slot_src[e] = slot(pk->enode[e]);
+                    if ((pk->emeta[e] & 3u) == (uint32_t)SIM_EXTERNAL) pk->ev_slot_dst[e] = slot(pk->edest[e]);
+                }
+            if (ok && pk->slot_pos.size() - start > (size_t)kDaySlotCap) ok = false;
+            if (!ok) {
+                pk->slot_pos.resize(start);
+                pk->slot_key.resize(3 * start);
+                for (int64_t e = pk->task_off[tb]; e < pk->task_off[te]; ++e) pk->ev_slot_src[e] = pk->ev_slot_dst[e] = -1;
+            }
+            pk->day_slot_off[d + 1] = (int32_t)pk->slot_pos.size();
+        }
     }
     pk->rec_slot.assign(std::max(pk->D, 1), -1);
     for (int k = 0; k < p0->n_record; ++k) pk->rec_slot[p0->record_days[k]] = k;
@@ -514,7 +607,7 @@ int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, P
 
 Layout layout_of(const Packed &pk, const sim_problem *p0) {
     return layout_for(pk.Np, pk.n_nodes, pk.n_inst, pk.Nc, pk.Nt, pk.R, pk.RL, pk.D, pk.n_events, p0->n_shift,
-                      pk.n_levels, pk.n_tasks, pk.n_record, pk.n_slots);
+                      pk.n_levels, pk.n_tasks, pk.n_units, (int64_t)pk.slot_pos.size(), pk.n_record, pk.n_slots);
 }
 
 }  // namespace
@@ -530,6 +623,8 @@ struct sim_handle {
     std::vector<int32_t> ev_inst, ev_local, ev_day;  // merged event index -> instance, local index, day
     std::vector<int64_t> lvl_off;   // host copy of the level boundaries (task offsets)
     std::vector<int32_t> lvl_ptr;   // [D+1]
+    std::vector<int32_t> day_slot_off;  // [D+1]: a day with slots runs its levels in LDS
+    std::vector<int64_t> lvl_ev_off;    // host copy of the event offsets of each level
     Layout lay{};
     void *ws = nullptr;
     bool own_ws = false;
@@ -694,6 +789,8 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
     h->node_id = pk.node_id;
     h->lvl_off = pk.lvl_off;
     h->lvl_ptr = pk.lvl_ptr;
+    h->day_slot_off = pk.day_slot_off;
+    h->lvl_ev_off = pk.lvl_ev_off;
     h->ev_inst = pk.ev_inst;
     h->ev_local = pk.ev_local;
     h->ev_day.resize(pk.n_events);
@@ -770,7 +867,6 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
     s.alpha = at<double>(h->ws, l.alpha);
     s.beta = at<double>(h->ws, l.beta);
     s.repid = at<uint32_t>(h->ws, l.repid);
-    s.shift = at<int32_t>(h->ws, l.shift);
     s.status = at<unsigned long long>(h->ws, l.status);
     s.prevalence = at<int32_t>(h->ws, l.prevalence);
     s.transitions = at<int64_t>(h->ws, l.transitions);
@@ -786,13 +882,18 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
     ev.dest = at<int32_t>(h->ws, l.ev_dest);
     ev.n = at<int32_t>(h->ws, l.ev_n);
     ev.meta = at<uint32_t>(h->ws, l.ev_meta);
+    ev.smap = at<uint32_t>(h->ws, l.ev_smap);
     ev.task_off = at<int32_t>(h->ws, l.task_off);
+    ev.priv_off = at<int32_t>(h->ws, l.priv_off);
+    ev.day_slot_off = at<int32_t>(h->ws, l.day_slot_off);
+    ev.slot_pos = at<int32_t>(h->ws, l.slot_pos);
+    ev.slot_key = at<uint32_t>(h->ws, l.slot_key);
+    ev.lvl_ev_off = at<int64_t>(h->ws, l.lvl_ev_off);
+    ev.slot_src = at<int32_t>(h->ws, l.ev_slot_src);
+    ev.slot_dst = at<int32_t>(h->ws, l.ev_slot_dst);
     ev.lvl_off = at<int64_t>(h->ws, l.lvl_off);
     ev.lvl_ptr = at<int32_t>(h->ws, l.lvl_ptr);
 
-    std::vector<int32_t> shift(MAXC * std::max<int64_t>(p->n_shift, 1), 0);
-    for (int hh = 0; hh < p->n_shift; ++hh)
-        for (int c = 0; c < h->Nc; ++c) shift[hh * MAXC + c] = p->N[(size_t)c * p->n_shift + hh];
     const unsigned long long ok = STATUS_OK;
     const int64_t S = (int64_t)h->n_inst * h->R, E = pk.n_events;
 
@@ -810,14 +911,21 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
         {(void *)s.alpha, pk.alpha.data(), sizeof(double) * S},
         {(void *)s.beta, pk.beta.data(), sizeof(double) * S * 4},
         {(void *)s.repid, pk.repid.data(), sizeof(uint32_t) * S},
-        {(void *)s.shift, shift.data(), sizeof(int32_t) * shift.size()},
         {(void *)ev.g, pk.eg.data(), sizeof(int32_t) * E},
         {(void *)ev.gm, pk.egm.data(), sizeof(int32_t) * E},
         {(void *)ev.node, pk.enode.data(), sizeof(int32_t) * E},
         {(void *)ev.dest, pk.edest.data(), sizeof(int32_t) * E},
         {(void *)ev.n, pk.en.data(), sizeof(int32_t) * E},
         {(void *)ev.meta, pk.emeta.data(), sizeof(uint32_t) * E},
+        {(void *)ev.smap, pk.esmap.data(), sizeof(uint32_t) * E},
         {(void *)ev.task_off, pk.task_off.data(), sizeof(int32_t) * (pk.n_tasks + 1)},
+        {(void *)ev.priv_off, pk.priv_off.data(), sizeof(int32_t) * pk.priv_off.size()},
+        {(void *)ev.day_slot_off, pk.day_slot_off.data(), sizeof(int32_t) * pk.day_slot_off.size()},
+        {(void *)ev.slot_pos, pk.slot_pos.data(), sizeof(int32_t) * pk.slot_pos.size()},
+        {(void *)ev.slot_key, pk.slot_key.data(), sizeof(uint32_t) * pk.slot_key.size()},
+        {(void *)ev.lvl_ev_off, pk.lvl_ev_off.data(), sizeof(int64_t) * pk.lvl_ev_off.size()},
+        {(void *)ev.slot_src, pk.ev_slot_src.data(), sizeof(int32_t) * pk.ev_slot_src.size()},
+        {(void *)ev.slot_dst, pk.ev_slot_dst.data(), sizeof(int32_t) * pk.ev_slot_dst.size()},
         {(void *)ev.lvl_off, pk.lvl_off.data(), sizeof(int64_t) * (pk.n_levels + 1)},
         {(void *)ev.lvl_ptr, pk.lvl_ptr.data(), sizeof(int32_t) * (h->D + 1)},
         {(void *)s.rec_slot, pk.rec_slot.data(), sizeof(int32_t) * h->D},
@@ -924,11 +1032,21 @@ int sim_run(sim_handle *h, int32_t n_days) {
         if (e != hipSuccess) return h->err = fmt("persistent launch: %s %s", hipGetErrorString(e), why), SIM_EDEVICE;
     } else {
         for (int32_t d = d0; d < d1; ++d) {
-            hipError_t e = timed(h, SIM_K_DAY, [&] { return launch_day(h->model, h->st, d, d > d0, 1, h->layout, h->stream); });
+            hipError_t e = timed(h, SIM_K_DAY, [&] { return launch_day(h->model, h->st, h->ev, d, d > d0, 1, h->layout, h->stream); });
             if (e != hipSuccess) return h->err = fmt("day kernel: %s", hipGetErrorString(e)), SIM_EDEVICE;
-            // big levels get a launch of their own; runs of small ones share one workgroup
+            // a day that fits runs its levels in LDS; otherwise big levels get a
+            // launch of their own and runs of small ones share one workgroup
             int32_t lv = h->lvl_ptr[d];
             const int32_t lv_end = h->lvl_ptr[d + 1];
+            if (h->day_slot_off[d + 1] > h->day_slot_off[d]) {
+                const int32_t s0 = h->day_slot_off[d], ns = h->day_slot_off[d + 1] - s0;
+                const int64_t e0 = h->lvl_ev_off[lv], ne = h->lvl_ev_off[lv_end] - e0;
+                e = timed(h, SIM_K_EVENTS, [&] {
+                    return launch_event_day(h->model, h->st, h->ev, d, lv, lv_end - lv, s0, ns, e0, ne, h->stream);
+                });
+                if (e != hipSuccess) return h->err = fmt("event kernel: %s", hipGetErrorString(e)), SIM_EDEVICE;
+                lv = lv_end;
+            }
             while (lv < lv_end) {
                 const int64_t size = (h->lvl_off[lv + 1] - h->lvl_off[lv]) * h->RL;
                 if (size > kSmallLevel) {
@@ -946,7 +1064,7 @@ int sim_run(sim_handle *h, int32_t n_days) {
                 if (e != hipSuccess) return h->err = fmt("event kernel: %s", hipGetErrorString(e)), SIM_EDEVICE;
             }
         }
-        hipError_t e = timed(h, SIM_K_CLOSE, [&] { return launch_day(h->model, h->st, d1, 1, 0, h->layout, h->stream); });
+        hipError_t e = timed(h, SIM_K_CLOSE, [&] { return launch_day(h->model, h->st, h->ev, d1, 1, 0, h->layout, h->stream); });
         if (e != hipSuccess) return h->err = fmt("closing kernel: %s", hipGetErrorString(e)), SIM_EDEVICE;
     }
     h->day = d1;
@@ -1197,7 +1315,7 @@ int sim_slots_step(sim_handle *h, int32_t *finished, int32_t *n_finished) {
             size[k] = std::max(size[k], (h->lvl_off[lv + 1] - h->lvl_off[lv]) * 64);  // tasks x lanes
         }
     }
-    hipError_t e = timed(h, SIM_K_DAY, [&] { return launch_day(h->model, h->st, T, 1, 1, LAYOUT_TILE, h->stream); });
+    hipError_t e = timed(h, SIM_K_DAY, [&] { return launch_day(h->model, h->st, h->ev, T, 1, 1, LAYOUT_TILE, h->stream); });
     if (e != hipSuccess) return h->err = fmt("day kernel: %s", hipGetErrorString(e)), SIM_EDEVICE;
     // big levels get a launch of their own; runs of small ones one workgroup per slot
     int32_t k = 0;

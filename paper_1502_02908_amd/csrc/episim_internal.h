@@ -10,9 +10,9 @@
 //                       that a wavefront's loads of one compartment coalesce
 //   phi[l]              binary64 environmental infectious pressure
 //   events              SoA in execution order (day, then level, then task,
-//                       then list order), 24 bytes per event: global index g,
+//                       then list order), 28 bytes per event: global index g,
 //                       merged index, node, dest, n, packed meta (kind,
-//                       select mask, shift id)
+//                       select mask, shift id), compartment map of the shift
 #pragma once
 #include <cstdint>
 
@@ -23,11 +23,13 @@ constexpr int MAXT = 8;
 constexpr unsigned long long STATUS_OK = ~0ull;  // else (g << 32) | replicate of an infeasible event
 constexpr unsigned long long STATUS_LIMIT_TAG = 0xFFFFFFFEull;  // high word when a node hit SIM_MAX_FIRED
 
-// meta word of an event: bits 0-1 kind, bits 2-9 select mask, bits 10-15 shift id + 1 (0 = none)
+// meta word of an event: bits 0-1 kind, bits 2-9 select mask, bits 10-15 shift id + 1 (0 = none),
+// bit 16 set when the event continues the task of the event before it
 __host__ __device__ inline uint32_t meta_pack(int kind, uint32_t mask, int shift) {
     return (uint32_t)kind | (mask << 2) | ((uint32_t)(shift + 1) << 10);
 }
 constexpr int MAX_SHIFT_IDS = 63;
+constexpr uint32_t kMetaCont = 1u << 16;
 
 // Model description, passed by value (lands in the kernel-argument segment,
 // read with scalar loads).
@@ -71,7 +73,6 @@ struct DevState {
     const double *alpha;        // [sets]
     const double *beta;         // [sets][4]
     const uint32_t *repid;      // [sets] second Philox key word
-    const int32_t *shift;       // [n_shift_ids][MAXC] compartment offsets
     unsigned long long *status; // first infeasible event, or STATUS_OK ([RL / 64] in a slot handle)
     SlotInfo *slots;            // [RL / 64] slot table of a slot handle, null otherwise
     // daily records
@@ -90,8 +91,20 @@ struct DevEvents {
     const int32_t *dest;
     const int32_t *n;
     const uint32_t *meta;
+    const uint32_t *smap;       // per event: landing compartment of each source compartment, 4 bits each
     const int32_t *task_off;    // task boundaries into the arrays above (a task's events in list order)
     const int64_t *lvl_off;     // level boundaries into the tasks
+    const int32_t *priv_off;    // [D * n_units + 1]: private tasks of unit u on day d are
+                                // priv_off[d * n_units + u] .. priv_off[d * n_units + u + 1] - 1
+    // days run in LDS (one lane per node): the positions their level tasks touch
+    // are slot_pos[day_slot_off[d]] ..; slot_src / slot_dst give each event's
+    // slot of its node / destination on such a day, -1 otherwise
+    const int32_t *day_slot_off;
+    const int32_t *slot_pos;
+    const uint32_t *slot_key;   // [3 per slot] Philox key (seed, replicate id) and set of the slot's node
+    const int64_t *lvl_ev_off;  // event offsets of each level
+    const int32_t *slot_src;
+    const int32_t *slot_dst;
     const int32_t *lvl_ptr;     // [D+1]: levels of day d are lvl_ptr[d] .. lvl_ptr[d+1]-1
 };
 
@@ -99,18 +112,32 @@ struct DevEvents {
 // or tiles of kTileNodes nodes x 64 replicate lanes per workgroup (R > 1,
 // lane stride RL a multiple of 64).
 constexpr int kTileNodes = 128;
+constexpr int kLaneUnit = 256;  // positions of one workgroup with one lane per node
 enum { LAYOUT_LANES = 0, LAYOUT_TILE = 1 };
 
+// Positions per unit of the day phase (a workgroup's nodes); a private task
+// (a level-1 run of one node's single-node events) runs in its node's unit
+// right after the SSA.
+inline int64_t unit_positions(int layout) { return layout == LAYOUT_TILE ? kTileNodes : kLaneUnit; }
+
 // Host-side launchers (episim_device.hip). Each returns a hipError_t as int.
-int launch_day(const Model &m, const DevState &s, int32_t d, int prologue, int ssa, int layout,
-               void *stream);
+int launch_day(const Model &m, const DevState &s, const DevEvents &ev, int32_t d, int prologue, int ssa,
+               int layout, void *stream);
 int launch_events(const Model &m, const DevState &s, const DevEvents &ev, int32_t d, int64_t begin,
                   int64_t end, void *stream);
 int launch_event_levels(const Model &m, const DevState &s, const DevEvents &ev, int32_t d, int32_t lv_begin,
                         int32_t lv_end, void *stream);
-// levels of at most this many (event, replicate) pairs are grouped into one
+// levels of at most this many (task, replicate) pairs are grouped into one
 // single-workgroup launch
 constexpr int64_t kSmallLevel = 512;
+// a day with one lane per node, at most kDayEventCap level events in at most
+// kDayLevelCap levels and at most kDaySlotCap distinct nodes touched by them
+// runs its levels in LDS
+constexpr int64_t kDayEventCap = 512;
+constexpr int64_t kDaySlotCap = 768;
+constexpr int64_t kDayLevelCap = 64;
+int launch_event_day(const Model &m, const DevState &s, const DevEvents &ev, int32_t d, int32_t lv0, int32_t nl,
+                     int32_t s0, int32_t ns, int64_t e0, int64_t ne, void *stream);
 int launch_slot_events(const Model &m, const DevState &s, const DevEvents &ev, int32_t step, int32_t k,
                        int32_t k_end, int64_t max_count, void *stream);
 int launch_slot_init(const DevState &s, int32_t nc, const int32_t *u0, const double *v0, int32_t slot,
