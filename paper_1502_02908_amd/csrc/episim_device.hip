@@ -730,12 +730,57 @@ __global__ __launch_bounds__(kBlock) void k_day(Model m, DevState s, DevEvents e
 // always holds the same replicate and its counts add up in registers.
 // In a slot handle, column y is slot y: d is the handle's step, the slot's own
 // day is d - t0, and the slot's lanes past its replicate count are idle.
+//
+// Past the regular tiles, workgroups of four wavefronts take the heavy herds:
+// each wavefront one (herd, replicate) chain, walked with the whole wavefront
+// (kHeavyBlocks workgroups cover the 64 replicate lanes of a column), then the
+// herd's private task for that replicate; the units holding heavy herds are
+// skipped by the regular tiles.
+constexpr int kHeavyBlocks = 64 / kWaves;
+
+template <class Rules>
+__device__ __forceinline__ void heavy_chain(const Model &m, const DevState &s, const DevEvents &ev, int64_t hb,
+                                            int32_t d, bool prologue, bool ssa, int32_t r_end,
+                                            unsigned long long *status) {
+    constexpr int NC = Rules::NC;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int32_t pos = s.heavy_pos[hb / kHeavyBlocks];
+    const int32_t r = (int32_t)blockIdx.y * 64 + (int32_t)(hb % kHeavyBlocks) * kWaves + wave;
+    Tally<NC> t{};
+    day_wave<Rules>(m, s, lane == 0 ? (int64_t)pos * s.RL + r : s.L, d, prologue, ssa, t, r_end, status);
+    if (r >= r_end) return;
+    const int32_t inst = s.inst[pos];
+    const int64_t S = (int64_t)s.n_inst * s.R;
+    const int64_t set = (int64_t)inst * s.R + r;
+    if (lane == 0) {
+        if (prologue) {
+            if (t.prev) atomicAdd(&s.prevalence[(d - 1) * S + set], (int32_t)t.prev);
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                if (comp_on<NC>(m, c) && t.tot[c])
+                    atomicAdd((unsigned long long *)&s.totals[((d - 1) * S + set) * m.nc + c], (unsigned long long)t.tot[c]);
+        }
+        if (ssa && t.trans) atomicAdd((unsigned long long *)&s.transitions[d * S + set], (unsigned long long)t.trans);
+    }
+    if (!ssa) return;
+    // the herd's private task of the day (at most one per node and day), run
+    // by another lane of this wavefront: lane 0's stores first, then fresh lines
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    fresh_l1();
+    const int64_t k = (int64_t)d * (s.Np / kTileNodes) + pos / kTileNodes;
+    const int64_t t0 = ev.priv_off[k], t1 = ev.priv_off[k + 1];
+    for (int64_t tk = t0 + lane; tk < t1; tk += 64)
+        if (ev.node[ev.task_off[tk]] == pos) event_task<NC>(m, s, ev, tk, r, d, status);
+}
+
 template <class Rules>
 __global__ __launch_bounds__(kBlock) void k_day_tile(Model m, DevState s, DevEvents ev, int32_t d,
                                                      int32_t prologue, int32_t ssa) {
     constexpr int NC = Rules::NC;
     int32_t r_end = s.R;
     unsigned long long *status = s.status;
+    const int64_t nx = s.Np / kTileNodes;
+    if (s.n_heavy && blockIdx.x < nx && s.unit_heavy[blockIdx.x]) return;  // uniform over the workgroup
     if (s.slots) {
         const SlotInfo si = s.slots[blockIdx.y];
         const int32_t ds = d - si.t0;
@@ -747,6 +792,10 @@ __global__ __launch_bounds__(kBlock) void k_day_tile(Model m, DevState s, DevEve
         status += blockIdx.y;
     }
     if (!block_ok(status)) return;
+    if (blockIdx.x >= nx) {
+        heavy_chain<Rules>(m, s, ev, blockIdx.x - nx, d, prologue != 0, ssa != 0, r_end, status);
+        return;
+    }
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t pos0 = (int64_t)blockIdx.x * kTileNodes;
     const int32_t r = (int32_t)blockIdx.y * 64 + lane;
@@ -1352,7 +1401,7 @@ int launch_day(const Model &m, const DevState &s, const DevEvents &ev, int32_t d
     int32_t dd = d, pro = prologue, sa = ssa;
     void *args[] = {&mm, &ss, &ee, &dd, &pro, &sa};
     if (layout == LAYOUT_TILE) {
-        const unsigned nx = (unsigned)((s.Np + kTileNodes - 1) / kTileNodes);
+        const unsigned nx = (unsigned)((s.Np + kTileNodes - 1) / kTileNodes + (int64_t)s.n_heavy * kHeavyBlocks);
         return (int)hipLaunchKernel(t.tile, dim3(nx, (unsigned)(s.RL / 64)), dim3(kBlock), args, 0,
                                     (hipStream_t)stream);
     }

@@ -260,26 +260,50 @@ int64_t pad_nodes(int layout) { return unit_positions(layout); /* one workgroup 
 // attempt. Returns the number of positions (a multiple of the padding
 // granule); pos_node[pos] = node or -1.
 constexpr int64_t kSoloHerds = 128;
+// With replicate tiles, the largest herds of an instance (at most
+// kHeavyHerds, and one per 64 nodes) get units of their own whose every
+// (herd, replicate) chain is walked by a wavefront of its own; they are placed
+// first, the remaining positions of their units stay empty.
+constexpr int64_t kHeavyHerds = 32;
 
-int64_t order_nodes(const sim_problem *p, int layout, std::vector<int32_t> *pos_node) {
+int64_t order_nodes(const sim_problem *p, int layout, int64_t heavy, std::vector<int32_t> *pos_node) {
     const int64_t Nn = p->n_nodes, Nc = p->n_comp;
-    std::vector<int64_t> size(Nn, 0);
-    for (int64_t i = 0; i < Nn; ++i)
-        for (int64_t c = 0; c < Nc; ++c) size[i] += p->u0[i * Nc + c];
+    // a herd's size is its largest population over the horizon: the SSA only
+    // moves individuals between compartments of a node, so node totals follow
+    // from the initial state and the events alone (hubs that receive many
+    // movements grow well past their initial size)
+    std::vector<int64_t> now(Nn, 0), size(Nn, 0);
+    for (int64_t i = 0; i < Nn; ++i) {
+        for (int64_t c = 0; c < Nc; ++c) now[i] += p->u0[i * Nc + c];
+        size[i] = now[i];
+    }
+    for (int64_t e = 0; e < p->n_events; ++e) {
+        const int32_t i = p->ev_node[e], k = p->ev_kind[e], n = p->ev_n[e];
+        if (k == SIM_ENTER) now[i] += n;
+        if (k == SIM_EXIT || k == SIM_EXTERNAL) now[i] -= n;
+        if (k == SIM_EXTERNAL) {
+            now[p->ev_dest[e]] += n;
+            size[p->ev_dest[e]] = std::max(size[p->ev_dest[e]], now[p->ev_dest[e]]);
+        }
+        size[i] = std::max(size[i], now[i]);
+    }
     std::vector<int32_t> rank(Nn);
     for (int64_t i = 0; i < Nn; ++i) rank[i] = (int32_t)i;
     std::stable_sort(rank.begin(), rank.end(), [&](int32_t a, int32_t b) { return size[a] > size[b]; });
     const int64_t G = unit_nodes(layout), P = pad_nodes(layout);
     // solo wavefronts only pay off when the rest still fills many wavefronts
     const int64_t solo = (layout == LAYOUT_LANES && Nn >= 64 * kSoloHerds) ? kSoloHerds : 0;
-    const int64_t rest = Nn - solo;
-    const int64_t body = solo * 64 + rest;
+    const int64_t hv = layout == LAYOUT_TILE ? std::min(heavy, Nn) : 0;
+    const int64_t hv_span = ((hv + G - 1) / G) * G;
+    const int64_t rest = Nn - solo - hv;
+    const int64_t body = solo * 64 + hv_span + rest;
     const int64_t Np = Nn == 0 ? 0 : ((body + P - 1) / P) * P;
     pos_node->assign(Np, -1);
     for (int64_t q = 0; q < solo; ++q) (*pos_node)[q * 64] = rank[q];
-    const int64_t base = solo * 64;
+    for (int64_t q = 0; q < hv; ++q) (*pos_node)[q] = rank[q];
+    const int64_t base = solo * 64 + hv_span;
     const int64_t U = (Np - base) / G;
-    int64_t q = solo;
+    int64_t q = solo + hv;
     for (int64_t j = 0; j < G && q < Nn; ++j)
         for (int64_t uu = 0; uu < U && q < Nn; ++uu) {
             const int64_t u = (j & 1) ? U - 1 - uu : uu;
@@ -292,14 +316,14 @@ int64_t order_nodes(const sim_problem *p, int layout, std::vector<int32_t> *pos_
 struct Layout {
     size_t u, phi, node_id, inst, inst_off, seed, coef, alpha, beta, repid, status, ev_g, ev_gm, ev_node,
         ev_dest, ev_n, ev_meta, ev_smap, task_off, priv_off, day_slot_off, slot_pos, slot_key, lvl_ev_off, ev_slot_src, ev_slot_dst, lvl_off, lvl_ptr, prevalence, transitions, totals, snap_u, snap_v, rec_slot, slots,
-        u0, v0, total;
+        u0, v0, heavy_pos, unit_heavy, total;
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 Layout layout_for(int64_t Np, int64_t n_nodes, int64_t n_inst, int64_t Nc, int64_t Nt, int64_t R, int64_t RL,
                   int64_t D, int64_t n_events, int64_t n_shift_ids, int64_t n_levels, int64_t n_tasks,
-                  int64_t n_units, int64_t n_day_slots, int64_t n_record, int64_t n_slots) {
+                  int64_t n_units, int64_t n_day_slots, int64_t n_record, int64_t n_slots, int64_t n_heavy) {
     Layout l{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -344,6 +368,8 @@ Layout layout_for(int64_t Np, int64_t n_nodes, int64_t n_inst, int64_t Nc, int64
     l.rec_slot = take(sizeof(int32_t) * D);
     // slot handles: the slot table and the network's initial state by position
     l.slots = take(sizeof(SlotInfo) * n_slots);
+    l.heavy_pos = take(sizeof(int32_t) * n_heavy);
+    l.unit_heavy = take(n_units);
     l.u0 = take(n_slots ? sizeof(int32_t) * Nc * Np : 0);
     l.v0 = take(n_slots ? sizeof(double) * Np : 0);
     l.total = off;
@@ -365,6 +391,8 @@ struct Packed {
     std::vector<int64_t> lvl_off;   // task offsets of each level
     std::vector<int32_t> task_off;  // event offsets of each task
     std::vector<int32_t> priv_off;  // private tasks of (day, unit)
+    std::vector<int32_t> heavy_pos; // positions of the herds whose chains get a wavefront each
+    std::vector<uint8_t> unit_heavy;
     std::vector<int32_t> day_slot_off, slot_pos, ev_slot_src, ev_slot_dst;  // days run in LDS
     std::vector<uint32_t> slot_key;     // per slot: Philox key (seed, replicate id) and set of its node
     std::vector<int64_t> lvl_ev_off;    // event offsets of each level
@@ -375,7 +403,7 @@ struct Packed {
 // n_slots > 0 builds a slot handle of one network: n_slots columns of 64
 // replicate lanes, parameters supplied later slot by slot.
 int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, Packed *pk, std::string *err,
-                 int32_t n_slots = 0) {
+                 int32_t n_slots = 0, int32_t launch = SIM_LAUNCH_KERNELS) {
     if (n < 1 || !ps) return *err = "no problems", SIM_EINVAL;
     for (int32_t k = 0; k < n; ++k) {
         int rc = validate(ps[k], err);
@@ -408,12 +436,18 @@ int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, P
     for (int32_t k = 0; k < n; ++k) {
         pk->inst_off[k] = (int32_t)pk->n_nodes;
         pk->inst_pos0[k] = (int32_t)pk->Np;
-        pk->Np += order_nodes(ps[k], pk->layout, &pos_node[k]);
+        const int64_t heavy = (pk->layout == LAYOUT_TILE && launch == SIM_LAUNCH_KERNELS)
+                                  ? std::min<int64_t>(kHeavyHerds, ps[k]->n_nodes / 64) : 0;
+        const int64_t np_k = order_nodes(ps[k], pk->layout, heavy, &pos_node[k]);
+        for (int64_t j = 0; j < heavy; ++j) pk->heavy_pos.push_back((int32_t)(pk->Np + j));
+        pk->Np += np_k;
         pk->n_nodes += ps[k]->n_nodes;
         pk->n_events += ps[k]->n_events;
     }
     if (pk->Np * (int64_t)pk->RL > INT32_MAX) return *err = "positions x replicate lanes must stay below 2^31", SIM_EINVAL;
     if (pk->n_events > INT32_MAX) return *err = "too many events", SIM_EINVAL;
+    pk->unit_heavy.assign(pk->Np / unit_positions(pk->layout), 0);
+    for (int32_t hp : pk->heavy_pos) pk->unit_heavy[hp / unit_positions(pk->layout)] = 1;
     pk->node_id.assign(pk->Np, -1);
     pk->inst.assign(pk->Np, 0);
     pk->lane_of.assign(pk->n_nodes, 0);
@@ -607,7 +641,8 @@ int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, P
 
 Layout layout_of(const Packed &pk, const sim_problem *p0) {
     return layout_for(pk.Np, pk.n_nodes, pk.n_inst, pk.Nc, pk.Nt, pk.R, pk.RL, pk.D, pk.n_events, p0->n_shift,
-                      pk.n_levels, pk.n_tasks, pk.n_units, (int64_t)pk.slot_pos.size(), pk.n_record, pk.n_slots);
+                      pk.n_levels, pk.n_tasks, pk.n_units, (int64_t)pk.slot_pos.size(), pk.n_record, pk.n_slots,
+                      (int64_t)pk.heavy_pos.size());
 }
 
 }  // namespace
@@ -765,7 +800,7 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
         return g_create_error = "unknown launch mode", SIM_EINVAL;
     Packed pk;
     if (n_slots > 0 && opts.events_mode != SIM_EVENTS_LEVELS) return g_create_error = "slot handles run event levels", SIM_EINVAL;
-    int rc = build_packed(ps, n, opts.events_mode, &pk, &g_create_error, n_slots);
+    int rc = build_packed(ps, n, opts.events_mode, &pk, &g_create_error, n_slots, opts.launch);
     if (rc != SIM_OK) return rc;
     const sim_problem *p = ps[0];
 
@@ -875,6 +910,9 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
     s.snap_v = at<double>(h->ws, l.snap_v);
     s.rec_slot = at<int32_t>(h->ws, l.rec_slot);
     s.slots = h->n_slots ? at<SlotInfo>(h->ws, l.slots) : nullptr;
+    s.n_heavy = (int32_t)pk.heavy_pos.size();
+    s.heavy_pos = at<int32_t>(h->ws, l.heavy_pos);
+    s.unit_heavy = s.n_heavy ? at<uint8_t>(h->ws, l.unit_heavy) : nullptr;
     DevEvents &ev = h->ev;
     ev.g = at<int32_t>(h->ws, l.ev_g);
     ev.gm = at<int32_t>(h->ws, l.ev_gm);
@@ -929,6 +967,8 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
         {(void *)ev.lvl_off, pk.lvl_off.data(), sizeof(int64_t) * (pk.n_levels + 1)},
         {(void *)ev.lvl_ptr, pk.lvl_ptr.data(), sizeof(int32_t) * (h->D + 1)},
         {(void *)s.rec_slot, pk.rec_slot.data(), sizeof(int32_t) * h->D},
+        {(void *)s.heavy_pos, pk.heavy_pos.data(), sizeof(int32_t) * pk.heavy_pos.size()},
+        {(void *)s.unit_heavy, pk.unit_heavy.data(), s.n_heavy ? pk.unit_heavy.size() : 0},
     };
     for (const Up &up : ups) {
         if (up.bytes == 0) continue;
@@ -994,7 +1034,9 @@ int sim_plan_levels(int64_t n_events, const int32_t *ev_day, const int32_t *ev_k
 size_t sim_workspace_bytes_batch(const sim_problem *const *problems, int32_t n_problems, const sim_device_opts *o) {
     std::string err;
     Packed pk;
-    if (build_packed(problems, n_problems, o ? o->events_mode : SIM_EVENTS_LEVELS, &pk, &err) != SIM_OK) return 0;
+    if (build_packed(problems, n_problems, o ? o->events_mode : SIM_EVENTS_LEVELS, &pk, &err, 0,
+                     o ? o->launch : SIM_LAUNCH_KERNELS) != SIM_OK)
+        return 0;
     return layout_of(pk, problems[0]).total;
 }
 

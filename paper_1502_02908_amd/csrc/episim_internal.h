@@ -75,6 +75,11 @@ struct DevState {
     const uint32_t *repid;      // [sets] second Philox key word
     unsigned long long *status; // first infeasible event, or STATUS_OK ([RL / 64] in a slot handle)
     SlotInfo *slots;            // [RL / 64] slot table of a slot handle, null otherwise
+    // replicate tiles: the herds whose every (herd, replicate) chain gets a
+    // wavefront of its own, and the units that hold only such herds
+    int32_t n_heavy;
+    const int32_t *heavy_pos;   // [n_heavy]
+    const uint8_t *unit_heavy;  // [n_units], null if n_heavy == 0
     // daily records
     int32_t *prevalence;        // [D][sets]
     int64_t *transitions;       // [D][sets]
