@@ -315,7 +315,9 @@ __device__ __forceinline__ void pairs_walk_block(const Model &m, Chain<2 * NP, 2
                                                  uint32_t node, uint32_t day, uint32_t key0, uint32_t key1,
                                                  unsigned long long *status, int32_t r) {
     constexpr int NT = 2 * NP;
+    __shared__ double sh_tau[kWaves][64];
     const uint32_t lane = threadIdx.x & 63u;
+    const int wave = threadIdx.x >> 6;
     const unsigned long long below = (1ull << lane) - 1ull;
     for (;;) {
         const Word4 o = philox4x32_10(Word4{kbase + lane, node, day, 0u}, key0, key1);
@@ -358,17 +360,23 @@ __device__ __forceinline__ void pairs_walk_block(const Model &m, Chain<2 * NP, 2
             if (!changed) break;
         }
         const double tau = E / lam;  // lambda = 0: tau = inf, never fires
-        // the clock, attempt by attempt; most rounds end below the window end
+        // the clock, attempt by attempt; most rounds end below the window end.
+        // The waiting times go through LDS and come back as broadcast reads,
+        // which issue ahead of the dependent additions.
+        sh_tau[wave][lane] = tau;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         double t = c.clock;
 #pragma unroll 16
-        for (int i = 0; i < 64; ++i) t = t + lane_f64(tau, i);
+        for (int i = 0; i < 64; ++i) t = t + sh_tau[wave][i];
         int A = 64;
         double clock = t;
         if (!(t < 1.0)) {
             double s = c.clock, mine = 0.0;
 #pragma unroll 16
             for (int i = 0; i < 64; ++i) {
-                s = s + lane_f64(tau, i);
+                s = s + sh_tau[wave][i];
                 if ((int)lane == i) mine = s;
             }
             A = __popcll(__ballot(mine < 1.0));
@@ -397,6 +405,7 @@ __device__ __forceinline__ void pairs_walk_block(const Model &m, Chain<2 * NP, 2
         }
         if (A < 64 || !(c.lam > 0.0)) return;
         kbase = kbase + 64;
+        __builtin_amdgcn_wave_barrier();  // the next round rewrites sh_tau
     }
 }
 
