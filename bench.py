@@ -46,12 +46,13 @@ def algorithmic_bytes(p, day_launches, ev_counts_by_kind):
     return node_days * per_node_day, ev_bytes, per_node_day
 
 
-def counter_traffic(kernel):
+def counter_traffic(kernel, workload):
     """HBM bytes per launch of kernel from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE scaled by a copy of known size), or
-    None if the kernel source changed since the counters were taken."""
+    summary of the workload (FETCH_SIZE and WRITE_SIZE scaled by a copy of
+    known size), or None if there is none or the kernel source changed since
+    the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "hbm_counters_sise3_37k.txt")
+    path = os.path.join(ROOT, "profiles", f"hbm_counters_{workload.replace('-', '_')}.txt")
     src = os.path.join(ROOT, "paper_1502_02908_amd", "csrc", "episim_device.hip")
     if not os.path.exists(path):
         return None
@@ -123,21 +124,116 @@ def batched_leg(P, synth, torch, steps, plain_sample):
         speedup_vs_plain=round(t_plain / t_batch * R, 2))
 
 
+def instances_leg(P, synth, torch, n_inst=64, days=730):
+    """Uneven instances: 64 SISe3 networks with node counts log-uniform in
+    [1e3, 2e5] (seeds 4000 + j), one trajectory each with its own prior-box
+    parameters, over 730 days, packed into one handle against the same
+    instances run one handle each."""
+    import numpy as np
+    rng = np.random.default_rng(4)
+    sizes = np.exp(rng.uniform(np.log(1e3), np.log(2e5), n_inst)).astype(int)
+    coef, alpha, beta = synth.prior_draws(n_inst, seed=4)
+    t0 = time.perf_counter()
+    insts = [synth.sise3_network(n_nodes=int(n), n_days=days, seed=4000 + j).with_replicates(
+        1, coef=coef[j:j + 1], alpha=alpha[j:j + 1], beta=beta[j:j + 1]) for j, n in enumerate(sizes)]
+    print(f"[bench] {n_inst} instances ({int(sizes.sum())} nodes) generated in {time.perf_counter() - t0:.0f} s",
+          file=sys.stderr, flush=True)
+    sim = P.Simulator(insts)
+    u0 = np.concatenate([q.u0 for q in insts])[None]
+    v0 = np.concatenate([q.v0 for q in insts])[None]
+    times = []
+    for k in range(3):
+        sim.set_state(u0, v0, 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.run(0)
+        sim.sync()
+        torch.cuda.synchronize()
+        if k > 0:
+            times.append(time.perf_counter() - t0)
+    sim.close()
+    t_pack = min(times)
+    t_plain = 0.0
+    for q in insts:
+        with P.Simulator(q) as s1:
+            s1.run(0)
+            s1.sync()
+            s1.set_state(q.u0[None], q.v0[None], 0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s1.run(0)
+            s1.sync()
+            torch.cuda.synchronize()
+            t_plain += time.perf_counter() - t0
+    nd = float(sizes.sum()) * days
+    return dict(workload=f"{n_inst} SISe3 instances, {int(sizes.min())}-{int(sizes.max())} nodes "
+                         f"({int(sizes.sum())} in all), 1 trajectory each, {days} days",
+                instances_per_s=round(n_inst / t_pack, 3), ms_packed=round(t_pack * 1e3, 2),
+                node_days_per_s=round(nd / t_pack, 1), plain_ms=round(t_plain * 1e3, 2),
+                speedup_vs_plain=round(t_plain / t_pack, 2))
+
+
+def serving_leg(P, synth, torch, rate, seconds, budget_gb):
+    """Requests over the three resident serving networks (1k, 37k and 250k
+    nodes, 1461 days): Poisson arrivals at `rate` per second for `seconds`,
+    horizons 365-1461 days, 1-64 replicates with prior-box parameters."""
+    import numpy as np
+    from paper_1502_02908_amd.serve import Server, plan_slots
+    t0 = time.perf_counter()
+    nets = synth.serving_networks()
+    reqs = synth.serving_requests(rate=rate, duration=seconds, seed=5)
+    print(f"[bench] serving: networks generated in {time.perf_counter() - t0:.0f} s, {len(reqs)} requests",
+          file=sys.stderr, flush=True)
+    demand = [net.n_nodes for net in nets]  # requests pick networks uniformly
+    slots, nbytes = plan_slots(nets, budget_gb * 2 ** 30, demand)
+    srv = Server(nets, slots, max_ahead=4)
+    last = [time.perf_counter()]
+
+    def progress(j, k):
+        if time.perf_counter() - last[0] > 10:
+            last[0] = time.perf_counter()
+            print(f"[bench] serving: network {j} step {k}", file=sys.stderr, flush=True)
+    try:
+        results, stats = srv.serve(reqs, on_step=progress)
+    finally:
+        srv.close()
+    out = stats.summary(results)
+    work = np.mean([nets[q["net"]].n_nodes * q["horizon"] * q["n_rep"] for q in reqs])
+    out.update(offered_rate=rate, arrival_seconds=seconds, hbm_budget_gb=budget_gb,
+               slot_bytes_gb=[round(b / 2 ** 30, 2) for b in nbytes],
+               mean_request_node_days=float(work),
+               errors=sum(r.error is not None for r in results))
+    return out
+
+
 def cpu_baseline(p, seconds):
+    """The oracle on the host's cores over a bounded sample of the workload:
+    the whole horizon if one run fits in `seconds`, else its first days."""
     from oracle import oracle as O
     threads = min(os.cpu_count() or 1, 16)
+    days = p.n_days
+    q = p
+    # size the sample from a short probe run
+    probe_days = max(1, min(p.n_days, 20))
+    t0 = time.perf_counter()
+    O.run(p.truncated(probe_days), threads=threads)
+    per_day = (time.perf_counter() - t0) / probe_days
+    if per_day * p.n_days > seconds:
+        days = max(probe_days, int(seconds / per_day))
+        q = p.truncated(days)
     runs, t_total, trans = 0, 0.0, 0
     while t_total < seconds or runs == 0:
         t0 = time.perf_counter()
-        r = O.run(p, threads=threads)
+        r = O.run(q, threads=threads)
         t_total += time.perf_counter() - t0
         trans += int(r["transitions"].sum())
         runs += 1
         if runs >= 20:
             break
-    nd = p.n_nodes * p.n_days * p.n_rep * runs
+    nd = q.n_nodes * q.n_days * q.n_rep * runs
+    what = "the full workload" if days == p.n_days else f"the first {days} of its {p.n_days} days"
     return dict(value=nd / t_total, unit="node-days/s", cores=threads, kind="oracle",
-                sample=f"the full workload ({p.n_nodes} nodes x {p.n_days} days), {runs} run(s), "
+                sample=f"{what} ({p.n_nodes} nodes), {runs} run(s), "
                        f"oracle fork-join over {threads} threads, {t_total:.1f} s",
                 transitions_per_s=trans / t_total)
 
@@ -151,6 +247,11 @@ def main():
     ap.add_argument("--launch", default="kernels", choices=["kernels", "persistent"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-replicates leg")
+    ap.add_argument("--instances", action="store_true", help="add the 64-uneven-instances leg (slow to generate)")
+    ap.add_argument("--serving", action="store_true", help="add the serving leg")
+    ap.add_argument("--serving-rate", type=float, default=2.0, help="request arrivals per second")
+    ap.add_argument("--serving-seconds", type=float, default=30.0, help="seconds of arrivals")
+    ap.add_argument("--serving-budget-gb", type=float, default=96.0, help="HBM budget for the slots")
     ap.add_argument("--plain-sample", type=int, default=6)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -240,7 +341,7 @@ def main():
         unit_desc = f"{per_nd // 2} B per node (read) per launch"
     avg_s = dom_ms / 1e3 / dom_n
     achieved = bytes_per_launch / avg_s / 1e9
-    traffic = counter_traffic("k_day") if (dom == "day" and args.workload == "sise3-37k") else None
+    traffic = counter_traffic("k_day", args.workload) if dom == "day" else None
     roofline = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 5), traffic=traffic,
                     kernel=dom, avg_launch_us=round(avg_s * 1e6, 3), launches_per_step=dom_n // steps_timed,
@@ -252,6 +353,10 @@ def main():
     batched = None
     if not args.no_batched and args.workload == "sise3-37k":
         batched = batched_leg(P, synth, torch, max(1, min(args.steps, 3)), args.plain_sample)
+
+    instances = instances_leg(P, synth, torch) if args.instances else None
+    serving = (serving_leg(P, synth, torch, args.serving_rate, args.serving_seconds, args.serving_budget_gb)
+               if args.serving else None)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -268,6 +373,10 @@ def main():
         transitions_per_s=round(trans_per_step * args.steps / total, 1),
         transitions_per_step=trans_per_step,
         roofline=roofline, kernels=kernel_breakdown, batched=batched, cpu_baseline=cpu)
+    if instances:
+        line["instances"] = instances
+    if serving:
+        line["serving"] = serving
     print(json.dumps(line), flush=True)
 
 

@@ -617,6 +617,16 @@ __device__ void flush_tile(const Model &m, const DevState &s, const Tally<NC> &t
     __syncthreads();
 }
 
+// Per-lane parameters of a replicate tile, staged in LDS once per tile (every
+// position of a tile belongs to one instance, so lane r has the same set):
+// rate constants, shedding and decay rates and the Philox key.
+struct TileParams {
+    double (*coef)[64];   // [MAXT][64]
+    double *alpha;        // [64]
+    double (*beta)[64];   // [4][64]
+    uint32_t *key0, *key1;
+};
+
 // The day phase for the lane l of a wavefront (every lane of the wavefront
 // must call it; lanes with l >= L or replicate lane r >= r_end take part in
 // the wavefront-level steps only): close day d-1 (phi update + record) if
@@ -624,7 +634,7 @@ __device__ void flush_tile(const Model &m, const DevState &s, const Tally<NC> &t
 template <class Rules>
 __device__ __forceinline__ void day_wave(const Model &m, const DevState &s, int64_t l, int32_t d,
                                          bool prologue, bool ssa, Tally<Rules::NC> &t, int32_t r_end,
-                                         unsigned long long *status) {
+                                         unsigned long long *status, const TileParams *tp = nullptr) {
     constexpr int NC = Rules::NC, NT = Rules::NT;
     const int32_t R = s.R, RL = s.RL;
     const bool in_range = l < s.L;
@@ -654,9 +664,10 @@ __device__ __forceinline__ void day_wave(const Model &m, const DevState &s, int6
             if ((m.nmask >> c) & 1u) N += x[c];
         }
         const int q = season((int64_t)m.day0 + dp);
-        const double a = 1.0 - s.beta[set * 4 + q];
+        const int lane = threadIdx.x & 63;
+        const double a = 1.0 - (tp ? tp->beta[q][lane] : s.beta[set * 4 + q]);
         const double b = a * phi;
-        const double shed = N > 0 ? s.alpha[set] * ((double)I / (double)N) : 0.0;
+        const double shed = N > 0 ? (tp ? tp->alpha[lane] : s.alpha[set]) * ((double)I / (double)N) : 0.0;
         phi = b + shed;
         t.prev += I > 0 ? 1 : 0;
 #pragma unroll
@@ -673,11 +684,12 @@ __device__ __forceinline__ void day_wave(const Model &m, const DevState &s, int6
     }
     if (!ssa) return;
     typename Rules::State ch;
-    const uint32_t key0 = active ? s.seed[inst] : 0u;
-    const uint32_t key1 = active ? s.repid[set] : 0u;
+    const int lane_t = threadIdx.x & 63;
+    const uint32_t key0 = active ? (tp ? tp->key0[lane_t] : s.seed[inst]) : 0u;
+    const uint32_t key1 = active ? (tp ? tp->key1[lane_t] : s.repid[set]) : 0u;
 #pragma unroll
     for (int k = 0; k < NT; ++k) {
-        double c = active && trans_on<NT>(m, k) ? s.coef[set * m.nt + k] : 0.0;
+        double c = active && trans_on<NT>(m, k) ? (tp ? tp->coef[k][lane_t] : s.coef[set * m.nt + k]) : 0.0;
         if ((m.uses_phi >> k) & 1u) c = c * phi;
         ch.cphi[k] = c;
     }
@@ -808,11 +820,26 @@ __global__ __launch_bounds__(kBlock) void k_day_tile(Model m, DevState s, DevEve
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t pos0 = (int64_t)blockIdx.x * kTileNodes;
     const int32_t r = (int32_t)blockIdx.y * 64 + lane;
+    __shared__ double sh_coef[Rules::NT][64], sh_alpha[64], sh_beta[4][64];
+    __shared__ uint32_t sh_k0[64], sh_k1[64];
+    if (wave == 0 && r < r_end) {
+        const int32_t inst = s.inst[pos0];  // every position of a tile belongs to one instance
+        const int64_t set = (int64_t)inst * s.R + r;
+#pragma unroll
+        for (int k = 0; k < Rules::NT; ++k) sh_coef[k][lane] = trans_on<Rules::NT>(m, k) ? s.coef[set * m.nt + k] : 0.0;
+        sh_alpha[lane] = s.alpha[set];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sh_beta[q][lane] = s.beta[set * 4 + q];
+        sh_k0[lane] = s.seed[inst];
+        sh_k1[lane] = s.repid[set];
+    }
+    __syncthreads();
+    const TileParams tp{sh_coef, sh_alpha, sh_beta, sh_k0, sh_k1};
     Tally<NC> t{};
     for (int j = wave; j < kTileNodes; j += kWaves) {
         const int64_t pos = pos0 + j;
         if (pos >= s.Np) break;
-        day_wave<Rules>(m, s, pos * s.RL + r, d, prologue != 0, ssa != 0, t, r_end, status);
+        day_wave<Rules>(m, s, pos * s.RL + r, d, prologue != 0, ssa != 0, t, r_end, status, &tp);
     }
     // instances are padded to whole tiles: one instance per workgroup
     flush_tile<NC>(m, s, t, r < r_end ? s.inst[pos0] * s.R + r : -1, prologue ? d - 1 : -1, ssa ? d : -1);

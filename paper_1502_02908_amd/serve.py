@@ -86,9 +86,12 @@ def plan_slots(networks, hbm_budget, demand, max_slots=256):
     w = np.asarray(demand, float)
     w = w / w.sum()
     out = []
-    for j in range(len(networks)):
+    for j, net in enumerate(networks):
         n = int((hbm_budget * w[j] - base[j]) // per[j])
-        out.append(int(min(max(n, 1), max_slots)))
+        # lane indices stay below 2^31: positions (nodes plus padding and the
+        # units of the largest herds) times 64 lanes per slot
+        cap = (2 ** 31 - 1) // (64 * (net.n_nodes + 512))
+        out.append(int(min(max(n, 1), max_slots, cap)))
     return out, [b + n * p for b, n, p in zip(base, out, per)]
 
 
