@@ -1,6 +1,8 @@
 """GPU path against the oracle, element by element, on seeded inputs: every
 compartment count, daily record and snapshot bit-exact, phi within 1e-12
 relative (and in practice bit-identical). Calls go through the C ABI."""
+import os
+
 import numpy as np
 import pytest
 
@@ -16,7 +18,7 @@ pytestmark = pytest.mark.gpu
 def both(p, **kw):
     say(f"[parity] {p.name} Nn={p.n_nodes} R={p.n_rep} D={p.n_days} events={p.n_events} {kw}")
     g = gpu_run(p, **kw)
-    o = O.run(p, threads=8)
+    o = O.run(p, threads=min(16, os.cpu_count() or 1))
     return g, o
 
 
@@ -215,3 +217,12 @@ def test_general_stoichiometry_sir(launch):
     g, o = both(p, launch=launch)
     assert_parity(g, o)
     assert o["transitions"].sum() > 5000
+
+
+def test_config3_full_1m_nodes_1461_days():
+    # the full-size scale-up network: every count and record against the oracle
+    p = synth.config3()
+    p.record_days = np.array([730, 1460], np.int32)
+    g, o = both(p)
+    assert_parity(g, o)
+    say(f"[parity] config3 transitions={o['transitions'].sum()} levels={g['levels']}")
