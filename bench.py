@@ -30,6 +30,12 @@ WORKLOADS = {
                    make=lambda synth: synth.config1()),
     "sise3-1m": dict(desc="SISe3 farm network, 1,000,000 nodes x 1461 days, seed 3",
                      make=lambda synth: synth.config3()),
+    # the 37k network with the rate constants scaled by u = 10 (Sec. 4.1's load variant)
+    "sise3-37k-u10": dict(desc="SISe3 farm network, 37,000 nodes x 1461 days, seed 2, u = 10",
+                          make=lambda synth: synth.config2(u=10.0)),
+    # the paper's synthetic SSA-heavy model (Sec. 4.2): S <-> I at rate 1, S = I = 1000, no events
+    "synthetic-1k": dict(desc="synthetic S<->I model, 1,000 nodes x 1000 days, S = I = 1000, rates 1",
+                         make=lambda synth: synth.flip_model(n_nodes=1000, n_days=1000)),
 }
 
 

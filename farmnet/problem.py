@@ -53,6 +53,8 @@ class Problem:
     seed: int = 1
     day0: int = 0
     replicate_id: Optional[np.ndarray] = None  # uint32 [R]
+    reactant2: Optional[np.ndarray] = None  # int32 [Nt]: second reactant of a mass-action rate, -1 none
+    phi_pre_events: int = 0  # 1: phi is fed by the state before the day's events
     record_days: Optional[np.ndarray] = None   # int32 ascending
     name: str = ""
 
@@ -74,6 +76,8 @@ class Problem:
         if self.replicate_id is None:
             self.replicate_id = np.arange(self.n_rep, dtype=np.uint32)
         self.replicate_id = np.ascontiguousarray(self.replicate_id, dtype=np.uint32)
+        if self.reactant2 is not None:
+            self.reactant2 = i32(self.reactant2)
         if self.record_days is None:
             self.record_days = np.zeros(0, dtype=np.int32)
         self.record_days = i32(self.record_days)

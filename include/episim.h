@@ -86,6 +86,13 @@ extern "C" {
  *    compartment), ev_shift in [-1,n_shift) (-1 = none).
  *  record_days[n_record]      strictly ascending days in [0,D) whose end state is snapshotted.
  *  seed, replicate_id[R]      Philox key words; replicate_id NULL means 0..R-1.
+ *  reactant2[Nt]              NULL, or per transition a second reactant in [0,Nc) or -1: a
+ *                             mass-action rate is also multiplied by X[reactant2[k]] (the
+ *                             bimolecular rate of the SIR example, Sec. 2.1).
+ *  phi_pre_events             0: phi is updated from the state after the day's events (Algorithm
+ *                             1, the default); 1: from the state after the SSA and before the
+ *                             events (eq:numstep5 as written). Records are taken after the events
+ *                             either way.
  */
 typedef struct sim_problem {
     int32_t n_nodes, n_comp, n_trans, n_rep, n_days, day0;
@@ -104,6 +111,8 @@ typedef struct sim_problem {
     const int32_t *record_days;
     uint32_t seed;
     const uint32_t *replicate_id;
+    const int32_t *reactant2;
+    int32_t phi_pre_events;
 } sim_problem;
 
 /* Execution of the event phase. */

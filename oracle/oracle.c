@@ -88,6 +88,8 @@ typedef struct oracle_problem {
     const int32_t *ev_day, *ev_kind, *ev_node, *ev_dest, *ev_n, *ev_select, *ev_shift;
     uint32_t seed;
     const uint32_t *replicate_id; /* [R] */
+    const int32_t *reactant2;     /* [Nt] second reactant of a mass-action rate, -1 if none; NULL: none */
+    int32_t phi_pre_events;       /* 1: phi from the state after the SSA, before the events */
 } oracle_problem;
 
 /* Outputs for days [d_begin, d_end); indices are relative to d_begin. */
@@ -204,6 +206,9 @@ static double rates(const oracle_problem *p, int r, const int32_t *x, double phi
         double v = p->coef[(size_t)r * p->Nt + k];
         if (p->uses_phi[k]) v = v * phi;
         v = v * (double)x[p->reactant[k]];
+        /* a bimolecular rate (mass action, e.g. the SIR example of Sec. 2.1)
+         * is also proportional to its second reactant's count */
+        if (p->reactant2 && p->reactant2[k] >= 0) v = v * (double)x[p->reactant2[k]];
         w[k] = v;
         lam = lam + w[k];
     }
@@ -375,6 +380,13 @@ int oracle_run(const oracle_problem *p, int32_t *u, double *v, int32_t d_begin, 
                 ntr[i] = ssa_node(p, r, i, d, ur + (size_t)i * Nc, vr[i]);
             int64_t trans = 0;
             for (int32_t i = 0; i < Nn; ++i) trans += ntr[i];
+            /* eq:numstep5 as written feeds phi with the state before the
+             * events (the variant reading; the default follows Algorithm 1) */
+            if (p->phi_pre_events) {
+                #pragma omp parallel for schedule(static) if (threads > 1)
+                for (int32_t i = 0; i < Nn; ++i)
+                    vr[i] = phi_update(p, r, d, ur + (size_t)i * Nc, vr[i]);
+            }
             /* 2. deterministic step: this day's events in list order */
             while (e < p->n_events && p->ev_day[e] == d) {
                 if (apply_event(p, r, e, d, ur) != 0) {
@@ -389,10 +401,12 @@ int oracle_run(const oracle_problem *p, int32_t *u, double *v, int32_t d_begin, 
                 ++e;
             }
             if (failed) break;
-            /* 3. continuous-state update */
-            #pragma omp parallel for schedule(static) if (threads > 1)
-            for (int32_t i = 0; i < Nn; ++i)
-                vr[i] = phi_update(p, r, d, ur + (size_t)i * Nc, vr[i]);
+            /* 3. continuous-state update (Algorithm 1: after the events) */
+            if (!p->phi_pre_events) {
+                #pragma omp parallel for schedule(static) if (threads > 1)
+                for (int32_t i = 0; i < Nn; ++i)
+                    vr[i] = phi_update(p, r, d, ur + (size_t)i * Nc, vr[i]);
+            }
             /* 4. record */
             if (out->transitions) out->transitions[(size_t)dd * R + r] = trans;
             if (out->prevalence) {

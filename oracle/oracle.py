@@ -31,6 +31,7 @@ class _Problem(C.Structure):
         ("ev_day", _i32p), ("ev_kind", _i32p), ("ev_node", _i32p), ("ev_dest", _i32p),
         ("ev_n", _i32p), ("ev_select", _i32p), ("ev_shift", _i32p),
         ("seed", C.c_uint32), ("replicate_id", _u32p),
+        ("reactant2", _i32p), ("phi_pre_events", C.c_int32),
     ]
 
 
@@ -127,7 +128,9 @@ def run(p, d_begin=0, d_end=None, u=None, v=None, threads=1, record_days=None, r
     v = np.ascontiguousarray(np.array(v, dtype=np.float64).reshape(R, Nn))
     rec = p.record_days if record_days is None else np.asarray(record_days, np.int32)
     rec = np.ascontiguousarray(rec[(rec >= d_begin) & (rec < d_end)], np.int32)
-    keep = [p.S, p.reactant, p.uses_phi, p.coef, p.alpha, p.beta, p.E, p.N, p.replicate_id]
+    r2 = getattr(p, "reactant2", None)
+    r2 = None if r2 is None else np.ascontiguousarray(r2, np.int32)
+    keep = [p.S, p.reactant, p.uses_phi, p.coef, p.alpha, p.beta, p.E, p.N, p.replicate_id, r2]
     prob = _Problem(
         Nn, Nc, p.n_trans, R, p.day0,
         _ptr(p.S, _i32p), _ptr(p.reactant, _i32p), _ptr(p.uses_phi, _i32p),
@@ -137,7 +140,8 @@ def run(p, d_begin=0, d_end=None, u=None, v=None, threads=1, record_days=None, r
         p.n_events,
         _ptr(p.ev_day, _i32p), _ptr(p.ev_kind, _i32p), _ptr(p.ev_node, _i32p), _ptr(p.ev_dest, _i32p),
         _ptr(p.ev_n, _i32p), _ptr(p.ev_select, _i32p), _ptr(p.ev_shift, _i32p),
-        p.seed & 0xFFFFFFFF, _ptr(p.replicate_id, _u32p))
+        p.seed & 0xFFFFFFFF, _ptr(p.replicate_id, _u32p),
+        None if r2 is None else _ptr(r2, _i32p), int(getattr(p, "phi_pre_events", 0)))
     out = dict(
         prevalence=np.zeros((D, R), np.int32),
         transitions=np.zeros((D, R), np.int64),

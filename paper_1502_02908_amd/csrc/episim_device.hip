@@ -143,11 +143,15 @@ struct GenericRules {
     static constexpr int kPairs = 0;
     using State = Chain<NC, NT>;
     __device__ static __forceinline__ double rate(const Model &m, const State &c, int k) {
-        double xr = 0.0;
+        double xr = 0.0, xr2 = 0.0;
 #pragma unroll
-        for (int cc = 0; cc < NC; ++cc)
+        for (int cc = 0; cc < NC; ++cc) {
             if (m.reactant[k] == cc) xr = c.xd[cc];
-        return c.cphi[k] * xr;
+            if (m.reactant2[k] == cc) xr2 = c.xd[cc];
+        }
+        const double w = c.cphi[k] * xr;
+        // a mass-action rate is also proportional to its second reactant
+        return m.reactant2[k] >= 0 ? w * xr2 : w;
     }
     __device__ static __forceinline__ void rates(const Model &m, State &c) {
         double lam = 0.0;
@@ -654,21 +658,34 @@ __device__ __forceinline__ void day_wave(const Model &m, const DevState &s, int6
         for (int c = 0; c < NC; ++c) x[c] = comp_on<NC>(m, c) ? s.u[(int64_t)c * s.L + l] : 0;
         phi = s.phi[l];
     }
-    if (active && prologue) {
-        const double phi_in = phi;
-        const int32_t dp = d - 1;
+    // phi_{d+1} = (1 - beta(day0 + d)) phi_d + alpha I/N (eq:siminfpressure, Euler step)
+    auto phi_next = [&](const int32_t *y, int32_t dd, double ph, long long *Iout) {
         long long I = 0, N = 0;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            if ((m.imask >> c) & 1u) I += x[c];
-            if ((m.nmask >> c) & 1u) N += x[c];
+            if ((m.imask >> c) & 1u) I += y[c];
+            if ((m.nmask >> c) & 1u) N += y[c];
         }
-        const int q = season((int64_t)m.day0 + dp);
+        *Iout = I;
+        const int q = season((int64_t)m.day0 + dd);
         const int lane = threadIdx.x & 63;
         const double a = 1.0 - (tp ? tp->beta[q][lane] : s.beta[set * 4 + q]);
-        const double b = a * phi;
+        const double b = a * ph;
         const double shed = N > 0 ? (tp ? tp->alpha[lane] : s.alpha[set]) * ((double)I / (double)N) : 0.0;
-        phi = b + shed;
+        return b + shed;
+    };
+    if (active && prologue) {
+        const double phi_in = phi;
+        const int32_t dp = d - 1;
+        long long I = 0;
+        if (m.phi_pre) {
+            // phi was already fed by the state before the events of day dp
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                if ((m.imask >> c) & 1u) I += x[c];
+        } else {
+            phi = phi_next(x, dp, phi, &I);
+        }
         t.prev += I > 0 ? 1 : 0;
 #pragma unroll
         for (int c = 0; c < NC; ++c) t.tot[c] += x[c];
@@ -704,6 +721,15 @@ __device__ __forceinline__ void day_wave(const Model &m, const DevState &s, int6
 #pragma unroll
         for (int c = 0; c < NC; ++c)
             if (comp_on<NC>(m, c)) s.u[(int64_t)c * s.L + l] = (int32_t)ch.xd[c];
+    }
+    if (active && m.phi_pre) {
+        // eq:numstep5 as written: phi from the state after the SSA, before the events
+        int32_t y[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) y[c] = (int32_t)ch.xd[c];
+        long long I = 0;
+        const double phi2 = phi_next(y, d, phi, &I);
+        if (__double_as_longlong(phi2) != __double_as_longlong(phi)) s.phi[l] = phi2;
     }
 }
 

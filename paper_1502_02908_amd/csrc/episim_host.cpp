@@ -155,6 +155,7 @@ int validate(const sim_problem *p, std::string *err) {
     if (p->n_comp < 1 || p->n_comp > SIM_MAX_COMP) return *err = "n_comp must be in [1, 8]", SIM_EINVAL;
     if (p->n_trans < 1 || p->n_trans > SIM_MAX_TRANS) return *err = "n_trans must be in [1, 8]", SIM_EINVAL;
     if (p->n_rep < 1) return *err = "n_rep must be >= 1", SIM_EINVAL;
+    if (p->phi_pre_events != 0 && p->phi_pre_events != 1) return *err = "phi_pre_events must be 0 or 1", SIM_EINVAL;
     if (p->n_days < 0) return *err = "n_days < 0", SIM_EINVAL;
     if ((int64_t)p->n_nodes * p->n_rep > INT32_MAX)
         return *err = "n_nodes * n_rep must be below 2^31", SIM_EINVAL;
@@ -172,6 +173,8 @@ int validate(const sim_problem *p, std::string *err) {
         const int a = p->reactant[k];
         if (a < 0 || a >= Nc) return *err = fmt("reactant[%d] out of range", k), SIM_EINVAL;
         if (p->uses_phi[k] != 0 && p->uses_phi[k] != 1) return *err = fmt("uses_phi[%d] not 0/1", k), SIM_EINVAL;
+        if (p->reactant2 && (p->reactant2[k] < -1 || p->reactant2[k] >= Nc))
+            return *err = fmt("reactant2[%d] out of range", k), SIM_EINVAL;
         for (int c = 0; c < Nc; ++c) {
             const int32_t s = p->S[(size_t)c * Nt + k];
             if (c == a && s != -1) return *err = fmt("S[%d,%d] must be -1 (the reactant of transition %d)", c, k, k), SIM_EINVAL;
@@ -231,10 +234,12 @@ int same_model(const sim_problem *a, const sim_problem *b, std::string *err) {
     const size_t Nc = a->n_comp, Nt = a->n_trans;
     if (a->n_comp != b->n_comp || a->n_trans != b->n_trans || a->n_rep != b->n_rep || a->n_days != b->n_days ||
         a->day0 != b->day0 || a->phi_I_mask != b->phi_I_mask || a->phi_N_mask != b->phi_N_mask ||
-        a->n_select != b->n_select || a->n_shift != b->n_shift || a->n_record != b->n_record)
+        a->n_select != b->n_select || a->n_shift != b->n_shift || a->n_record != b->n_record ||
+        a->phi_pre_events != b->phi_pre_events || (a->reactant2 == nullptr) != (b->reactant2 == nullptr))
         return *err = "packed problems must share sizes, replicates, horizon, day0, masks and record days", SIM_EINVAL;
     if (!eq(a->S, b->S, sizeof(int32_t) * Nc * Nt) || !eq(a->reactant, b->reactant, sizeof(int32_t) * Nt) ||
         !eq(a->uses_phi, b->uses_phi, sizeof(int32_t) * Nt) ||
+        (a->reactant2 && !eq(a->reactant2, b->reactant2, sizeof(int32_t) * Nt)) ||
         !eq(a->E, b->E, sizeof(int32_t) * Nc * a->n_select) || !eq(a->N, b->N, sizeof(int32_t) * Nc * a->n_shift) ||
         !eq(a->record_days, b->record_days, sizeof(int32_t) * a->n_record))
         return *err = "packed problems must share the model (S, reactants, uses_phi, E, N) and record days", SIM_EINVAL;
@@ -846,10 +851,13 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
     m.nt = h->Nt;
     m.day0 = p->day0;
     m.seed = p->seed;
+    m.phi_pre = p->phi_pre_events;
+    for (int k = 0; k < MAXT; ++k) m.reactant2[k] = -1;
     m.uses_phi = 0;
     for (int k = 0; k < h->Nt; ++k) {
         if (p->uses_phi[k]) m.uses_phi |= 1u << k;
         m.reactant[k] = p->reactant[k];
+        m.reactant2[k] = p->reactant2 ? p->reactant2[k] : -1;
         for (int c = 0; c < h->Nc; ++c) m.S[c][k] = p->S[(size_t)c * h->Nt + k];
     }
     m.imask = p->phi_I_mask;
@@ -857,7 +865,7 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
     // paired S <-> I classes: transition k moves one individual from compartment k to k ^ 1
     m.pairs = (h->Nc == h->Nt && h->Nc % 2 == 0) ? 1 : 0;
     for (int k = 0; k < h->Nt && m.pairs; ++k) {
-        if (p->reactant[k] != k) m.pairs = 0;
+        if (p->reactant[k] != k || m.reactant2[k] >= 0) m.pairs = 0;
         for (int c = 0; c < h->Nc && m.pairs; ++c) {
             const int want = c == k ? -1 : (c == (k ^ 1) ? 1 : 0);
             if (p->S[(size_t)c * h->Nt + k] != want) m.pairs = 0;

@@ -41,6 +41,8 @@ struct Model {
     uint32_t uses_phi;          // bit k: rate k proportional to phi
     uint32_t imask, nmask;      // compartments counted in I and in N
     int32_t reactant[MAXT];
+    int32_t reactant2[MAXT];    // second reactant of a mass-action rate, -1 if none
+    int32_t phi_pre;            // 1: phi from the state after the SSA, before the events
     int32_t S[MAXC][MAXT];      // S[c][k]
 };
 

@@ -41,6 +41,7 @@ class sim_problem(C.Structure):
         ("ev_n", _i32p), ("ev_select", _i32p), ("ev_shift", _i32p),
         ("n_record", C.c_int32), ("record_days", _i32p),
         ("seed", C.c_uint32), ("replicate_id", _u32p),
+        ("reactant2", _i32p), ("phi_pre_events", C.c_int32),
     ]
 
 
@@ -124,6 +125,8 @@ def _marshal(p):
                ev_n=i32(p.ev_n), ev_select=i32(p.ev_select), ev_shift=i32(p.ev_shift),
                record_days=i32(p.record_days if p.record_days is not None else np.zeros(0)),
                replicate_id=np.ascontiguousarray(p.replicate_id, dtype=np.uint32))
+    r2 = getattr(p, "reactant2", None)
+    arr["reactant2"] = None if r2 is None else i32(r2)
     s = sim_problem(
         p.n_nodes, p.n_comp, p.n_trans, p.n_rep, p.n_days, getattr(p, "day0", 0),
         _p(arr["u0"], _i32p), _p(arr["v0"], _f64p),
@@ -137,7 +140,8 @@ def _marshal(p):
         _p(arr["ev_dest"], _i32p), _p(arr["ev_n"], _i32p), _p(arr["ev_select"], _i32p),
         _p(arr["ev_shift"], _i32p),
         len(arr["record_days"]), _p(arr["record_days"], _i32p),
-        int(p.seed) & 0xFFFFFFFF, _p(arr["replicate_id"], _u32p))
+        int(p.seed) & 0xFFFFFFFF, _p(arr["replicate_id"], _u32p),
+        None if arr["reactant2"] is None else _p(arr["reactant2"], _i32p), int(getattr(p, "phi_pre_events", 0)))
     return s, arr
 
 

@@ -233,8 +233,11 @@ TWO_NODE_KW = dict(n_days=3, upsilon=0.9, gamma=0.4, alpha=1.0, beta=(0.3, 0.3, 
                    u0=((3, 1), (2, 0)), phi0=(1.6, 0.0))
 
 
-def two_node_samples(R=200000, lib_path=None):
+def two_node_samples(R=200000, lib_path=None, pre=False):
+    import dataclasses
     p = synth.two_node(**TWO_NODE_KW).with_replicates(R)
+    if pre:
+        p = dataclasses.replace(p, phi_pre_events=1)
     r = O.run(p, record_days=[0, 1, 2], lib_path=lib_path)
     return p, r["snap_u"]  # [day, R, 2, 2]
 
@@ -401,3 +404,59 @@ def check_conservation(lib_path=None):
             got[:, cls_of[c]] += r["u"][0, :, c]
         ok = ok and (got == want).all() and (r["u"] >= 0).all() and r["transitions"].sum() > 1000
     return ok, int(np.abs(got - want).sum())
+
+
+# ---------------------------------------------------------------------------
+# Mass-action (bimolecular) rates: the SIR example of Sec. 2.1, one node,
+# S + I -> 2I at rate c_1 * S * I and I -> R at rate c_2 * I. Its master
+# equation on the (S, I) lattice is small enough to solve exactly.
+# ---------------------------------------------------------------------------
+
+def sir_mass_action(S0=6, I0=2, c_inf=0.3, c_rec=0.5, n_days=2, R=1, second_reactant=True):
+    from farmnet.problem import Problem
+    none = np.zeros(0, np.int32)
+    return Problem(n_nodes=1, n_comp=3, n_trans=2, n_rep=R, n_days=n_days,
+                   u0=np.array([[S0, I0, 0]]), v0=np.zeros(1),
+                   S=np.array([[-1, 0], [1, -1], [0, 1]]), reactant=np.array([0, 1]),
+                   uses_phi=np.array([0, 0]), coef=np.tile([c_inf, c_rec], (R, 1)), alpha=np.zeros(R),
+                   beta=np.zeros((R, 4)), phi_I_mask=0b010, phi_N_mask=0b111,
+                   E=np.ones((3, 1), np.int32), N=np.zeros((3, 0), np.int32),
+                   ev_day=none, ev_kind=none, ev_node=none, ev_dest=none, ev_n=none, ev_select=none,
+                   ev_shift=none, seed=17, reactant2=np.array([1 if second_reactant else -1, -1]),
+                   name="sir-mass-action")
+
+
+def sir_exact(S0, I0, c_inf, c_rec, t, bimolecular=True):
+    """P(S, I) at time t from the generator of the chain (exact matrix exponential)."""
+    states = [(S, I) for S in range(S0 + 1) for I in range(S0 + I0 + 1 - S)]
+    idx = {st: k for k, st in enumerate(states)}
+    Q = np.zeros((len(states), len(states)))
+    for (S, I), k in idx.items():
+        a = c_inf * S * (I if bimolecular else 1)
+        b = c_rec * I
+        if S > 0 and a > 0:
+            Q[k, idx[(S - 1, I + 1)]] += a
+        if I > 0:
+            Q[k, idx[(S, I - 1)]] += b
+        Q[k, k] = -(a + b)
+    row = linalg.expm(Q * t)[idx[(S0, I0)]]
+    return {st: row[k] for st, k in idx.items()}
+
+
+def sir_samples(R=200000, lib_path=None, **kw):
+    p = sir_mass_action(R=R, **kw)
+    r = O.run(p, record_days=list(range(p.n_days)), lib_path=lib_path)
+    return p, r["snap_u"][:, :, 0, :]  # [day, R, c]
+
+
+def sir_pvalues(snap, S0, I0, c_inf, c_rec, bimolecular=True):
+    pv = []
+    for d in range(snap.shape[0]):
+        law = sir_exact(S0, I0, c_inf, c_rec, d + 1.0, bimolecular)
+        keys = sorted(law)
+        counts = defaultdict(int)
+        for S, I, _ in snap[d]:
+            counts[(int(S), int(I))] += 1
+        obs = np.array([counts[k] for k in keys], float)
+        pv.append(gof(obs, [law[k] for k in keys]))
+    return pv

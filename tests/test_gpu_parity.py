@@ -226,3 +226,40 @@ def test_config3_full_1m_nodes_1461_days():
     g, o = both(p)
     assert_parity(g, o)
     say(f"[parity] config3 transitions={o['transitions'].sum()} levels={g['levels']}")
+
+
+# --- method variants ----------------------------------------------------------
+
+@pytest.mark.parametrize("launch", [P.LAUNCH_KERNELS, P.LAUNCH_PERSISTENT])
+def test_phi_from_pre_event_state(launch):
+    # eq:numstep5 as written: phi fed by the state after the SSA, before the events
+    import dataclasses
+    p = dataclasses.replace(synth.sise3_network(n_nodes=2000, n_days=90, seed=41, u=10.0, age_days=(10, 30)),
+                            phi_pre_events=1)
+    p.record_days = np.array([5, 89], np.int32)
+    g, o = both(p, launch=launch)
+    assert_parity(g, o)
+    post = O.run(dataclasses.replace(p, phi_pre_events=0), threads=8)
+    assert not np.array_equal(post["v"], o["v"])
+
+
+def test_phi_from_pre_event_state_replicate_tiles():
+    import dataclasses
+    base = dataclasses.replace(synth.sise3_network(n_nodes=900, n_days=60, seed=42, age_days=(10, 30)),
+                               phi_pre_events=1)
+    coef, alpha, beta = synth.prior_draws(70, seed=43)
+    p = base.with_replicates(70, coef=coef, alpha=alpha, beta=beta)
+    g, o = both(p)
+    assert_parity(g, o)
+
+
+@pytest.mark.parametrize("launch", [P.LAUNCH_KERNELS, P.LAUNCH_PERSISTENT])
+def test_mass_action_sir(launch):
+    # S + I -> 2I at rate c S I (the bimolecular rate of the SIR example), I -> R, R -> S
+    import dataclasses
+    p = dataclasses.replace(sir_network(n_days=50), uses_phi=np.zeros(3, np.int32),
+                            coef=np.array([[0.004, 0.2, 0.05]]), reactant2=np.array([1, -1, -1], np.int32))
+    p.record_days = np.array([3, 49], np.int32)
+    g, o = both(p, launch=launch)
+    assert_parity(g, o)
+    assert o["transitions"].sum() > 5000

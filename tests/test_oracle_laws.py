@@ -36,6 +36,31 @@ def test_two_node_distinguishes_phi_reading():
     assert min(pv) < 1e-8, pv
 
 
+def test_two_node_pre_event_variant():
+    """The variant that feeds phi from the state before the events (eq:numstep5
+    as written) follows its own exact law, and the same samples reject the
+    default reading's law."""
+    p, snap = laws.two_node_samples(pre=True)
+    pv = laws.two_node_pvalues(snap, laws.two_node_exact_pre(p))
+    assert min(pv) > laws.P_MIN, pv
+    pv = laws.two_node_pvalues(snap, laws.two_node_exact(p))
+    assert min(pv) < 1e-8, pv
+
+
+def test_mass_action_sir_master_equation():
+    """Bimolecular S + I -> 2I (rate c S I) with recovery: the (S, I) law after
+    one and two days is the exact matrix exponential of the chain's generator;
+    the same samples reject a rate that ignores the second reactant."""
+    kw = dict(S0=6, I0=2, c_inf=0.3, c_rec=0.5)
+    p, snap = laws.sir_samples(**kw)
+    pv = laws.sir_pvalues(snap, **kw)
+    assert min(pv) > laws.P_MIN, pv
+    pv = laws.sir_pvalues(snap, bimolecular=False, **kw)
+    assert min(pv) < 1e-8, pv
+    # conservation: S + I + R stays 8
+    assert (snap.sum(axis=2) == 8).all()
+
+
 @pytest.mark.parametrize("day0", [0, 50, 300])
 def test_phi_closed_form(day0):
     ok, worst = laws.check_phi_closed_form(day0=day0)

@@ -44,7 +44,7 @@ MUTATIONS = {
     # moved animals dropped instead of added at the destination
     "lost_move": ([("xt[to] += m[c];", "(void)to;")], laws.check_conservation),
     # phi fed by the state before the events (the other reading of eq:numstep5)
-    "phi_before_events": ([("vr[i] = phi_update(p, r, d, ur + (size_t)i * Nc, vr[i]);", "(void)0;"),
+    "phi_before_events": ([("if (!p->phi_pre_events) {", "if (0) {"),
                            ("ntr[i] = ssa_node(p, r, i, d, ur + (size_t)i * Nc, vr[i]);",
                             "{ ntr[i] = ssa_node(p, r, i, d, ur + (size_t)i * Nc, vr[i]);"
                             " vr[i] = phi_update(p, r, d, ur + (size_t)i * Nc, vr[i]); }")],
