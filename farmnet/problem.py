@@ -55,6 +55,8 @@ class Problem:
     replicate_id: Optional[np.ndarray] = None  # uint32 [R]
     reactant2: Optional[np.ndarray] = None  # int32 [Nt]: second reactant of a mass-action rate, -1 none
     phi_pre_events: int = 0  # 1: phi is fed by the state before the day's events
+    n_regions: int = 0       # regions of the goal function's aggregates (Sec. 4.3)
+    region: Optional[np.ndarray] = None  # int32 [Nn] region of each node, or -1
     record_days: Optional[np.ndarray] = None   # int32 ascending
     name: str = ""
 
@@ -78,6 +80,8 @@ class Problem:
         self.replicate_id = np.ascontiguousarray(self.replicate_id, dtype=np.uint32)
         if self.reactant2 is not None:
             self.reactant2 = i32(self.reactant2)
+        if self.region is not None:
+            self.region = i32(self.region).reshape(self.n_nodes)
         if self.record_days is None:
             self.record_days = np.zeros(0, dtype=np.int32)
         self.record_days = i32(self.record_days)

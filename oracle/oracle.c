@@ -90,6 +90,8 @@ typedef struct oracle_problem {
     const uint32_t *replicate_id; /* [R] */
     const int32_t *reactant2;     /* [Nt] second reactant of a mass-action rate, -1 if none; NULL: none */
     int32_t phi_pre_events;       /* 1: phi from the state after the SSA, before the events */
+    int32_t n_regions;            /* regions for the aggregates of the goal function (Sec. 4.3) */
+    const int32_t *region;        /* [Nn] region of each node in [0, n_regions), or -1 */
 } oracle_problem;
 
 /* Outputs for days [d_begin, d_end); indices are relative to d_begin. */
@@ -101,6 +103,7 @@ typedef struct oracle_output {
     const int32_t *record_days; /* absolute day indices, ascending */
     int32_t *snap_u;       /* [n_record*R*Nn*Nc] */
     double *snap_v;        /* [n_record*R*Nn] */
+    int64_t *regional;     /* [D*R*n_regions*Nc] compartment sums over the nodes of each region (or NULL) */
     /* error report: smallest (event index, replicate) that was infeasible */
     int64_t err_event;
     int32_t err_rep;
@@ -424,6 +427,17 @@ int oracle_run(const oracle_problem *p, int32_t *u, double *v, int32_t d_begin, 
                     int64_t t = 0;
                     for (int32_t i = 0; i < Nn; ++i) t += ur[(size_t)i * Nc + c];
                     out->totals[((size_t)dd * R + r) * Nc + c] = t;
+                }
+            }
+            /* regional aggregates: X summed over the nodes of each region
+             * (the inner sum of eq:goal, one sample trajectory) */
+            if (out->regional && p->n_regions > 0) {
+                int64_t *g = out->regional + ((size_t)dd * R + r) * p->n_regions * Nc;
+                for (int64_t q = 0; q < (int64_t)p->n_regions * Nc; ++q) g[q] = 0;
+                for (int32_t i = 0; i < Nn; ++i) {
+                    const int32_t j = p->region[i];
+                    if (j < 0) continue;
+                    for (int c = 0; c < Nc; ++c) g[(size_t)j * Nc + c] += ur[(size_t)i * Nc + c];
                 }
             }
             while (rec < out->n_record && out->record_days[rec] < d) ++rec;

@@ -32,6 +32,7 @@ class _Problem(C.Structure):
         ("ev_n", _i32p), ("ev_select", _i32p), ("ev_shift", _i32p),
         ("seed", C.c_uint32), ("replicate_id", _u32p),
         ("reactant2", _i32p), ("phi_pre_events", C.c_int32),
+        ("n_regions", C.c_int32), ("region", _i32p),
     ]
 
 
@@ -39,7 +40,7 @@ class _Output(C.Structure):
     _fields_ = [
         ("prevalence", _i32p), ("transitions", _i64p), ("totals", _i64p),
         ("n_record", C.c_int32), ("record_days", _i32p),
-        ("snap_u", _i32p), ("snap_v", _f64p),
+        ("snap_u", _i32p), ("snap_v", _f64p), ("regional", _i64p),
         ("err_event", C.c_int64), ("err_rep", C.c_int32), ("err_day", C.c_int32),
     ]
 
@@ -130,7 +131,10 @@ def run(p, d_begin=0, d_end=None, u=None, v=None, threads=1, record_days=None, r
     rec = np.ascontiguousarray(rec[(rec >= d_begin) & (rec < d_end)], np.int32)
     r2 = getattr(p, "reactant2", None)
     r2 = None if r2 is None else np.ascontiguousarray(r2, np.int32)
-    keep = [p.S, p.reactant, p.uses_phi, p.coef, p.alpha, p.beta, p.E, p.N, p.replicate_id, r2]
+    reg = getattr(p, "region", None)
+    J = 0 if reg is None else int(p.n_regions)
+    reg = None if reg is None else np.ascontiguousarray(reg, np.int32)
+    keep = [p.S, p.reactant, p.uses_phi, p.coef, p.alpha, p.beta, p.E, p.N, p.replicate_id, r2, reg]
     prob = _Problem(
         Nn, Nc, p.n_trans, R, p.day0,
         _ptr(p.S, _i32p), _ptr(p.reactant, _i32p), _ptr(p.uses_phi, _i32p),
@@ -141,16 +145,19 @@ def run(p, d_begin=0, d_end=None, u=None, v=None, threads=1, record_days=None, r
         _ptr(p.ev_day, _i32p), _ptr(p.ev_kind, _i32p), _ptr(p.ev_node, _i32p), _ptr(p.ev_dest, _i32p),
         _ptr(p.ev_n, _i32p), _ptr(p.ev_select, _i32p), _ptr(p.ev_shift, _i32p),
         p.seed & 0xFFFFFFFF, _ptr(p.replicate_id, _u32p),
-        None if r2 is None else _ptr(r2, _i32p), int(getattr(p, "phi_pre_events", 0)))
+        None if r2 is None else _ptr(r2, _i32p), int(getattr(p, "phi_pre_events", 0)),
+        J, None if reg is None else _ptr(reg, _i32p))
     out = dict(
         prevalence=np.zeros((D, R), np.int32),
         transitions=np.zeros((D, R), np.int64),
         totals=np.zeros((D, R, Nc), np.int64),
         snap_u=np.zeros((len(rec), R, Nn, Nc), np.int32),
         snap_v=np.zeros((len(rec), R, Nn), np.float64),
+        regional=np.zeros((D, R, J, Nc), np.int64),
     )
     o = _Output(_ptr(out["prevalence"], _i32p), _ptr(out["transitions"], _i64p), _ptr(out["totals"], _i64p),
-                len(rec), _ptr(rec, _i32p), _ptr(out["snap_u"], _i32p), _ptr(out["snap_v"], _f64p), -1, -1, -1)
+                len(rec), _ptr(rec, _i32p), _ptr(out["snap_u"], _i32p), _ptr(out["snap_v"], _f64p),
+                _ptr(out["regional"], _i64p) if J else None, -1, -1, -1)
     rc = lib(lib_path).oracle_run(C.byref(prob), _ptr(u, _i32p), _ptr(v, _f64p), d_begin, d_end, threads, C.byref(o))
     del keep
     out.update(u=u, v=v, rc=rc, err_event=o.err_event, err_rep=o.err_rep, err_day=o.err_day,
