@@ -52,6 +52,7 @@ extern "C" {
 #define SIM_MAX_TRANS 8
 #define SIM_MAX_EVENT_N (1 << 24)   /* largest n of one event */
 #define SIM_MAX_FIRED   (1 << 24)   /* largest number of SSA transitions of one node in one day */
+#define SIM_MAX_REGIONS 4096        /* largest number of regions of the goal function */
 
 /* Event kinds (Sec. 3.2: E1 = one node, E2 = two nodes). */
 #define SIM_EXIT     0  /* E1: remove n individuals sampled from the selected compartments */
@@ -93,6 +94,8 @@ extern "C" {
  *                             1, the default); 1: from the state after the SSA and before the
  *                             events (eq:numstep5 as written). Records are taken after the events
  *                             either way.
+ *  n_regions, region[Nn]      regions of the goal function (Sec. 4.3): region[i] in [0, n_regions) or
+ *                             -1; with n_regions > 0 the daily regional sums are recorded.
  */
 typedef struct sim_problem {
     int32_t n_nodes, n_comp, n_trans, n_rep, n_days, day0;
@@ -113,6 +116,8 @@ typedef struct sim_problem {
     const uint32_t *replicate_id;
     const int32_t *reactant2;
     int32_t phi_pre_events;
+    int32_t n_regions;
+    const int32_t *region;
 } sim_problem;
 
 /* Execution of the event phase. */
@@ -142,6 +147,9 @@ typedef struct sim_device_opts {
  *   totals[D*R*Nc]        sum over nodes of each compartment after day d, [d][r][c]
  *   snap_u[n_record*R*Nn*Nc], snap_v[n_record*R*Nn]
  *                         u and phi at the end of each record day, [k][r][i][c] / [k][r][i]
+ *   regional[D*R*n_regions*Nc]
+ *                         X summed over the nodes of each region after day d's events, [d][r][j][c]
+ *                         (the inner sum of eq:goal for one sample trajectory)
  * Days not yet simulated read as 0. */
 typedef struct sim_output {
     int32_t *prevalence;
@@ -149,6 +157,7 @@ typedef struct sim_output {
     int64_t *totals;
     int32_t *snap_u;
     double *snap_v;
+    int64_t *regional;
 } sim_output;
 
 typedef struct sim_handle sim_handle;
@@ -268,6 +277,19 @@ int sim_slot_query(sim_handle *h, int32_t slot);
 /* The slot's current state after all enqueued work (synchronises):
  * u[n_rep*Nn*Nc] as [r][i][c], v[n_rep*Nn] as [r][i]. */
 int sim_slot_state(sim_handle *h, int32_t slot, int32_t *u, double *v);
+
+/* Goal function of the parameter-fitting study (Sec. 4.3): the R replicates of
+ * `instance` are the N sample trajectories of one parameter vector and
+ * reference[D*n_regions*Nc] ([d][j][c], host memory) holds the regional sums
+ * of the reference trajectory. Over days [d_begin, d_end), already simulated,
+ * with the integral over t taken as the sum over days:
+ *   G2  = sum_d sum_j || mean_i x_ij(d) - ref_j(d) ||^2               (eq:goal)
+ *   VG2 = sum_d sum_j (1/(N-1)) sum_i || x_ij(d) - mean_j(d) ||^2     (eq:goalvariance,
+ *                                                                      eq:goalsigma; 0 if N = 1)
+ * The per-day sums are reduced on the device, the days added in order on the
+ * host. Synchronises. SIM_ESTATE without regions or for days not simulated. */
+int sim_goal(sim_handle *h, int32_t instance, const int64_t *reference, int32_t d_begin, int32_t d_end,
+             double *G2, double *VG2);
 
 /* Release all resources. NULL is a no-op. */
 void sim_destroy(sim_handle *h);

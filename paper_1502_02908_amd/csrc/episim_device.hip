@@ -555,7 +555,7 @@ struct Tally {
 // (every lane of the workgroup belongs to the same trajectory).
 template <int NC>
 __device__ void flush_block(const Model &m, const DevState &s, const Tally<NC> &t, int32_t set, int32_t d_rec,
-                            int32_t d_ssa) {
+                            int32_t d_ssa, int32_t region) {
     __shared__ long long part[kWaves][2 + NC];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t S = (int64_t)s.n_inst * s.R;
@@ -582,6 +582,9 @@ __device__ void flush_block(const Model &m, const DevState &s, const Tally<NC> &
         } else if (i >= 2 && d_rec >= 0 && comp_on<NC>(m, i - 2)) {
             if (sum) atomicAdd((unsigned long long *)&s.totals[(d_rec * S + set) * m.nc + (i - 2)],
                                (unsigned long long)sum);
+            if (sum && region >= 0)
+                atomicAdd((unsigned long long *)&s.regional[((d_rec * S + set) * s.n_regions + region) * m.nc + (i - 2)],
+                          (unsigned long long)sum);
         }
     }
     __syncthreads();
@@ -591,7 +594,7 @@ __device__ void flush_block(const Model &m, const DevState &s, const Tally<NC> &
 // add them to the records of the lane's set.
 template <int NC>
 __device__ void flush_tile(const Model &m, const DevState &s, const Tally<NC> &t, int32_t set, int32_t d_rec,
-                           int32_t d_ssa) {
+                           int32_t d_ssa, int32_t region) {
     __shared__ long long part[kWaves][64][2 + NC];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t S = (int64_t)s.n_inst * s.R;
@@ -612,8 +615,12 @@ __device__ void flush_tile(const Model &m, const DevState &s, const Tally<NC> &t
             if (v[0]) atomicAdd(&s.prevalence[d_rec * S + set], (int32_t)v[0]);
 #pragma unroll
             for (int c = 0; c < NC; ++c)
-                if (comp_on<NC>(m, c) && v[2 + c])
+                if (comp_on<NC>(m, c) && v[2 + c]) {
                     atomicAdd((unsigned long long *)&s.totals[(d_rec * S + set) * m.nc + c], (unsigned long long)v[2 + c]);
+                    if (region >= 0)
+                        atomicAdd((unsigned long long *)&s.regional[((d_rec * S + set) * s.n_regions + region) * m.nc + c],
+                                  (unsigned long long)v[2 + c]);
+                }
         }
         if (d_ssa >= 0 && v[1])
             atomicAdd((unsigned long long *)&s.transitions[d_ssa * S + set], (unsigned long long)v[1]);
@@ -767,7 +774,8 @@ __global__ __launch_bounds__(kBlock) void k_day(Model m, DevState s, DevEvents e
     const int32_t d_rec = prologue ? d - 1 : -1;
     const int32_t d_ssa = ssa ? d : -1;
     // one lane per node; instances are padded to whole workgroups: one set per workgroup
-    flush_block<NC>(m, s, t, s.inst[(int64_t)blockIdx.x * kBlock], d_rec, d_ssa);
+    flush_block<NC>(m, s, t, s.inst[(int64_t)blockIdx.x * kBlock], d_rec, d_ssa,
+                    s.n_regions ? s.pos_region[(int64_t)blockIdx.x * kBlock] : -1);
     if (ssa) private_tasks<NC>(m, s, ev, d, blockIdx.x, s.Np / kLaneUnit, 0, 1, 1, s.status);
 }
 
@@ -802,10 +810,15 @@ __device__ __forceinline__ void heavy_chain(const Model &m, const DevState &s, c
     if (lane == 0) {
         if (prologue) {
             if (t.prev) atomicAdd(&s.prevalence[(d - 1) * S + set], (int32_t)t.prev);
+            const int32_t region = s.n_regions ? s.pos_region[pos] : -1;
 #pragma unroll
             for (int c = 0; c < NC; ++c)
-                if (comp_on<NC>(m, c) && t.tot[c])
+                if (comp_on<NC>(m, c) && t.tot[c]) {
                     atomicAdd((unsigned long long *)&s.totals[((d - 1) * S + set) * m.nc + c], (unsigned long long)t.tot[c]);
+                    if (region >= 0)
+                        atomicAdd((unsigned long long *)&s.regional[(((d - 1) * S + set) * s.n_regions + region) * m.nc + c],
+                                  (unsigned long long)t.tot[c]);
+                }
         }
         if (ssa && t.trans) atomicAdd((unsigned long long *)&s.transitions[d * S + set], (unsigned long long)t.trans);
     }
@@ -868,7 +881,8 @@ __global__ __launch_bounds__(kBlock) void k_day_tile(Model m, DevState s, DevEve
         day_wave<Rules>(m, s, pos * s.RL + r, d, prologue != 0, ssa != 0, t, r_end, status, &tp);
     }
     // instances are padded to whole tiles: one instance per workgroup
-    flush_tile<NC>(m, s, t, r < r_end ? s.inst[pos0] * s.R + r : -1, prologue ? d - 1 : -1, ssa ? d : -1);
+    flush_tile<NC>(m, s, t, r < r_end ? s.inst[pos0] * s.R + r : -1, prologue ? d - 1 : -1, ssa ? d : -1,
+                   s.n_regions ? s.pos_region[pos0] : -1);
     if (ssa)
         private_tasks<NC>(m, s, ev, d, blockIdx.x, s.Np / kTileNodes, (int32_t)blockIdx.y * 64, 64, r_end, status);
 }
@@ -1308,6 +1322,50 @@ __global__ __launch_bounds__(kEvBlock) void k_slot_events(Model m, DevState s, D
     }
 }
 
+// Goal function of the fitting study (Sec. 4.3, eq:goal, eq:goalvariance): for
+// day d = d_begin + blockIdx.x, with the N = R trajectories of one instance
+// (sets s0 .. s0 + N - 1) and the reference's regional sums of that day
+// ref[blockIdx.x][j][c], part[blockIdx.x] gets
+// sum_j ||mean_i x_ij - ref_j||^2 and part[gridDim.x + blockIdx.x] gets
+// sum_j sum_i ||x_ij - mean_j||^2 / (N - 1). One workgroup per day; the
+// (region, compartment) terms are summed in a fixed order.
+__global__ __launch_bounds__(kBlock) void k_goal(DevState s, int32_t nc, int64_t s0, int32_t N, const int64_t *ref,
+                                                 int32_t d_begin, double *part) {
+    __shared__ double sh_g[kBlock], sh_v[kBlock];
+    const int32_t d = d_begin + (int32_t)blockIdx.x;
+    const int64_t S = (int64_t)s.n_inst * s.R;
+    const int32_t J = s.n_regions;
+    double g = 0.0, v = 0.0;
+    for (int32_t q = threadIdx.x; q < J * nc; q += kBlock) {
+        const int32_t j = q / nc, c = q % nc;
+        long long sum = 0;
+        for (int32_t i = 0; i < N; ++i) sum += s.regional[(((int64_t)d * S + s0 + i) * J + j) * nc + c];
+        const double mean = (double)sum / (double)N;
+        const double diff = mean - (double)ref[((int64_t)blockIdx.x * J + j) * nc + c];
+        g += diff * diff;
+        double ss = 0.0;
+        for (int32_t i = 0; i < N; ++i) {
+            const double e = (double)s.regional[(((int64_t)d * S + s0 + i) * J + j) * nc + c] - mean;
+            ss += e * e;
+        }
+        v += N > 1 ? ss / (double)(N - 1) : 0.0;
+    }
+    sh_g[threadIdx.x] = g;
+    sh_v[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sh_g[threadIdx.x] += sh_g[threadIdx.x + w];
+            sh_v[threadIdx.x] += sh_v[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = sh_g[0];
+        part[gridDim.x + blockIdx.x] = sh_v[0];
+    }
+}
+
 // Start a slot: write its table entry, clear its error word and its records,
 // and load every replicate lane of it with the network's initial state.
 __global__ __launch_bounds__(kBlock) void k_slot_init(DevState s, int32_t nc, const int32_t *u0, const double *v0,
@@ -1364,7 +1422,8 @@ __global__ __launch_bounds__(kBlock) void k_persist(Model m, DevState s, DevEven
                         if (pos >= s.Np) break;
                         day_wave<Rules>(m, s, pos * s.RL + r, d, prologue, ssa, t, s.R, s.status);
                     }
-                    flush_tile<NC>(m, s, t, r < s.R ? s.inst[pos0] * s.R + r : -1, d_rec, d_ssa);
+                    flush_tile<NC>(m, s, t, r < s.R ? s.inst[pos0] * s.R + r : -1, d_rec, d_ssa,
+                                   s.n_regions ? s.pos_region[pos0] : -1);
                     if (ssa)
                         private_tasks<NC>(m, s, ev, d, tile % nx, nx, (int32_t)(tile / nx) * 64, 64, s.R, s.status);
                 }
@@ -1374,7 +1433,8 @@ __global__ __launch_bounds__(kBlock) void k_persist(Model m, DevState s, DevEven
                     const int64_t l = chunk * kBlock + threadIdx.x;
                     Tally<NC> t{};
                     day_wave<Rules>(m, s, l, d, prologue, ssa, t, s.R, s.status);
-                    flush_block<NC>(m, s, t, s.inst[chunk * kBlock], d_rec, d_ssa);
+                    flush_block<NC>(m, s, t, s.inst[chunk * kBlock], d_rec, d_ssa,
+                                    s.n_regions ? s.pos_region[chunk * kBlock] : -1);
                     if (ssa) private_tasks<NC>(m, s, ev, d, chunk, s.Np / kLaneUnit, 0, 1, 1, s.status);
                 }
             }
@@ -1564,6 +1624,18 @@ int launch_slot_init(const DevState &s, int32_t nc, const int32_t *u0, const dou
     SlotInfo in = info;
     void *args[] = {&ss, &n, &a, &b, &sl, &in};
     return (int)hipLaunchKernel((void *)&k_slot_init, dim3(grid), dim3(kBlock), args, 0, (hipStream_t)stream);
+}
+
+int launch_goal(const DevState &s, int32_t nc, int64_t s0, int32_t N, const int64_t *ref, int32_t d_begin,
+                int32_t n_days, double *part, void *stream) {
+    if (n_days <= 0) return hipSuccess;
+    DevState ss = s;
+    int32_t a = nc, n = N, db = d_begin;
+    int64_t b = s0;
+    const int64_t *r = ref;
+    double *pp = part;
+    void *args[] = {&ss, &a, &b, &n, &r, &db, &pp};
+    return (int)hipLaunchKernel((void *)&k_goal, dim3((unsigned)n_days), dim3(kBlock), args, 0, (hipStream_t)stream);
 }
 
 }  // namespace episim

@@ -156,6 +156,11 @@ int validate(const sim_problem *p, std::string *err) {
     if (p->n_trans < 1 || p->n_trans > SIM_MAX_TRANS) return *err = "n_trans must be in [1, 8]", SIM_EINVAL;
     if (p->n_rep < 1) return *err = "n_rep must be >= 1", SIM_EINVAL;
     if (p->phi_pre_events != 0 && p->phi_pre_events != 1) return *err = "phi_pre_events must be 0 or 1", SIM_EINVAL;
+    if (p->n_regions < 0 || p->n_regions > SIM_MAX_REGIONS || (p->n_regions > 0 && p->n_nodes > 0 && !p->region))
+        return *err = "n_regions must be in [0, SIM_MAX_REGIONS] with a region per node", SIM_EINVAL;
+    for (int64_t i = 0; p->n_regions > 0 && i < p->n_nodes; ++i)
+        if (p->region[i] < -1 || p->region[i] >= p->n_regions)
+            return *err = fmt("region[%lld] out of range", (long long)i), SIM_EINVAL;
     if (p->n_days < 0) return *err = "n_days < 0", SIM_EINVAL;
     if ((int64_t)p->n_nodes * p->n_rep > INT32_MAX)
         return *err = "n_nodes * n_rep must be below 2^31", SIM_EINVAL;
@@ -235,7 +240,8 @@ int same_model(const sim_problem *a, const sim_problem *b, std::string *err) {
     if (a->n_comp != b->n_comp || a->n_trans != b->n_trans || a->n_rep != b->n_rep || a->n_days != b->n_days ||
         a->day0 != b->day0 || a->phi_I_mask != b->phi_I_mask || a->phi_N_mask != b->phi_N_mask ||
         a->n_select != b->n_select || a->n_shift != b->n_shift || a->n_record != b->n_record ||
-        a->phi_pre_events != b->phi_pre_events || (a->reactant2 == nullptr) != (b->reactant2 == nullptr))
+        a->phi_pre_events != b->phi_pre_events || (a->reactant2 == nullptr) != (b->reactant2 == nullptr) ||
+        a->n_regions != b->n_regions)
         return *err = "packed problems must share sizes, replicates, horizon, day0, masks and record days", SIM_EINVAL;
     if (!eq(a->S, b->S, sizeof(int32_t) * Nc * Nt) || !eq(a->reactant, b->reactant, sizeof(int32_t) * Nt) ||
         !eq(a->uses_phi, b->uses_phi, sizeof(int32_t) * Nt) ||
@@ -271,7 +277,35 @@ constexpr int64_t kSoloHerds = 128;
 // first, the remaining positions of their units stay empty.
 constexpr int64_t kHeavyHerds = 32;
 
-int64_t order_nodes(const sim_problem *p, int layout, int64_t heavy, std::vector<int32_t> *pos_node) {
+// One group of herds, ranked largest first, placed from position base: solo
+// wavefronts first (one lane per node, large groups only), then dealt over the
+// units of the group; the group is padded to whole workgroups / tiles.
+// Returns the positions it takes.
+int64_t place_group(const std::vector<int32_t> &ranked, int layout, int64_t base, std::vector<int32_t> *pos_node) {
+    const int64_t n = (int64_t)ranked.size(), G = unit_nodes(layout), P = pad_nodes(layout);
+    // solo wavefronts only pay off when the rest still fills many wavefronts
+    const int64_t solo = (layout == LAYOUT_LANES && n >= 64 * kSoloHerds) ? kSoloHerds : 0;
+    const int64_t span = n == 0 ? 0 : ((solo * 64 + (n - solo) + P - 1) / P) * P;
+    pos_node->resize(base + span, -1);
+    for (int64_t q = 0; q < solo; ++q) (*pos_node)[base + q * 64] = ranked[q];
+    const int64_t b2 = base + solo * 64;
+    const int64_t U = (base + span - b2) / G;
+    int64_t q = solo;
+    for (int64_t j = 0; j < G && q < n; ++j)
+        for (int64_t uu = 0; uu < U && q < n; ++uu) {
+            const int64_t u = (j & 1) ? U - 1 - uu : uu;
+            (*pos_node)[b2 + u * G + j] = ranked[q++];
+        }
+    return span;
+}
+
+// Positions of one instance's nodes (pos_node[pos] = node or -1) and the
+// region of each position (-1 outside regions). With regions, every unit of
+// work holds herds of one region only, so the per-unit sums of the records
+// are also regional sums; the heavy herds' own units may mix regions (their
+// chains record on their own).
+int64_t order_nodes(const sim_problem *p, int layout, int64_t heavy, std::vector<int32_t> *pos_node,
+                    std::vector<int32_t> *pos_region) {
     const int64_t Nn = p->n_nodes, Nc = p->n_comp;
     // a herd's size is its largest population over the horizon: the SSA only
     // moves individuals between compartments of a node, so node totals follow
@@ -295,40 +329,42 @@ int64_t order_nodes(const sim_problem *p, int layout, int64_t heavy, std::vector
     std::vector<int32_t> rank(Nn);
     for (int64_t i = 0; i < Nn; ++i) rank[i] = (int32_t)i;
     std::stable_sort(rank.begin(), rank.end(), [&](int32_t a, int32_t b) { return size[a] > size[b]; });
-    const int64_t G = unit_nodes(layout), P = pad_nodes(layout);
-    // solo wavefronts only pay off when the rest still fills many wavefronts
-    const int64_t solo = (layout == LAYOUT_LANES && Nn >= 64 * kSoloHerds) ? kSoloHerds : 0;
+    const int64_t G = unit_nodes(layout);
     const int64_t hv = layout == LAYOUT_TILE ? std::min(heavy, Nn) : 0;
     const int64_t hv_span = ((hv + G - 1) / G) * G;
-    const int64_t rest = Nn - solo - hv;
-    const int64_t body = solo * 64 + hv_span + rest;
-    const int64_t Np = Nn == 0 ? 0 : ((body + P - 1) / P) * P;
-    pos_node->assign(Np, -1);
-    for (int64_t q = 0; q < solo; ++q) (*pos_node)[q * 64] = rank[q];
-    for (int64_t q = 0; q < hv; ++q) (*pos_node)[q] = rank[q];
-    const int64_t base = solo * 64 + hv_span;
-    const int64_t U = (Np - base) / G;
-    int64_t q = solo + hv;
-    for (int64_t j = 0; j < G && q < Nn; ++j)
-        for (int64_t uu = 0; uu < U && q < Nn; ++uu) {
-            const int64_t u = (j & 1) ? U - 1 - uu : uu;
-            (*pos_node)[base + u * G + j] = rank[q++];
-        }
-    return Np;
+    const int32_t J = p->n_regions > 0 ? p->n_regions : 0;
+    auto region_of = [&](int32_t i) { return J > 0 ? p->region[i] : -1; };
+    pos_node->assign(hv_span, -1);
+    pos_region->assign(hv_span, -1);
+    for (int64_t q = 0; q < hv; ++q) {
+        (*pos_node)[q] = rank[q];
+        (*pos_region)[q] = region_of(rank[q]);
+    }
+    // groups: the herds outside regions, then region by region (one group without regions)
+    std::vector<std::vector<int32_t>> groups(J + 1);
+    for (int64_t q = hv; q < Nn; ++q) groups[region_of(rank[q]) + 1].push_back(rank[q]);
+    int64_t base = hv_span;
+    for (int32_t j = -1; j < J; ++j) {
+        const int64_t span = place_group(groups[j + 1], layout, base, pos_node);
+        pos_region->resize(base + span, j);
+        base += span;
+    }
+    return base;
 }
 
 // Device buffer layout of one handle.
 struct Layout {
     size_t u, phi, node_id, inst, inst_off, seed, coef, alpha, beta, repid, status, ev_g, ev_gm, ev_node,
         ev_dest, ev_n, ev_meta, ev_smap, task_off, priv_off, day_slot_off, slot_pos, slot_key, lvl_ev_off, ev_slot_src, ev_slot_dst, lvl_off, lvl_ptr, prevalence, transitions, totals, snap_u, snap_v, rec_slot, slots,
-        u0, v0, heavy_pos, unit_heavy, total;
+        u0, v0, heavy_pos, unit_heavy, pos_region, regional, goal_ref, goal_part, total;
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 Layout layout_for(int64_t Np, int64_t n_nodes, int64_t n_inst, int64_t Nc, int64_t Nt, int64_t R, int64_t RL,
                   int64_t D, int64_t n_events, int64_t n_shift_ids, int64_t n_levels, int64_t n_tasks,
-                  int64_t n_units, int64_t n_day_slots, int64_t n_record, int64_t n_slots, int64_t n_heavy) {
+                  int64_t n_units, int64_t n_day_slots, int64_t n_record, int64_t n_slots, int64_t n_heavy,
+                  int64_t n_regions) {
     Layout l{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -374,6 +410,10 @@ Layout layout_for(int64_t Np, int64_t n_nodes, int64_t n_inst, int64_t Nc, int64
     // slot handles: the slot table and the network's initial state by position
     l.slots = take(sizeof(SlotInfo) * n_slots);
     l.heavy_pos = take(sizeof(int32_t) * n_heavy);
+    l.pos_region = take(n_regions ? sizeof(int32_t) * Np : 0);
+    l.regional = take(sizeof(int64_t) * D * S * n_regions * Nc);
+    l.goal_ref = take(sizeof(int64_t) * D * n_regions * Nc);
+    l.goal_part = take(n_regions ? sizeof(double) * 2 * D : 0);
     l.unit_heavy = take(n_units);
     l.u0 = take(n_slots ? sizeof(int32_t) * Nc * Np : 0);
     l.v0 = take(n_slots ? sizeof(double) * Np : 0);
@@ -396,6 +436,7 @@ struct Packed {
     std::vector<int64_t> lvl_off;   // task offsets of each level
     std::vector<int32_t> task_off;  // event offsets of each task
     std::vector<int32_t> priv_off;  // private tasks of (day, unit)
+    std::vector<int32_t> pos_region; // region of each position (-1 outside regions)
     std::vector<int32_t> heavy_pos; // positions of the herds whose chains get a wavefront each
     std::vector<uint8_t> unit_heavy;
     std::vector<int32_t> day_slot_off, slot_pos, ev_slot_src, ev_slot_dst;  // days run in LDS
@@ -423,6 +464,7 @@ int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, P
     const sim_problem *p0 = ps[0];
     if (n_slots < 0 || (n_slots > 0 && n != 1)) return *err = "a slot handle holds one network", SIM_EINVAL;
     if (n_slots > 0 && p0->n_record > 0) return *err = "slot handles keep no snapshots (n_record must be 0)", SIM_EINVAL;
+    if (n_slots > 0 && p0->n_regions > 0) return *err = "slot handles keep no regional records", SIM_EINVAL;
     if ((int64_t)n_slots * 64 > 65535 * 64) return *err = "too many slots", SIM_EINVAL;
     pk->n_inst = n;
     pk->n_slots = n_slots;
@@ -443,7 +485,9 @@ int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, P
         pk->inst_pos0[k] = (int32_t)pk->Np;
         const int64_t heavy = (pk->layout == LAYOUT_TILE && launch == SIM_LAUNCH_KERNELS)
                                   ? std::min<int64_t>(kHeavyHerds, ps[k]->n_nodes / 64) : 0;
-        const int64_t np_k = order_nodes(ps[k], pk->layout, heavy, &pos_node[k]);
+        std::vector<int32_t> preg;
+        const int64_t np_k = order_nodes(ps[k], pk->layout, heavy, &pos_node[k], &preg);
+        pk->pos_region.insert(pk->pos_region.end(), preg.begin(), preg.end());
         for (int64_t j = 0; j < heavy; ++j) pk->heavy_pos.push_back((int32_t)(pk->Np + j));
         pk->Np += np_k;
         pk->n_nodes += ps[k]->n_nodes;
@@ -647,7 +691,7 @@ int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, P
 Layout layout_of(const Packed &pk, const sim_problem *p0) {
     return layout_for(pk.Np, pk.n_nodes, pk.n_inst, pk.Nc, pk.Nt, pk.R, pk.RL, pk.D, pk.n_events, p0->n_shift,
                       pk.n_levels, pk.n_tasks, pk.n_units, (int64_t)pk.slot_pos.size(), pk.n_record, pk.n_slots,
-                      (int64_t)pk.heavy_pos.size());
+                      (int64_t)pk.heavy_pos.size(), p0->n_regions);
 }
 
 }  // namespace
@@ -921,6 +965,9 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
     s.n_heavy = (int32_t)pk.heavy_pos.size();
     s.heavy_pos = at<int32_t>(h->ws, l.heavy_pos);
     s.unit_heavy = s.n_heavy ? at<uint8_t>(h->ws, l.unit_heavy) : nullptr;
+    s.n_regions = p->n_regions;
+    s.pos_region = at<int32_t>(h->ws, l.pos_region);
+    s.regional = at<int64_t>(h->ws, l.regional);
     DevEvents &ev = h->ev;
     ev.g = at<int32_t>(h->ws, l.ev_g);
     ev.gm = at<int32_t>(h->ws, l.ev_gm);
@@ -976,6 +1023,7 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
         {(void *)ev.lvl_ptr, pk.lvl_ptr.data(), sizeof(int32_t) * (h->D + 1)},
         {(void *)s.rec_slot, pk.rec_slot.data(), sizeof(int32_t) * h->D},
         {(void *)s.heavy_pos, pk.heavy_pos.data(), sizeof(int32_t) * pk.heavy_pos.size()},
+        {(void *)s.pos_region, pk.pos_region.data(), s.n_regions ? sizeof(int32_t) * pk.pos_region.size() : 0},
         {(void *)s.unit_heavy, pk.unit_heavy.data(), s.n_heavy ? pk.unit_heavy.size() : 0},
     };
     for (const Up &up : ups) {
@@ -987,6 +1035,8 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
         }
     }
     rc = check_device(hipMemset(at<char>(h->ws, l.prevalence), 0, l.rec_slot - l.prevalence), &err, "clear records");
+    if (!rc && l.goal_ref > l.regional)
+        rc = check_device(hipMemset(at<char>(h->ws, l.regional), 0, l.goal_ref - l.regional), &err, "clear regional records");
     for (int32_t j = 0; !rc && j < std::max(h->n_slots, 1); ++j)
         rc = check_device(hipMemcpy(s.status + j, &ok, sizeof ok, hipMemcpyHostToDevice), &err, "upload status");
     if (rc) {
@@ -1073,6 +1123,11 @@ int sim_run(sim_handle *h, int32_t n_days) {
     int rc = check_device(hipMemsetAsync(h->st.prevalence + (size_t)d0 * S, 0, sizeof(int32_t) * n_days * S, h->stream), &h->err, "clear");
     if (!rc) rc = check_device(hipMemsetAsync(h->st.transitions + (size_t)d0 * S, 0, sizeof(int64_t) * n_days * S, h->stream), &h->err, "clear");
     if (!rc) rc = check_device(hipMemsetAsync(h->st.totals + (size_t)d0 * S * h->Nc, 0, sizeof(int64_t) * n_days * S * h->Nc, h->stream), &h->err, "clear");
+    if (!rc && h->st.n_regions > 0) {
+        const size_t per_day = (size_t)S * h->st.n_regions * h->Nc;
+        rc = check_device(hipMemsetAsync(h->st.regional + (size_t)d0 * per_day, 0, sizeof(int64_t) * n_days * per_day, h->stream),
+                          &h->err, "clear");
+    }
     if (rc) return rc;
     if (h->launch == SIM_LAUNCH_PERSISTENT && h->L > 0) {
         char why[256] = {0};
@@ -1163,6 +1218,7 @@ int sim_trajectory(sim_handle *h, sim_output *out) {
         {out->totals, h->st.totals, sizeof(int64_t) * DS * h->Nc},
         {out->snap_u, h->st.snap_u, sizeof(int32_t) * h->n_record * (size_t)h->R * h->n_nodes * h->Nc},
         {out->snap_v, h->st.snap_v, sizeof(double) * h->n_record * (size_t)h->R * h->n_nodes},
+        {out->regional, h->st.regional, sizeof(int64_t) * DS * h->st.n_regions * h->Nc},
     };
     for (const Down &d : downs) {
         if (!d.dst || d.bytes == 0) continue;
@@ -1250,6 +1306,38 @@ int sim_kernel_times(sim_handle *h, int32_t enable, double *ms, int64_t *launche
     for (int k = 0; k < 4; ++k) {
         if (ms) ms[k] = h->ms[k];
         if (launches) launches[k] = h->launches[k];
+    }
+    return SIM_OK;
+}
+
+int sim_goal(sim_handle *h, int32_t instance, const int64_t *reference, int32_t d_begin, int32_t d_end, double *G2,
+             double *VG2) {
+    if (!h || !reference || !G2 || !VG2) return SIM_EINVAL;
+    h->err.clear();
+    if (h->st.n_regions <= 0) return h->err = "the problem has no regions", SIM_ESTATE;
+    if (instance < 0 || instance >= h->n_inst) return h->err = "instance out of range", SIM_EINVAL;
+    if (d_begin < 0 || d_end > h->D || d_end < d_begin) return h->err = "days out of range", SIM_EINVAL;
+    if (d_end > h->day) return h->err = fmt("day %d has not been simulated", d_end - 1), SIM_ESTATE;
+    *G2 = 0.0;
+    *VG2 = 0.0;
+    const int32_t n = d_end - d_begin;
+    if (n == 0) return SIM_OK;
+    const size_t per_day = (size_t)h->st.n_regions * h->Nc;
+    int64_t *ref = at<int64_t>(h->ws, h->lay.goal_ref);
+    double *part = at<double>(h->ws, h->lay.goal_part);
+    int rc = check_device(hipMemcpyAsync(ref, reference + (size_t)d_begin * per_day, sizeof(int64_t) * n * per_day,
+                                         hipMemcpyHostToDevice, h->stream), &h->err, "upload reference");
+    if (!rc)
+        rc = check_device((hipError_t)launch_goal(h->st, h->Nc, (int64_t)instance * h->R, h->R, ref, d_begin, n, part,
+                                                  h->stream), &h->err, "goal kernel");
+    std::vector<double> host(2 * (size_t)n);
+    if (!rc) rc = sim_sync(h);
+    if (!rc) rc = check_device(hipMemcpy(host.data(), part, sizeof(double) * host.size(), hipMemcpyDeviceToHost), &h->err, "download");
+    if (rc) return rc;
+    // the integral over t as the sum over days, in day order
+    for (int32_t k = 0; k < n; ++k) {
+        *G2 += host[k];
+        *VG2 += host[n + k];
     }
     return SIM_OK;
 }

@@ -89,6 +89,9 @@ struct DevState {
     int32_t *snap_u;            // [n_record][R][n_nodes][nc]
     double *snap_v;             // [n_record][R][n_nodes]
     const int32_t *rec_slot;    // [D] snapshot slot of day d, or -1
+    int32_t n_regions;          // regions of the goal function's aggregates (0: none)
+    const int32_t *pos_region;  // [Np] region of each position, -1 outside regions
+    int64_t *regional;          // [D][sets][n_regions][nc] compartment sums per region
 };
 
 struct DevEvents {
@@ -147,6 +150,8 @@ int launch_event_day(const Model &m, const DevState &s, const DevEvents &ev, int
                      int32_t s0, int32_t ns, int64_t e0, int64_t ne, void *stream);
 int launch_slot_events(const Model &m, const DevState &s, const DevEvents &ev, int32_t step, int32_t k,
                        int32_t k_end, int64_t max_count, void *stream);
+int launch_goal(const DevState &s, int32_t nc, int64_t s0, int32_t N, const int64_t *ref, int32_t d_begin,
+                int32_t n_days, double *part, void *stream);
 int launch_slot_init(const DevState &s, int32_t nc, const int32_t *u0, const double *v0, int32_t slot,
                      const SlotInfo &info, void *stream);
 int launch_persistent(const Model &m, const DevState &s, const DevEvents &ev, int32_t d_begin,

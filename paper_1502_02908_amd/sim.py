@@ -42,6 +42,7 @@ class sim_problem(C.Structure):
         ("n_record", C.c_int32), ("record_days", _i32p),
         ("seed", C.c_uint32), ("replicate_id", _u32p),
         ("reactant2", _i32p), ("phi_pre_events", C.c_int32),
+        ("n_regions", C.c_int32), ("region", _i32p),
     ]
 
 
@@ -53,7 +54,7 @@ class sim_device_opts(C.Structure):
 
 class sim_output(C.Structure):
     _fields_ = [("prevalence", _i32p), ("transitions", _i64p), ("totals", _i64p),
-                ("snap_u", _i32p), ("snap_v", _f64p)]
+                ("snap_u", _i32p), ("snap_v", _f64p), ("regional", _i64p)]
 
 
 # every symbol of include/episim.h with its C signature
@@ -70,6 +71,7 @@ SIGNATURES = {
     "sim_last_error": (C.c_char_p, [C.c_void_p]),
     "sim_plan_levels": (C.c_int, [C.c_int64, _i32p, _i32p, _i32p, _i32p, C.c_int32, _i32p, _i32p]),
     "sim_kernel_times": (C.c_int, [C.c_void_p, C.c_int32, _f64p, _i64p]),
+    "sim_goal": (C.c_int, [C.c_void_p, C.c_int32, _i64p, C.c_int32, C.c_int32, _f64p, _f64p]),
     "sim_create_batch": (C.c_int, [C.POINTER(C.POINTER(sim_problem)), C.c_int32, C.POINTER(sim_device_opts),
                                    C.POINTER(C.c_void_p)]),
     "sim_workspace_bytes_batch": (C.c_size_t, [C.POINTER(C.POINTER(sim_problem)), C.c_int32,
@@ -127,6 +129,8 @@ def _marshal(p):
                replicate_id=np.ascontiguousarray(p.replicate_id, dtype=np.uint32))
     r2 = getattr(p, "reactant2", None)
     arr["reactant2"] = None if r2 is None else i32(r2)
+    n_regions = int(getattr(p, "n_regions", 0) or 0)
+    arr["region"] = i32(p.region) if n_regions > 0 else None
     s = sim_problem(
         p.n_nodes, p.n_comp, p.n_trans, p.n_rep, p.n_days, getattr(p, "day0", 0),
         _p(arr["u0"], _i32p), _p(arr["v0"], _f64p),
@@ -141,7 +145,8 @@ def _marshal(p):
         _p(arr["ev_shift"], _i32p),
         len(arr["record_days"]), _p(arr["record_days"], _i32p),
         int(p.seed) & 0xFFFFFFFF, _p(arr["replicate_id"], _u32p),
-        None if arr["reactant2"] is None else _p(arr["reactant2"], _i32p), int(getattr(p, "phi_pre_events", 0)))
+        None if arr["reactant2"] is None else _p(arr["reactant2"], _i32p), int(getattr(p, "phi_pre_events", 0)),
+        n_regions, None if arr["region"] is None else _p(arr["region"], _i32p))
     return s, arr
 
 
@@ -186,6 +191,7 @@ class Simulator:
         self.Nn = sum(q.n_nodes for q in probs)
         self.node_counts = [q.n_nodes for q in probs]
         self.n_record = 0 if probs[0].record_days is None else len(probs[0].record_days)
+        self.n_regions = int(getattr(probs[0], "n_regions", 0) or 0)
         self._h = C.c_void_p()
         self._ws = None
         torch = _torch_cuda()
@@ -223,16 +229,32 @@ class Simulator:
         self._check(lib().sim_sync(self._h))
 
     def trajectory(self):
-        """Daily records [D][set] (set = instance * R + replicate) and snapshots."""
+        """Daily records [D][set] (set = instance * R + replicate), snapshots,
+        and with regions the regional sums [D][set][region][compartment]."""
         D, R, Nc, Nn, K = self.D, self.R, self.Nc, self.Nn, self.n_record
         S = self.n_inst * R
         out = dict(prevalence=np.zeros((D, S), np.int32), transitions=np.zeros((D, S), np.int64),
                    totals=np.zeros((D, S, Nc), np.int64), snap_u=np.zeros((K, R, Nn, Nc), np.int32),
                    snap_v=np.zeros((K, R, Nn), np.float64))
+        if self.n_regions:
+            out["regional"] = np.zeros((D, S, self.n_regions, Nc), np.int64)
         o = sim_output(_p(out["prevalence"], _i32p), _p(out["transitions"], _i64p), _p(out["totals"], _i64p),
-                       _p(out["snap_u"], _i32p), _p(out["snap_v"], _f64p))
+                       _p(out["snap_u"], _i32p), _p(out["snap_v"], _f64p),
+                       _p(out["regional"], _i64p) if self.n_regions else None)
         self._check(lib().sim_trajectory(self._h, C.byref(o)))
         return out
+
+    def goal(self, reference, instance=0, d_begin=0, d_end=None):
+        """(G2, VG2) of instance's R replicates against reference[D][region][compartment]
+        (the regional sums of the reference trajectory) over days [d_begin, d_end)."""
+        ref = np.ascontiguousarray(reference, dtype=np.int64)
+        if ref.shape != (self.D, self.n_regions, self.Nc):
+            raise ValueError(f"reference must have shape {(self.D, self.n_regions, self.Nc)}")
+        g, vg = C.c_double(), C.c_double()
+        d_end = self.D if d_end is None else d_end
+        self._check(lib().sim_goal(self._h, int(instance), _p(ref, _i64p), int(d_begin), int(d_end),
+                                   C.byref(g), C.byref(vg)))
+        return g.value, vg.value
 
     def get_state(self):
         u = np.zeros((self.R, self.Nn, self.Nc), np.int32)

@@ -66,6 +66,12 @@ BAD = {
     "day past horizon": lambda p: p.ev_day.__setitem__(-1, p.n_days),
     "negative n": lambda p: p.ev_n.__setitem__(0, -2),
     "record days not ascending": lambda p: setattr(p, "record_days", np.array([5, 5], np.int32)),
+    "region out of range": lambda p: (setattr(p, "n_regions", 3),
+                                      setattr(p, "region", np.full(p.n_nodes, 3, np.int32))),
+    "region below -1": lambda p: (setattr(p, "n_regions", 3),
+                                  setattr(p, "region", np.full(p.n_nodes, -2, np.int32))),
+    "too many regions": lambda p: (setattr(p, "n_regions", 4097),
+                                   setattr(p, "region", np.zeros(p.n_nodes, np.int32))),
 }
 
 
