@@ -297,6 +297,60 @@ __device__ __forceinline__ double lane_f64(double v, int lane) {
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// Inclusive prefix sum over the 64 lanes of a wavefront: shifts by 1, 2, 4, 8
+// within rows of 16 lanes, then lane 15's sum into rows 1 and 3 and lane 31's
+// into rows 2 and 3 (lanes without a source add +0).
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ double dpp_f64(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, Ctrl, RowMask, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), Ctrl, RowMask, 0xf, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+__device__ __forceinline__ double wave_prefix_sum(double v) {
+    v = v + dpp_f64<0x111, 0xf>(v);  // row_shr:1
+    v = v + dpp_f64<0x112, 0xf>(v);  // row_shr:2
+    v = v + dpp_f64<0x114, 0xf>(v);  // row_shr:4
+    v = v + dpp_f64<0x118, 0xf>(v);  // row_shr:8
+    v = v + dpp_f64<0x142, 0xa>(v);  // row_bcast:15
+    v = v + dpp_f64<0x143, 0xc>(v);  // row_bcast:31
+    return v;
+}
+
+// The clock of a round without the attempt-by-attempt sum. While the running
+// clock stays in one binade [2^e, 2^(e+1)) every partial sum is an integer
+// multiple of its spacing h = 2^(e-52), and adding a waiting time rounds to
+// the nearest multiple: s + tau -> (s/h + rn(tau/h)) h. Those integers add
+// exactly (each partial sum that matters stays below 2^53), so one prefix
+// sum over the lanes gives every partial sum of the round bit for bit. A sum
+// that reaches 2^(e+1) leaves the binade: for e = -1 that is the window end
+// (the attempt does not fire, whatever the rounding above 1); otherwise the
+// round has to be summed attempt by attempt, and so has a round in which a
+// waiting time lies exactly half-way between two multiples (ties round to
+// even, which depends on the partial sum) or whose clock is 0. Returns the
+// number of attempts that fire (-1: sum attempt by attempt) and their clock.
+__device__ __forceinline__ int clock_by_scan(double clock, double tau, double *clock_out) {
+    const long long cb = __double_as_longlong(clock);
+    const int e = (int)((cb >> 52) & 0x7ff) - 1023;
+    if (!(clock > 0.0) || e < -960 || e > -1) return -1;
+    const double up = __longlong_as_double((long long)(1023 + 52 - e) << 52);    // 2^(52-e)
+    const double down = __longlong_as_double((long long)(1023 - 52 + e) << 52);  // 2^(e-52)
+    const double S0 = clock * up;                                                // in [2^52, 2^53)
+    const double T = 0x1p53 - S0;
+    const double v = tau * up;
+    const double fl = floor(v);
+    const double fr = v - fl;
+    const double mk = fr > 0.5 ? fl + 1.0 : fl;
+    const double P = wave_prefix_sum(mk);
+    const int A = __popcll(__ballot(P < T));
+    const unsigned long long upto = A >= 63 ? ~0ull : ((2ull << A) - 1ull);
+    if ((__ballot(fr == 0.5) & upto) != 0ull) return -1;
+    if (A < 64 && e != -1) return -1;
+    *clock_out = A > 0 ? (S0 + lane_f64(P, A - 1)) * down : clock;
+    return A;
+}
+
 // One chain walked by the whole wavefront, 64 attempts per round, for paired
 // classes. Attempt kbase + i belongs to lane i; its draws do not depend on the
 // state, but the transition it picks (eq:sampling2) and its waiting time
@@ -364,27 +418,32 @@ __device__ __forceinline__ void pairs_walk_block(const Model &m, Chain<2 * NP, 2
             if (!changed) break;
         }
         const double tau = E / lam;  // lambda = 0: tau = inf, never fires
-        // the clock, attempt by attempt; most rounds end below the window end.
-        // The waiting times go through LDS and come back as broadcast reads,
-        // which issue ahead of the dependent additions.
-        sh_tau[wave][lane] = tau;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        double t = c.clock;
+        double clock;
+        int A = clock_by_scan(c.clock, tau, &clock);
+        if (A < 0) {
+            // the clock, attempt by attempt. The waiting times go through LDS
+            // and come back as broadcast reads, which issue ahead of the
+            // dependent additions.
+            sh_tau[wave][lane] = tau;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            double t = c.clock;
 #pragma unroll 16
-        for (int i = 0; i < 64; ++i) t = t + sh_tau[wave][i];
-        int A = 64;
-        double clock = t;
-        if (!(t < 1.0)) {
-            double s = c.clock, mine = 0.0;
+            for (int i = 0; i < 64; ++i) t = t + sh_tau[wave][i];
+            A = 64;
+            clock = t;
+            if (!(t < 1.0)) {
+                double s = c.clock, mine = 0.0;
 #pragma unroll 16
-            for (int i = 0; i < 64; ++i) {
-                s = s + sh_tau[wave][i];
-                if ((int)lane == i) mine = s;
+                for (int i = 0; i < 64; ++i) {
+                    s = s + sh_tau[wave][i];
+                    if ((int)lane == i) mine = s;
+                }
+                A = __popcll(__ballot(mine < 1.0));
+                clock = A > 0 ? lane_f64(mine, A - 1) : c.clock;
             }
-            A = __popcll(__ballot(mine < 1.0));
-            clock = A > 0 ? lane_f64(mine, A - 1) : c.clock;
+            __builtin_amdgcn_wave_barrier();  // the next round rewrites sh_tau
         }
         bool limit = false;
         if (c.fired + A >= SIM_MAX_FIRED) {
@@ -409,7 +468,6 @@ __device__ __forceinline__ void pairs_walk_block(const Model &m, Chain<2 * NP, 2
         }
         if (A < 64 || !(c.lam > 0.0)) return;
         kbase = kbase + 64;
-        __builtin_amdgcn_wave_barrier();  // the next round rewrites sh_tau
     }
 }
 
