@@ -389,6 +389,7 @@ __device__ __forceinline__ void pairs_walk_block(const Model &m, Chain<2 * NP, 2
             for (int k = 0; k < NT; ++k) j += c.cum[k] < target ? 1 : 0;
         }
         double lam = c.lam;
+        int settle = 63;  // the attempts 0 .. settle need their final picks
         for (int pass = 0; pass < 64; ++pass) {
             double x[NT];
 #pragma unroll
@@ -412,12 +413,31 @@ __device__ __forceinline__ void pairs_walk_block(const Model &m, Chain<2 * NP, 2
             int jn = 0;
 #pragma unroll
             for (int k = 0; k < NT; ++k) jn += cum[k] < target ? 1 : 0;
-            const bool changed = __ballot(jn != j) != 0ull;
+            const unsigned long long moved = __ballot(jn != j);
             j = jn;
             lam = l;
-            if (!changed) break;
+            if (moved == 0ull) break;
+            if (pass == 0) continue;  // large herds settle in one or two passes without it
+            // An attempt whose clock surely lands past the window end stops
+            // the chain, so only the picks up to it have to settle. If none of
+            // them moved in this pass, they and their waiting times are those
+            // of the attempt-by-attempt walk (each was computed from the
+            // unchanged picks below it); the clock bound then comes from exact
+            // waiting times, and its margin is far above the rounding of the
+            // approximate prefix sum.
+            const double reach = c.clock + wave_prefix_sum(l > 0.0 ? E / l : __builtin_inf());
+            const unsigned long long over = __ballot(!(reach < 1.0 + 0x1p-30));
+            if (over != 0ull) {
+                const int a = __ffsll((long long)over) - 1;
+                if ((moved & (a >= 63 ? ~0ull : ((2ull << a) - 1ull))) == 0ull) {
+                    settle = a;
+                    break;
+                }
+            }
         }
-        const double tau = E / lam;  // lambda = 0: tau = inf, never fires
+        // lambda = 0: tau = inf, never fires; attempts past `settle` do not
+        // fire and may hold unsettled picks
+        const double tau = (int)lane > settle ? __builtin_inf() : E / lam;
         double clock;
         int A = clock_by_scan(c.clock, tau, &clock);
         if (A < 0) {
@@ -696,14 +716,76 @@ struct TileParams {
     uint32_t *key0, *key1;
 };
 
+// Draw n of the tot individuals in the compartments of mask from x without
+// replacement (Sec. 3.2): draw q picks the individual at a uniform position
+// in [0, remaining) of the selected compartments in ascending order, from the
+// Philox block (q / 2, g, d, 1). Removes them from x and counts them in take.
+// pre, when given, holds the first kPreDraws draws (computed ahead in parallel).
+constexpr int kPreDraws = 4;
+
+template <int NC>
+__device__ __forceinline__ void draw_individuals(int32_t *x, int32_t *take, uint32_t mask, int32_t n, long long tot,
+                                                 uint32_t g, int32_t d, uint32_t key0, uint32_t key1,
+                                                 const uint64_t *pre = nullptr) {
+    long long cum[NC];  // running sums of the selected compartments, ascending
+    long long run = 0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        take[c] = 0;
+        run += ((mask >> c) & 1u) ? x[c] : 0;
+        cum[c] = run;
+    }
+    Word4 o{0, 0, 0, 0};
+    for (int32_t q = 0; q < n; ++q) {
+        uint64_t bits;
+        if (pre && q < kPreDraws) {
+            bits = pre[q];
+        } else if ((q & 1) == 0) {
+            o = philox4x32_10(Word4{(uint32_t)q >> 1, g, (uint32_t)d, 1u}, key0, key1);
+            bits = ((uint64_t)o.b << 32) | o.a;
+        } else {
+            bits = ((uint64_t)o.d << 32) | o.c;
+        }
+        const uint64_t pick = __umul64hi(bits, (uint64_t)tot);  // uniform on [0, tot)
+        // the compartment holding individual `pick` in ascending order is the
+        // number of running sums at or below it (a compartment outside the
+        // mask, or empty, repeats the sum before it and is passed over)
+        int chosen = 0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) chosen += (uint64_t)cum[c] <= pick ? 1 : 0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const int hit = c == chosen ? 1 : 0;
+            x[c] -= hit;
+            take[c] += hit;
+            cum[c] -= c >= chosen ? 1 : 0;
+        }
+        tot -= 1;
+    }
+}
+
+// Compartment that an individual drawn from compartment c lands in (internal
+// and external transfers): 4 bits per source compartment of the event's map.
+__device__ __forceinline__ int shifted(uint32_t smap, int c) { return (int)((smap >> (4 * c)) & 0xFu); }
+
+// What a kernel may add to day_wave: after_prologue() runs on every lane once
+// the previous day is closed, before the SSA; after_ssa(state, active) sees the
+// lane's chain state after the SSA and returns whether day_wave stores it.
+struct NoHooks {
+    __device__ void after_prologue() const {}
+    template <class St>
+    __device__ bool after_ssa(const St &, bool) const { return true; }
+};
+
 // The day phase for the lane l of a wavefront (every lane of the wavefront
 // must call it; lanes with l >= L or replicate lane r >= r_end take part in
 // the wavefront-level steps only): close day d-1 (phi update + record) if
 // prologue, then run the SSA of day d if ssa. Adds the lane's counts to t.
-template <class Rules>
+template <class Rules, class Hooks = NoHooks>
 __device__ __forceinline__ void day_wave(const Model &m, const DevState &s, int64_t l, int32_t d,
                                          bool prologue, bool ssa, Tally<Rules::NC> &t, int32_t r_end,
-                                         unsigned long long *status, const TileParams *tp = nullptr) {
+                                         unsigned long long *status, const TileParams *tp = nullptr,
+                                         const Hooks &hooks = Hooks{}) {
     constexpr int NC = Rules::NC, NT = Rules::NT;
     const int32_t R = s.R, RL = s.RL;
     const bool in_range = l < s.L;
@@ -764,6 +846,7 @@ __device__ __forceinline__ void day_wave(const Model &m, const DevState &s, int6
         }
         if (__double_as_longlong(phi) != __double_as_longlong(phi_in)) s.phi[l] = phi;
     }
+    hooks.after_prologue();
     if (!ssa) return;
     typename Rules::State ch;
     const int lane_t = threadIdx.x & 63;
@@ -782,7 +865,7 @@ __device__ __forceinline__ void day_wave(const Model &m, const DevState &s, int6
     Rules::rates(m, ch);
     run_chains<Rules>(m, ch, active, node, (uint32_t)d, key0, key1, status, set);
     t.trans += ch.fired;
-    if (active && ch.fired) {
+    if (hooks.after_ssa(ch, active) && active && ch.fired) {
 #pragma unroll
         for (int c = 0; c < NC; ++c)
             if (comp_on<NC>(m, c)) s.u[(int64_t)c * s.L + l] = (int32_t)ch.xd[c];
@@ -821,20 +904,144 @@ __device__ __forceinline__ void private_tasks(const Model &m, const DevState &s,
     }
 }
 
+// One private event of a workgroup's day, staged in LDS.
+struct PrivEv {
+    uint32_t meta, smap;
+    int32_t n, g, gm, node;
+};
+
+// A unit's private events in LDS (one lane per node): the event a thread
+// fetched at the start is parked once the prologue is done, and the counts
+// each lane holds after the SSA are handed over instead of being stored.
+template <int NC>
+struct LdsPrivHooks {
+    PrivEv *pe;
+    int32_t (*x)[kBlock];
+    int32_t *touch;
+    const PrivEv *mine;
+    bool has, lds;
+    __device__ void after_prologue() const {
+        if (has) pe[threadIdx.x] = *mine;
+    }
+    template <class St>
+    __device__ bool after_ssa(const St &ch, bool active) const {
+        if (!lds) return true;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) x[c][threadIdx.x] = active ? (int32_t)ch.xd[c] : 0;
+        touch[threadIdx.x] = active && ch.fired ? 1 : 0;
+        return false;
+    }
+};
+
+// One private task (a run of one node's single-node events, i the first)
+// applied to the counts in LDS, with the arithmetic of event_task. A run that
+// draws has the node to itself; runs of additions only may share it and add
+// atomically.
+template <int NC>
+__device__ void private_task_lds(const PrivEv *pe, int i, int n_ev, int32_t (*xs)[kBlock], int32_t *touch,
+                                 int32_t base, int32_t d, uint32_t key0, uint32_t key1, int32_t set,
+                                 unsigned long long *status) {
+    const int loc = pe[i].node - base;
+    int end = i + 1;
+    while (end < n_ev && (pe[end].meta & kMetaCont)) ++end;
+    bool draws = false;
+    for (int j = i; j < end; ++j) draws = draws || (int)(pe[j].meta & kEvKindMask) != SIM_ENTER;
+    touch[loc] = 1;
+    if (!draws) {
+        for (int j = i; j < end; ++j) {
+            const uint32_t mask = (pe[j].meta >> 2) & 0xffu;
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                if ((mask >> c) & 1u) atomicAdd(&xs[c][loc], pe[j].n);
+        }
+        return;
+    }
+    int32_t x[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) x[c] = xs[c][loc];
+    for (int j = i; j < end; ++j) {
+        const uint32_t meta = pe[j].meta;
+        const int kind = (int)(meta & kEvKindMask);
+        const uint32_t mask = (meta >> 2) & 0xffu;
+        const int32_t n = pe[j].n;
+        if (kind == SIM_ENTER) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                if ((mask >> c) & 1u) x[c] += n;
+            continue;
+        }
+        long long tot = 0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if ((mask >> c) & 1u) tot += x[c];
+        if ((long long)n > tot) {
+            atomicMin(status, ((unsigned long long)(uint32_t)pe[j].gm << 32) | (unsigned long long)(uint32_t)set);
+            break;
+        }
+        int32_t take[NC];
+        draw_individuals<NC>(x, take, mask, n, tot, (uint32_t)pe[j].g, d, key0, key1);
+        if (kind == SIM_INTERNAL) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                if (take[c]) {
+                    const int to = shifted(pe[j].smap, c);
+#pragma unroll
+                    for (int cc = 0; cc < NC; ++cc)
+                        if (cc == to) x[cc] += take[c];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) xs[c][loc] = x[c];
+}
+
 template <class Rules>
 __global__ __launch_bounds__(kBlock) void k_day(Model m, DevState s, DevEvents ev, int32_t d, int32_t prologue,
                                                 int32_t ssa) {
     constexpr int NC = Rules::NC;
+    __shared__ PrivEv sh_pe[kBlock];
+    __shared__ int32_t sh_x[NC][kBlock];
+    __shared__ int32_t sh_touch[kBlock];
     if (!block_ok(s.status)) return;
     const int64_t l = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    // The unit's private events of the day. With at most one per thread they
+    // are fetched now, alongside the state, and applied to the counts in LDS
+    // right after the SSA; each node is then stored once. Otherwise the SSA
+    // stores its counts and the tasks run on global memory.
+    const int64_t k = (int64_t)d * (s.Np / kLaneUnit) + blockIdx.x;
+    const int32_t pe0 = ssa ? ev.priv_ev_off[k] : 0;
+    const int32_t npe = ssa ? ev.priv_ev_off[k + 1] - pe0 : 0;
+    const bool lds = npe <= kBlock;
+    const bool has = lds && (int)threadIdx.x < npe;
+    PrivEv mine{0u, 0u, 0, 0, 0, 0};
+    if (has) {
+        const int64_t e = pe0 + threadIdx.x;
+        mine = PrivEv{ev.meta[e], ev.smap[e], ev.n[e], ev.g[e], ev.gm[e], ev.node[e]};
+    }
+    const LdsPrivHooks<NC> hooks{sh_pe, sh_x, sh_touch, &mine, has, lds && ssa};
     Tally<NC> t{};
-    day_wave<Rules>(m, s, l, d, prologue != 0, ssa != 0, t, s.R, s.status);
+    day_wave<Rules>(m, s, l, d, prologue != 0, ssa != 0, t, s.R, s.status, nullptr, hooks);
     const int32_t d_rec = prologue ? d - 1 : -1;
     const int32_t d_ssa = ssa ? d : -1;
     // one lane per node; instances are padded to whole workgroups: one set per workgroup
-    flush_block<NC>(m, s, t, s.inst[(int64_t)blockIdx.x * kBlock], d_rec, d_ssa,
-                    s.n_regions ? s.pos_region[(int64_t)blockIdx.x * kBlock] : -1);
-    if (ssa) private_tasks<NC>(m, s, ev, d, blockIdx.x, s.Np / kLaneUnit, 0, 1, 1, s.status);
+    const int32_t set = s.inst[(int64_t)blockIdx.x * kBlock];
+    flush_block<NC>(m, s, t, set, d_rec, d_ssa, s.n_regions ? s.pos_region[(int64_t)blockIdx.x * kBlock] : -1);
+    if (!ssa) return;
+    if (!lds) {
+        private_tasks<NC>(m, s, ev, d, blockIdx.x, s.Np / kLaneUnit, 0, 1, 1, s.status);
+        return;
+    }
+    // flush_block's barriers make the parked events and counts visible
+    if (has && !(sh_pe[threadIdx.x].meta & kMetaCont))
+        private_task_lds<NC>(sh_pe, threadIdx.x, npe, sh_x, sh_touch, (int32_t)(blockIdx.x * kBlock), d,
+                             s.seed[set], s.repid[set], set, s.status);
+    __syncthreads();
+    if (sh_touch[threadIdx.x]) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (comp_on<NC>(m, c)) s.u[(int64_t)c * s.L + l] = sh_x[c][threadIdx.x];
+    }
 }
 
 // Replicate tiles (replicate lanes in groups of 64): workgroup (x, y) takes
@@ -953,54 +1160,6 @@ __global__ __launch_bounds__(kBlock) void k_day_tile(Model m, DevState s, DevEve
 // ---------------------------------------------------------------------------
 
 
-// Draw n of the tot individuals in the compartments of mask from x without
-// replacement (Sec. 3.2): draw q picks the individual at a uniform position
-// in [0, remaining) of the selected compartments in ascending order, from the
-// Philox block (q / 2, g, d, 1). Removes them from x and counts them in take.
-// pre, when given, holds the first kPreDraws draws (computed ahead in parallel).
-constexpr int kPreDraws = 4;
-
-template <int NC>
-__device__ __forceinline__ void draw_individuals(int32_t *x, int32_t *take, uint32_t mask, int32_t n, long long tot,
-                                                 uint32_t g, int32_t d, uint32_t key0, uint32_t key1,
-                                                 const uint64_t *pre = nullptr) {
-    long long cum[NC];  // running sums of the selected compartments, ascending
-    long long run = 0;
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        take[c] = 0;
-        run += ((mask >> c) & 1u) ? x[c] : 0;
-        cum[c] = run;
-    }
-    Word4 o{0, 0, 0, 0};
-    for (int32_t q = 0; q < n; ++q) {
-        uint64_t bits;
-        if (pre && q < kPreDraws) {
-            bits = pre[q];
-        } else if ((q & 1) == 0) {
-            o = philox4x32_10(Word4{(uint32_t)q >> 1, g, (uint32_t)d, 1u}, key0, key1);
-            bits = ((uint64_t)o.b << 32) | o.a;
-        } else {
-            bits = ((uint64_t)o.d << 32) | o.c;
-        }
-        const uint64_t pick = __umul64hi(bits, (uint64_t)tot);  // uniform on [0, tot)
-        // the compartment holding individual `pick` in ascending order is the
-        // number of running sums at or below it (a compartment outside the
-        // mask, or empty, repeats the sum before it and is passed over)
-        int chosen = 0;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) chosen += (uint64_t)cum[c] <= pick ? 1 : 0;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const int hit = c == chosen ? 1 : 0;
-            x[c] -= hit;
-            take[c] += hit;
-            cum[c] -= c >= chosen ? 1 : 0;
-        }
-        tot -= 1;
-    }
-}
-
 // What one event needs besides the state: its packed kind / mask / shift,
 // node, destination, count, Philox counter word g, merged index gm (error
 // report) and the instance of its node.
@@ -1008,10 +1167,6 @@ struct EvDesc {
     uint32_t meta, smap;
     int32_t node, dest, n, g, gm, inst;
 };
-
-// Compartment that an individual drawn from compartment c lands in (internal
-// and external transfers): 4 bits per source compartment of the event's map.
-__device__ __forceinline__ int shifted(uint32_t smap, int c) { return (int)((smap >> (4 * c)) & 0xFu); }
 
 __device__ __forceinline__ EvDesc load_desc(const DevState &s, const DevEvents &ev, int64_t e) {
     EvDesc q;

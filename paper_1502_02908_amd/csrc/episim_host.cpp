@@ -355,7 +355,7 @@ int64_t order_nodes(const sim_problem *p, int layout, int64_t heavy, std::vector
 // Device buffer layout of one handle.
 struct Layout {
     size_t u, phi, node_id, inst, inst_off, seed, coef, alpha, beta, repid, status, ev_g, ev_gm, ev_node,
-        ev_dest, ev_n, ev_meta, ev_smap, task_off, priv_off, day_slot_off, slot_pos, slot_key, lvl_ev_off, ev_slot_src, ev_slot_dst, lvl_off, lvl_ptr, prevalence, transitions, totals, snap_u, snap_v, rec_slot, slots,
+        ev_dest, ev_n, ev_meta, ev_smap, task_off, priv_off, priv_ev_off, day_slot_off, slot_pos, slot_key, lvl_ev_off, ev_slot_src, ev_slot_dst, lvl_off, lvl_ptr, prevalence, transitions, totals, snap_u, snap_v, rec_slot, slots,
         u0, v0, heavy_pos, unit_heavy, pos_region, regional, goal_ref, goal_part, total;
 };
 
@@ -393,6 +393,7 @@ Layout layout_for(int64_t Np, int64_t n_nodes, int64_t n_inst, int64_t Nc, int64
     l.ev_smap = take(sizeof(uint32_t) * n_events);
     l.task_off = take(sizeof(int32_t) * (n_tasks + 1));
     l.priv_off = take(sizeof(int32_t) * (D * n_units + 1));
+    l.priv_ev_off = take(sizeof(int32_t) * (D * n_units + 1));
     l.day_slot_off = take(sizeof(int32_t) * (D + 1));
     l.slot_pos = take(sizeof(int32_t) * n_day_slots);
     l.slot_key = take(sizeof(uint32_t) * 3 * n_day_slots);
@@ -436,6 +437,7 @@ struct Packed {
     std::vector<int64_t> lvl_off;   // task offsets of each level
     std::vector<int32_t> task_off;  // event offsets of each task
     std::vector<int32_t> priv_off;  // private tasks of (day, unit)
+    std::vector<int32_t> priv_ev_off;  // and their events
     std::vector<int32_t> pos_region; // region of each position (-1 outside regions)
     std::vector<int32_t> heavy_pos; // positions of the herds whose chains get a wavefront each
     std::vector<uint8_t> unit_heavy;
@@ -612,6 +614,8 @@ int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, P
     pk->task_off.assign(n_tasks + 1, 0);
     for (int64_t t = 0; t < n_tasks; ++t) pk->task_off[tslot[t] + 1] = (int32_t)task_n[t];
     for (int64_t i = 0; i < n_tasks; ++i) pk->task_off[i + 1] += pk->task_off[i];
+    pk->priv_ev_off.resize(pk->priv_off.size());
+    for (size_t i = 0; i < pk->priv_off.size(); ++i) pk->priv_ev_off[i] = pk->task_off[pk->priv_off[i]];
     std::vector<int64_t> fill(n_tasks);
     for (int64_t t = 0; t < n_tasks; ++t) fill[t] = pk->task_off[tslot[t]];
     pk->eg.resize(E);
@@ -978,6 +982,7 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
     ev.smap = at<uint32_t>(h->ws, l.ev_smap);
     ev.task_off = at<int32_t>(h->ws, l.task_off);
     ev.priv_off = at<int32_t>(h->ws, l.priv_off);
+    ev.priv_ev_off = at<int32_t>(h->ws, l.priv_ev_off);
     ev.day_slot_off = at<int32_t>(h->ws, l.day_slot_off);
     ev.slot_pos = at<int32_t>(h->ws, l.slot_pos);
     ev.slot_key = at<uint32_t>(h->ws, l.slot_key);
@@ -1013,6 +1018,7 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
         {(void *)ev.smap, pk.esmap.data(), sizeof(uint32_t) * E},
         {(void *)ev.task_off, pk.task_off.data(), sizeof(int32_t) * (pk.n_tasks + 1)},
         {(void *)ev.priv_off, pk.priv_off.data(), sizeof(int32_t) * pk.priv_off.size()},
+        {(void *)ev.priv_ev_off, pk.priv_ev_off.data(), sizeof(int32_t) * pk.priv_ev_off.size()},
         {(void *)ev.day_slot_off, pk.day_slot_off.data(), sizeof(int32_t) * pk.day_slot_off.size()},
         {(void *)ev.slot_pos, pk.slot_pos.data(), sizeof(int32_t) * pk.slot_pos.size()},
         {(void *)ev.slot_key, pk.slot_key.data(), sizeof(uint32_t) * pk.slot_key.size()},

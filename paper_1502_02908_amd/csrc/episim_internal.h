@@ -106,6 +106,7 @@ struct DevEvents {
     const int64_t *lvl_off;     // level boundaries into the tasks
     const int32_t *priv_off;    // [D * n_units + 1]: private tasks of unit u on day d are
                                 // priv_off[d * n_units + u] .. priv_off[d * n_units + u + 1] - 1
+    const int32_t *priv_ev_off; // [D * n_units + 1]: their events, contiguous, in the same numbering
     // days run in LDS (one lane per node): the positions their level tasks touch
     // are slot_pos[day_slot_off[d]] ..; slot_src / slot_dst give each event's
     // slot of its node / destination on such a day, -1 otherwise
