@@ -322,14 +322,14 @@ __device__ __forceinline__ double wave_prefix_sum(double v) {
 // clock stays in one binade [2^e, 2^(e+1)) every partial sum is an integer
 // multiple of its spacing h = 2^(e-52), and adding a waiting time rounds to
 // the nearest multiple: s + tau -> (s/h + rn(tau/h)) h. Those integers add
-// exactly (each partial sum that matters stays below 2^53), so one prefix
-// sum over the lanes gives every partial sum of the round bit for bit. A sum
-// that reaches 2^(e+1) leaves the binade: for e = -1 that is the window end
-// (the attempt does not fire, whatever the rounding above 1); otherwise the
-// round has to be summed attempt by attempt, and so has a round in which a
-// waiting time lies exactly half-way between two multiples (ties round to
-// even, which depends on the partial sum) or whose clock is 0. Returns the
-// number of attempts that fire (-1: sum attempt by attempt) and their clock.
+// exactly (each partial sum that matters stays below 2^53), so one prefix sum
+// over the lanes gives every partial sum of the round bit for bit. A sum that
+// reaches 2^(e+1) leaves the binade: for e = -1 that is the window end (the
+// attempt does not fire, whatever the rounding above 1); otherwise the round
+// has to be summed attempt by attempt, and so has a round in which a waiting
+// time lies exactly half-way between two multiples (ties round to even, which
+// depends on the partial sum) or whose clock is 0. Returns the number of
+// attempts that fire (-1: sum attempt by attempt) and their clock.
 __device__ __forceinline__ int clock_by_scan(double clock, double tau, double *clock_out) {
     const long long cb = __double_as_longlong(clock);
     const int e = (int)((cb >> 52) & 0x7ff) - 1023;
@@ -341,14 +341,93 @@ __device__ __forceinline__ int clock_by_scan(double clock, double tau, double *c
     const double v = tau * up;
     const double fl = floor(v);
     const double fr = v - fl;
-    const double mk = fr > 0.5 ? fl + 1.0 : fl;
-    const double P = wave_prefix_sum(mk);
-    const int A = __popcll(__ballot(P < T));
+    const double P = wave_prefix_sum(fr > 0.5 ? fl + 1.0 : fl);
+    const int A = (int)__popcll(__ballot(P < T));
     const unsigned long long upto = A >= 63 ? ~0ull : ((2ull << A) - 1ull);
     if ((__ballot(fr == 0.5) & upto) != 0ull) return -1;
     if (A < 64 && e != -1) return -1;
     *clock_out = A > 0 ? (S0 + lane_f64(P, A - 1)) * down : clock;
     return A;
+}
+
+// Value v[idx / 64] of lane idx % 64 (idx uniform over the wavefront).
+template <int W>
+__device__ __forceinline__ double part_at(const double (&v)[W], int idx) {
+    double out = 0.0;
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+        if (idx / 64 == w) out = lane_f64(v[w], idx % 64);
+    return out;
+}
+
+// The clock of a round of the workgroup walk without the attempt-by-attempt
+// sum (the rule of clock_by_scan, carried past ties and binade ends). While the running
+// clock s stays in one binade [2^e, 2^(e+1)) every partial sum is an integer
+// multiple of its spacing h = 2^(e-52), and adding a waiting time rounds to
+// the nearest multiple: s + tau -> (s/h + rn(tau/h)) h. Those integers add
+// exactly (each partial sum that matters stays below 2^53), so prefix sums
+// over the round's attempts (attempt w * 64 + lane in tau[w]) give the
+// partial sums bit for bit up to the first attempt that either reaches
+// 2^(e+1) or lies exactly half-way between two multiples (ties round to even,
+// which depends on the partial sum). That attempt is added as the
+// attempt-by-attempt walk adds it, and the scan goes on from the next one in
+// the binade of the new sum; so does an attempt added to a clock of 0. The
+// first attempt whose sum is not below 1 ends the round. Returns the number of
+// attempts that fire and their clock, or -1 for a clock too small to scale
+// (the caller sums attempt by attempt). Every lane of the wavefront calls it.
+template <int W>
+__device__ __forceinline__ int clock_exact_scan(double clock, const double (&tau)[W], double *clock_out) {
+    const int lane = threadIdx.x & 63;
+    constexpr int N = 64 * W;
+    int done = 0;  // attempts before done fire; s is the clock after them
+    double s = clock;
+    for (int iter = 0; iter <= N; ++iter) {
+        if (done == N) break;
+        if (!(s > 0.0)) {
+            const double t0 = part_at<W>(tau, done);  // 0 + tau is tau
+            if (!(t0 < 1.0)) break;
+            s = t0;
+            ++done;
+            continue;
+        }
+        const long long cb = __double_as_longlong(s);
+        const int e = (int)((cb >> 52) & 0x7ff) - 1023;
+        if (e < -960) return -1;
+        const double up = __longlong_as_double((long long)(1023 + 52 - e) << 52);    // 2^(52-e)
+        const double down = __longlong_as_double((long long)(1023 - 52 + e) << 52);  // 2^(e-52)
+        const double S0 = s * up;                                                    // in [2^52, 2^53)
+        const double T = 0x1p53 - S0;
+        double P[W];
+        int special = N;  // first attempt past the binade or on a tie
+        double carry = 0.0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const bool live = 64 * w + lane >= done;
+            const double v = tau[w] * up;
+            const double fl = floor(v);
+            const double fr = v - fl;
+            P[w] = wave_prefix_sum(live ? (fr > 0.5 ? fl + 1.0 : fl) : 0.0) + carry;
+            carry = lane_f64(P[w], 63);
+            const unsigned long long odd = __ballot(live && (fr == 0.5 || !(P[w] < T)));
+            if (special == N && odd != 0ull) special = 64 * w + __ffsll((long long)odd) - 1;
+        }
+        const double before = special > done ? (S0 + part_at<W>(P, special - 1)) * down : s;
+        if (special == N) {
+            s = before;
+            done = N;
+            break;
+        }
+        const double s2 = before + part_at<W>(tau, special);
+        if (!(s2 < 1.0)) {
+            s = before;
+            done = special;
+            break;
+        }
+        s = s2;
+        done = special + 1;
+    }
+    *clock_out = s;
+    return done;
 }
 
 // One chain walked by the whole wavefront, 64 attempts per round, for paired
@@ -491,6 +570,157 @@ __device__ __forceinline__ void pairs_walk_block(const Model &m, Chain<2 * NP, 2
     }
 }
 
+// One chain walked by the four wavefronts of a workgroup, 256 attempts per
+// round (attempt kbase + t for thread t), for paired classes: the scheme of
+// pairs_walk_block, with the picks of each wavefront (one ballot per
+// transition) shared in LDS so that an attempt counts the picks of every
+// attempt below it, and the clock of the 256 waiting times decided by
+// wavefront 0. Every thread of the workgroup calls it with the same state and
+// ends with the same state. It pays off for long chains only: a round starts
+// only while the window still expects kGroupMinAttempts attempts
+// (lambda (1 - clock)), and a round whose picks do not settle within
+// kGroupPasses passes is dropped. Returns whether the chain is done; if not,
+// the caller continues with the single-wavefront walk from attempt kbase and
+// state c, which are those at the start of a round.
+constexpr double kGroupMinAttempts = 4096.0;
+constexpr int kGroupPasses = 8;
+
+template <int NP>
+__device__ bool pairs_walk_group(Chain<2 * NP, 2 * NP> &c, uint32_t &kbase, uint32_t node, uint32_t day,
+                                 uint32_t key0, uint32_t key1, unsigned long long *status, int32_t r) {
+    constexpr int NT = 2 * NP;
+    constexpr int kRound = kBlock;
+    __shared__ unsigned long long sh_b[2][kWaves][NT];  // picks of each wavefront and pass, per transition
+    __shared__ int sh_moved[2][kWaves];
+    __shared__ double sh_tau[kRound];
+    __shared__ double sh_clock;
+    __shared__ int sh_fired;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    int buf = 0;
+    for (;;) {
+        if (c.lam * (1.0 - c.clock) < kGroupMinAttempts) return false;  // the same in every thread
+        const Word4 o = philox4x32_10(Word4{kbase + (uint32_t)t, node, day, 0u}, key0, key1);
+        const double E = minus_log(unit_open(o.a, o.b));
+        const double U = unit_open(o.c, o.d);
+        int j = 0;
+        {
+            const double target = U * c.lam;
+#pragma unroll
+            for (int k = 0; k < NT; ++k) j += c.cum[k] < target ? 1 : 0;
+        }
+        double lam = c.lam;
+        bool settled = false;
+        for (int pass = 0; pass < kGroupPasses; ++pass) {
+            unsigned long long bk[NT];
+#pragma unroll
+            for (int k = 0; k < NT; ++k) bk[k] = __ballot(j == k);
+            if (lane == 0) {
+#pragma unroll
+                for (int k = 0; k < NT; ++k) sh_b[buf][wave][k] = bk[k];
+            }
+            __syncthreads();
+            double l = 0.0, cum[NT];
+#pragma unroll
+            for (int q = 0; q < NP; ++q) {
+                int inf = (int)__popcll(bk[2 * q] & below), rec = (int)__popcll(bk[2 * q + 1] & below);
+                for (int w = 0; w < wave; ++w) {
+                    inf += (int)__popcll(sh_b[buf][w][2 * q]);
+                    rec += (int)__popcll(sh_b[buf][w][2 * q + 1]);
+                }
+                const double dS = (double)(rec - inf);
+                l = l + c.cphi[2 * q] * (c.xd[2 * q] + dS);
+                cum[2 * q] = l;
+                l = l + c.cphi[2 * q + 1] * (c.xd[2 * q + 1] - dS);
+                cum[2 * q + 1] = l;
+            }
+            const double target = U * l;
+            int jn = 0;
+#pragma unroll
+            for (int k = 0; k < NT; ++k) jn += cum[k] < target ? 1 : 0;
+            const bool moved = __ballot(jn != j) != 0ull;
+            j = jn;
+            lam = l;
+            if (lane == 0) sh_moved[buf][wave] = moved ? 1 : 0;
+            __syncthreads();
+            bool any = false;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) any = any || sh_moved[buf][w] != 0;
+            buf ^= 1;
+            if (!any) {
+                settled = true;
+                break;
+            }
+        }
+        if (!settled) return false;  // the same in every thread; nothing of this round applied
+        const int last = buf ^ 1;  // the final picks' ballots
+        sh_tau[t] = E / lam;       // lambda = 0: tau = inf, never fires
+        __syncthreads();
+        if (wave == 0) {
+            double tw[kWaves];
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) tw[w] = sh_tau[64 * w + lane];
+            double clock;
+            int A = clock_exact_scan<kWaves>(c.clock, tw, &clock);
+            if (A < 0) {
+                // attempt by attempt, in order
+                double s = c.clock, mine[kWaves];
+#pragma unroll
+                for (int w = 0; w < kWaves; ++w) {
+                    mine[w] = 0.0;
+#pragma unroll 16
+                    for (int i = 0; i < 64; ++i) {
+                        s = s + sh_tau[64 * w + i];
+                        if (lane == i) mine[w] = s;
+                    }
+                }
+                A = 0;
+#pragma unroll
+                for (int w = 0; w < kWaves; ++w) A += (int)__popcll(__ballot(mine[w] < 1.0));
+                clock = c.clock;
+#pragma unroll
+                for (int w = 0; w < kWaves; ++w)
+                    if (A > 0 && (A - 1) / 64 == w) clock = lane_f64(mine[w], (A - 1) % 64);
+            }
+            if (lane == 0) {
+                sh_clock = clock;
+                sh_fired = A;
+            }
+        }
+        __syncthreads();
+        int A = sh_fired;
+        const double clock = sh_clock;
+        bool limit = false;
+        if (c.fired + A >= SIM_MAX_FIRED) {
+            A = SIM_MAX_FIRED - c.fired;
+            limit = true;
+        }
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            int inf = 0, rec = 0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) {
+                const int nw = A - 64 * w;
+                const unsigned long long fired = nw >= 64 ? ~0ull : (nw > 0 ? ((1ull << nw) - 1ull) : 0ull);
+                inf += (int)__popcll(sh_b[last][w][2 * q] & fired);
+                rec += (int)__popcll(sh_b[last][w][2 * q + 1] & fired);
+            }
+            const double d = (double)(rec - inf);
+            c.xd[2 * q] = c.xd[2 * q] + d;
+            c.xd[2 * q + 1] = c.xd[2 * q + 1] - d;
+        }
+        if (A > 0 && !limit) c.clock = clock;
+        c.fired = c.fired + A;
+        pairs_rates_full<NP>(c);
+        if (limit) {
+            if (t == 0) atomicMin(status, (STATUS_LIMIT_TAG << 32) | (unsigned long long)(uint32_t)r);
+            return true;
+        }
+        if (A < kRound || !(c.lam > 0.0)) return true;
+        kbase = kbase + kRound;
+    }
+}
+
 // A single live chain, run by the whole wavefront with every lane holding
 // the same state: lane i computes attempt kbase + i, and the attempts are
 // walked in order with the chosen transition held in a scalar register.
@@ -527,6 +757,8 @@ __device__ __forceinline__ void chain_uniform(const Model &m, typename Rules::St
 // chain in parallel (their -log rand and rand), parks them in LDS, and each
 // live lane then walks its own in order. With all 64 lanes live each lane
 // draws its own block. Every lane of the wavefront must call this.
+constexpr uint32_t kFewChains = 4;
+
 template <class Rules>
 __device__ __forceinline__ void run_chains(const Model &m, typename Rules::State &c, bool live, uint32_t node,
                                            uint32_t day, uint32_t key0, uint32_t key1,
@@ -547,8 +779,13 @@ __device__ __forceinline__ void run_chains(const Model &m, typename Rules::State
             continue;
         }
         const uint32_t nlive = (uint32_t)__popcll(mask);
-        if (nlive == 1) {  // one chain left: the whole wavefront walks it
-            const int h = __ffsll((long long)mask) - 1;
+        // One chain left, or a few of which one still expects many attempts in
+        // the window (lambda (1 - clock)): the whole wavefront walks them one
+        // after another, 64 attempts at a time, instead of a lane each.
+        const bool few = nlive <= kFewChains &&
+                         (nlive == 1 || __ballot(live && c.lam * (1.0 - c.clock) > 10.0 * (double)nlive) != 0ull);
+        for (unsigned long long left = few ? mask : 0ull; left != 0ull; left &= left - 1ull) {
+            const int h = __ffsll((long long)left) - 1;
             typename Rules::State u;
 #pragma unroll
             for (int k = 0; k < Rules::NC; ++k) u.xd[k] = lane_f64(c.xd[k], h);
@@ -571,8 +808,8 @@ __device__ __forceinline__ void run_chains(const Model &m, typename Rules::State
                 chain_uniform<Rules>(m, u, kb, nh, day, k0, k1, status, rh);
             }
             if ((int)lane == h) c = u;
-            break;
         }
+        if (few) break;
         const uint32_t per = 64u / nlive;
         const uint32_t rank = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
         if (live) {
@@ -706,6 +943,55 @@ __device__ void flush_tile(const Model &m, const DevState &s, const Tally<NC> &t
     __syncthreads();
 }
 
+// The SSA of a workgroup whose only herd sits in thread 0 (one lane per node):
+// with paired classes its chain is walked by all four wavefronts, otherwise
+// as anywhere else. Every thread of the workgroup calls it.
+template <class Rules>
+__device__ void group_chain(const Model &m, typename Rules::State &c, bool live, uint32_t node, uint32_t day,
+                            uint32_t key0, uint32_t key1, unsigned long long *status, int32_t r) {
+    if constexpr (Rules::kPairs == 0) {
+        run_chains<Rules>(m, c, live, node, day, key0, key1, status, r);
+    } else {
+        constexpr int NT = Rules::NT;
+        __shared__ double sh_x[NT], sh_cphi[NT], sh_cum[NT], sh_lam;
+        __shared__ uint32_t sh_key[4];
+        __shared__ int sh_go;
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int k = 0; k < NT; ++k) {
+                sh_x[k] = c.xd[k];
+                sh_cphi[k] = c.cphi[k];
+                sh_cum[k] = c.cum[k];
+            }
+            sh_lam = c.lam;
+            sh_key[0] = node;
+            sh_key[1] = key0;
+            sh_key[2] = key1;
+            sh_key[3] = (uint32_t)r;
+            sh_go = live && c.lam > 0.0 ? 1 : 0;
+        }
+        __syncthreads();
+        if (!sh_go) return;  // the same in every thread
+        typename Rules::State u;
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            u.xd[k] = sh_x[k];
+            u.cphi[k] = sh_cphi[k];
+            u.cum[k] = sh_cum[k];
+        }
+        u.lam = sh_lam;
+        u.clock = 0.0;
+        u.fired = 0;
+        uint32_t kb = 0;
+        // a short chain, or the end of a long one, is walked by wavefront 0
+        // alone (thread 0 is in it)
+        if (!pairs_walk_group<Rules::kPairs>(u, kb, sh_key[0], day, sh_key[1], sh_key[2], status, (int32_t)sh_key[3]) &&
+            threadIdx.x < 64)
+            pairs_walk_block<Rules::kPairs>(m, u, kb, sh_key[0], day, sh_key[1], sh_key[2], status, (int32_t)sh_key[3]);
+        if (threadIdx.x == 0) c = u;
+    }
+}
+
 // Per-lane parameters of a replicate tile, staged in LDS once per tile (every
 // position of a tile belongs to one instance, so lane r has the same set):
 // rate constants, shedding and decay rates and the Philox key.
@@ -781,30 +1067,43 @@ struct NoHooks {
 // must call it; lanes with l >= L or replicate lane r >= r_end take part in
 // the wavefront-level steps only): close day d-1 (phi update + record) if
 // prologue, then run the SSA of day d if ssa. Adds the lane's counts to t.
+// uniform_set >= 0 is the set of every lane (a workgroup of one instance and
+// one replicate), so that its parameters are read without waiting for the
+// lane's instance. Every load that does not depend on another is issued
+// first (padding positions hold zeros).
 template <class Rules, class Hooks = NoHooks>
 __device__ __forceinline__ void day_wave(const Model &m, const DevState &s, int64_t l, int32_t d,
                                          bool prologue, bool ssa, Tally<Rules::NC> &t, int32_t r_end,
                                          unsigned long long *status, const TileParams *tp = nullptr,
-                                         const Hooks &hooks = Hooks{}) {
+                                         const Hooks &hooks = Hooks{}, int32_t uniform_set = -1,
+                                         bool group_walk = false) {
     constexpr int NC = Rules::NC, NT = Rules::NT;
     const int32_t R = s.R, RL = s.RL;
     const bool in_range = l < s.L;
     const int32_t r = !in_range || RL == 1 ? 0 : (int32_t)(l % RL);
     const int32_t pos = !in_range ? 0 : (RL == 1 ? (int32_t)l : (int32_t)(l / RL));
-    const int32_t nid = in_range && r < r_end ? s.node_id[pos] : -1;
-    const bool active = nid >= 0;  // padding positions and idle lanes take part in the wavefront steps only
-    const int32_t inst = active ? s.inst[pos] : 0;
-    const int32_t set = inst * R + r;
+    const int32_t rec = prologue ? s.rec_slot[d - 1] : -1;
     int32_t x[NC];
     double phi = 0.0;
-    const uint32_t node = active ? (uint32_t)nid : 0u;
+    int32_t nid = -1, inst = 0;
 #pragma unroll
     for (int c = 0; c < NC; ++c) x[c] = 0;
-    if (active) {
+    if (in_range) {
+        nid = s.node_id[pos];
+        inst = s.inst[pos];
 #pragma unroll
         for (int c = 0; c < NC; ++c) x[c] = comp_on<NC>(m, c) ? s.u[(int64_t)c * s.L + l] : 0;
         phi = s.phi[l];
     }
+    const bool active = r < r_end && nid >= 0;  // padding positions and idle lanes take part in the wavefront steps only
+    if (!active) {
+        inst = 0;
+        phi = 0.0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) x[c] = 0;
+    }
+    const int32_t set = uniform_set >= 0 ? uniform_set : inst * R + r;
+    const uint32_t node = active ? (uint32_t)nid : 0u;
     // phi_{d+1} = (1 - beta(day0 + d)) phi_d + alpha I/N (eq:siminfpressure, Euler step)
     auto phi_next = [&](const int32_t *y, int32_t dd, double ph, long long *Iout) {
         long long I = 0, N = 0;
@@ -836,7 +1135,7 @@ __device__ __forceinline__ void day_wave(const Model &m, const DevState &s, int6
         t.prev += I > 0 ? 1 : 0;
 #pragma unroll
         for (int c = 0; c < NC; ++c) t.tot[c] += x[c];
-        const int32_t slot = s.rec_slot[dp];
+        const int32_t slot = rec;
         if (slot >= 0) {
             const int64_t base = (((int64_t)slot * R + r) * s.n_nodes + s.inst_off[inst] + node);
 #pragma unroll
@@ -863,7 +1162,10 @@ __device__ __forceinline__ void day_wave(const Model &m, const DevState &s, int6
     ch.clock = 0.0;
     ch.fired = 0;
     Rules::rates(m, ch);
-    run_chains<Rules>(m, ch, active, node, (uint32_t)d, key0, key1, status, set);
+    if (group_walk)
+        group_chain<Rules>(m, ch, active, node, (uint32_t)d, key0, key1, status, set);
+    else
+        run_chains<Rules>(m, ch, active, node, (uint32_t)d, key0, key1, status, set);
     t.trans += ch.fired;
     if (hooks.after_ssa(ch, active) && active && ch.fired) {
 #pragma unroll
@@ -1003,15 +1305,20 @@ __global__ __launch_bounds__(kBlock) void k_day(Model m, DevState s, DevEvents e
     __shared__ PrivEv sh_pe[kBlock];
     __shared__ int32_t sh_x[NC][kBlock];
     __shared__ int32_t sh_touch[kBlock];
-    if (!block_ok(s.status)) return;
     const int64_t l = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     // The unit's private events of the day. With at most one per thread they
     // are fetched now, alongside the state, and applied to the counts in LDS
     // right after the SSA; each node is then stored once. Otherwise the SSA
-    // stores its counts and the tasks run on global memory.
+    // stores its counts and the tasks run on global memory. Their bounds and
+    // the workgroup's set (one lane per node; instances are padded to whole
+    // workgroups) are read before the status check, which waits for them.
     const int64_t k = (int64_t)d * (s.Np / kLaneUnit) + blockIdx.x;
     const int32_t pe0 = ssa ? ev.priv_ev_off[k] : 0;
     const int32_t npe = ssa ? ev.priv_ev_off[k + 1] - pe0 : 0;
+    const int32_t set = s.inst[(int64_t)blockIdx.x * kBlock];
+    const bool group = s.unit_group[blockIdx.x] != 0;
+    if (!block_ok(s.status)) return;
+    const uint32_t key0 = s.seed[set], key1 = s.repid[set];
     const bool lds = npe <= kBlock;
     const bool has = lds && (int)threadIdx.x < npe;
     PrivEv mine{0u, 0u, 0, 0, 0, 0};
@@ -1021,11 +1328,9 @@ __global__ __launch_bounds__(kBlock) void k_day(Model m, DevState s, DevEvents e
     }
     const LdsPrivHooks<NC> hooks{sh_pe, sh_x, sh_touch, &mine, has, lds && ssa};
     Tally<NC> t{};
-    day_wave<Rules>(m, s, l, d, prologue != 0, ssa != 0, t, s.R, s.status, nullptr, hooks);
+    day_wave<Rules>(m, s, l, d, prologue != 0, ssa != 0, t, s.R, s.status, nullptr, hooks, set, group);
     const int32_t d_rec = prologue ? d - 1 : -1;
     const int32_t d_ssa = ssa ? d : -1;
-    // one lane per node; instances are padded to whole workgroups: one set per workgroup
-    const int32_t set = s.inst[(int64_t)blockIdx.x * kBlock];
     flush_block<NC>(m, s, t, set, d_rec, d_ssa, s.n_regions ? s.pos_region[(int64_t)blockIdx.x * kBlock] : -1);
     if (!ssa) return;
     if (!lds) {
@@ -1034,8 +1339,8 @@ __global__ __launch_bounds__(kBlock) void k_day(Model m, DevState s, DevEvents e
     }
     // flush_block's barriers make the parked events and counts visible
     if (has && !(sh_pe[threadIdx.x].meta & kMetaCont))
-        private_task_lds<NC>(sh_pe, threadIdx.x, npe, sh_x, sh_touch, (int32_t)(blockIdx.x * kBlock), d,
-                             s.seed[set], s.repid[set], set, s.status);
+        private_task_lds<NC>(sh_pe, threadIdx.x, npe, sh_x, sh_touch, (int32_t)(blockIdx.x * kBlock), d, key0, key1,
+                             set, s.status);
     __syncthreads();
     if (sh_touch[threadIdx.x]) {
 #pragma unroll

@@ -276,6 +276,10 @@ constexpr int64_t kSoloHerds = 128;
 // (herd, replicate) chain is walked by a wavefront of its own; they are placed
 // first, the remaining positions of their units stay empty.
 constexpr int64_t kHeavyHerds = 32;
+// With one lane per node and per-day launches, the kGroupHerds largest herds
+// of a large instance get a workgroup each: the herd sits at the unit's first
+// position and its chain is walked by all four wavefronts of the workgroup.
+constexpr int64_t kGroupHerds = 4;
 
 // One group of herds, ranked largest first, placed from position base: solo
 // wavefronts first (one lane per node, large groups only), then dealt over the
@@ -304,7 +308,7 @@ int64_t place_group(const std::vector<int32_t> &ranked, int layout, int64_t base
 // work holds herds of one region only, so the per-unit sums of the records
 // are also regional sums; the heavy herds' own units may mix regions (their
 // chains record on their own).
-int64_t order_nodes(const sim_problem *p, int layout, int64_t heavy, std::vector<int32_t> *pos_node,
+int64_t order_nodes(const sim_problem *p, int layout, int64_t heavy, int64_t group, std::vector<int32_t> *pos_node,
                     std::vector<int32_t> *pos_region) {
     const int64_t Nn = p->n_nodes, Nc = p->n_comp;
     // a herd's size is its largest population over the horizon: the SSA only
@@ -332,18 +336,26 @@ int64_t order_nodes(const sim_problem *p, int layout, int64_t heavy, std::vector
     const int64_t G = unit_nodes(layout);
     const int64_t hv = layout == LAYOUT_TILE ? std::min(heavy, Nn) : 0;
     const int64_t hv_span = ((hv + G - 1) / G) * G;
+    const int64_t gr = layout == LAYOUT_LANES ? std::min(group, Nn) : 0;
+    const int64_t lead = hv_span + gr * pad_nodes(layout);
     const int32_t J = p->n_regions > 0 ? p->n_regions : 0;
     auto region_of = [&](int32_t i) { return J > 0 ? p->region[i] : -1; };
-    pos_node->assign(hv_span, -1);
-    pos_region->assign(hv_span, -1);
+    pos_node->assign(lead, -1);
+    pos_region->assign(lead, -1);
     for (int64_t q = 0; q < hv; ++q) {
         (*pos_node)[q] = rank[q];
         (*pos_region)[q] = region_of(rank[q]);
     }
+    // a workgroup per group herd: the herd first, the rest padding of its region
+    for (int64_t q = 0; q < gr; ++q) {
+        const int64_t b = hv_span + q * pad_nodes(layout);
+        (*pos_node)[b] = rank[hv + q];
+        for (int64_t i = 0; i < pad_nodes(layout); ++i) (*pos_region)[b + i] = region_of(rank[hv + q]);
+    }
     // groups: the herds outside regions, then region by region (one group without regions)
     std::vector<std::vector<int32_t>> groups(J + 1);
-    for (int64_t q = hv; q < Nn; ++q) groups[region_of(rank[q]) + 1].push_back(rank[q]);
-    int64_t base = hv_span;
+    for (int64_t q = hv + gr; q < Nn; ++q) groups[region_of(rank[q]) + 1].push_back(rank[q]);
+    int64_t base = lead;
     for (int32_t j = -1; j < J; ++j) {
         const int64_t span = place_group(groups[j + 1], layout, base, pos_node);
         pos_region->resize(base + span, j);
@@ -356,7 +368,7 @@ int64_t order_nodes(const sim_problem *p, int layout, int64_t heavy, std::vector
 struct Layout {
     size_t u, phi, node_id, inst, inst_off, seed, coef, alpha, beta, repid, status, ev_g, ev_gm, ev_node,
         ev_dest, ev_n, ev_meta, ev_smap, task_off, priv_off, priv_ev_off, day_slot_off, slot_pos, slot_key, lvl_ev_off, ev_slot_src, ev_slot_dst, lvl_off, lvl_ptr, prevalence, transitions, totals, snap_u, snap_v, rec_slot, slots,
-        u0, v0, heavy_pos, unit_heavy, pos_region, regional, goal_ref, goal_part, total;
+        u0, v0, heavy_pos, unit_heavy, unit_group, pos_region, regional, goal_ref, goal_part, total;
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -416,6 +428,7 @@ Layout layout_for(int64_t Np, int64_t n_nodes, int64_t n_inst, int64_t Nc, int64
     l.goal_ref = take(sizeof(int64_t) * D * n_regions * Nc);
     l.goal_part = take(n_regions ? sizeof(double) * 2 * D : 0);
     l.unit_heavy = take(n_units);
+    l.unit_group = take(n_units);
     l.u0 = take(n_slots ? sizeof(int32_t) * Nc * Np : 0);
     l.v0 = take(n_slots ? sizeof(double) * Np : 0);
     l.total = off;
@@ -441,6 +454,7 @@ struct Packed {
     std::vector<int32_t> pos_region; // region of each position (-1 outside regions)
     std::vector<int32_t> heavy_pos; // positions of the herds whose chains get a wavefront each
     std::vector<uint8_t> unit_heavy;
+    std::vector<uint8_t> unit_group;  // units whose first herd is walked by the whole workgroup
     std::vector<int32_t> day_slot_off, slot_pos, ev_slot_src, ev_slot_dst;  // days run in LDS
     std::vector<uint32_t> slot_key;     // per slot: Philox key (seed, replicate id) and set of its node
     std::vector<int64_t> lvl_ev_off;    // event offsets of each level
@@ -482,15 +496,19 @@ int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, P
     std::vector<std::vector<int32_t>> pos_node(n);
     pk->inst_off.assign(n, 0);
     pk->inst_pos0.assign(n, 0);
+    std::vector<int64_t> group_units;
     for (int32_t k = 0; k < n; ++k) {
         pk->inst_off[k] = (int32_t)pk->n_nodes;
         pk->inst_pos0[k] = (int32_t)pk->Np;
         const int64_t heavy = (pk->layout == LAYOUT_TILE && launch == SIM_LAUNCH_KERNELS)
                                   ? std::min<int64_t>(kHeavyHerds, ps[k]->n_nodes / 64) : 0;
+        const int64_t group = (pk->layout == LAYOUT_LANES && launch == SIM_LAUNCH_KERNELS &&
+                               ps[k]->n_nodes >= 64 * kSoloHerds) ? kGroupHerds : 0;
         std::vector<int32_t> preg;
-        const int64_t np_k = order_nodes(ps[k], pk->layout, heavy, &pos_node[k], &preg);
+        const int64_t np_k = order_nodes(ps[k], pk->layout, heavy, group, &pos_node[k], &preg);
         pk->pos_region.insert(pk->pos_region.end(), preg.begin(), preg.end());
         for (int64_t j = 0; j < heavy; ++j) pk->heavy_pos.push_back((int32_t)(pk->Np + j));
+        for (int64_t j = 0; j < group; ++j) group_units.push_back((pk->Np + j * pad_nodes(pk->layout)) / unit_positions(pk->layout));
         pk->Np += np_k;
         pk->n_nodes += ps[k]->n_nodes;
         pk->n_events += ps[k]->n_events;
@@ -499,6 +517,8 @@ int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, P
     if (pk->n_events > INT32_MAX) return *err = "too many events", SIM_EINVAL;
     pk->unit_heavy.assign(pk->Np / unit_positions(pk->layout), 0);
     for (int32_t hp : pk->heavy_pos) pk->unit_heavy[hp / unit_positions(pk->layout)] = 1;
+    pk->unit_group.assign(pk->Np / unit_positions(pk->layout), 0);
+    for (int64_t u : group_units) pk->unit_group[u] = 1;
     pk->node_id.assign(pk->Np, -1);
     pk->inst.assign(pk->Np, 0);
     pk->lane_of.assign(pk->n_nodes, 0);
@@ -969,6 +989,7 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
     s.n_heavy = (int32_t)pk.heavy_pos.size();
     s.heavy_pos = at<int32_t>(h->ws, l.heavy_pos);
     s.unit_heavy = s.n_heavy ? at<uint8_t>(h->ws, l.unit_heavy) : nullptr;
+    s.unit_group = at<uint8_t>(h->ws, l.unit_group);
     s.n_regions = p->n_regions;
     s.pos_region = at<int32_t>(h->ws, l.pos_region);
     s.regional = at<int64_t>(h->ws, l.regional);
@@ -1031,6 +1052,7 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
         {(void *)s.heavy_pos, pk.heavy_pos.data(), sizeof(int32_t) * pk.heavy_pos.size()},
         {(void *)s.pos_region, pk.pos_region.data(), s.n_regions ? sizeof(int32_t) * pk.pos_region.size() : 0},
         {(void *)s.unit_heavy, pk.unit_heavy.data(), s.n_heavy ? pk.unit_heavy.size() : 0},
+        {(void *)s.unit_group, pk.unit_group.data(), pk.unit_group.size()},
     };
     for (const Up &up : ups) {
         if (up.bytes == 0) continue;

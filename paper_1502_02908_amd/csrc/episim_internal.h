@@ -82,6 +82,7 @@ struct DevState {
     int32_t n_heavy;
     const int32_t *heavy_pos;   // [n_heavy]
     const uint8_t *unit_heavy;  // [n_units], null if n_heavy == 0
+    const uint8_t *unit_group;  // [n_units]: one lane per node, the unit's first herd is walked by the whole workgroup
     // daily records
     int32_t *prevalence;        // [D][sets]
     int64_t *transitions;       // [D][sets]

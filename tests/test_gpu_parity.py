@@ -263,3 +263,46 @@ def test_mass_action_sir(launch):
     g, o = both(p, launch=launch)
     assert_parity(g, o)
     assert o["transitions"].sum() > 5000
+
+
+@pytest.mark.parametrize("density", [1.0, 3.0])
+def test_private_tasks_around_lds_capacity(density):
+    # the day kernel applies a unit's private tasks in LDS when the unit-day
+    # has at most 256 private events and on global memory otherwise; 512 nodes
+    # (two units) at about one single-node event per node-day put unit-days on
+    # both sides of that bound, three per node-day puts all of them past it
+    p = synth.sise3_network(n_nodes=512, n_days=60, seed=31, age_days=(10, 30), e1_per_node_day=density)
+    p.record_days = np.array([0, 30, 59], np.int32)
+    g, o = both(p)
+    assert_parity(g, o)
+    assert o["transitions"].sum() > 0
+
+
+@pytest.mark.parametrize("launch", [P.LAUNCH_KERNELS, P.LAUNCH_PERSISTENT])
+def test_group_walk_of_very_long_chains(launch):
+    # the paper's synthetic model (Sec. 4.2) on 8200 nodes, four of them with
+    # 6k to 40k transitions expected per day: with per-day launches their
+    # chains are walked by all four wavefronts of a workgroup (256 attempts per
+    # round) while thousands of attempts remain, then by one wavefront
+    p = synth.flip_model(n_nodes=8200, S0=5, I0=5, n_days=4)
+    for node, half in ((7, 3000), (100, 6000), (5000, 10000), (8199, 20000)):
+        p.u0[node] = (half, half)
+    p.record_days = np.array([0, 3], np.int32)
+    g, o = both(p, launch=launch)
+    assert_parity(g, o)
+    assert o["transitions"].sum() > 4 * 78000
+
+
+def test_group_units_on_a_farm_network():
+    # from 8192 nodes up, the four largest herds get a workgroup each (the
+    # workgroup walk when their chains are long, one wavefront otherwise);
+    # regions check the records of those units
+    p = synth.sise3_network(n_nodes=9000, n_days=150, seed=32, u=10.0, age_days=(20, 60))
+    rng = np.random.default_rng(3)
+    p.n_regions = 21
+    p.region = rng.integers(-1, 21, p.n_nodes).astype(np.int32)
+    p.record_days = np.array([0, 75, 149], np.int32)
+    g, o = both(p)
+    assert_parity(g, o)
+    assert np.array_equal(g["regional"], o["regional"])
+    assert o["transitions"].sum() > 100000
