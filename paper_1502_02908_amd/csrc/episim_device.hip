@@ -1006,8 +1006,12 @@ struct TileParams {
 // replacement (Sec. 3.2): draw q picks the individual at a uniform position
 // in [0, remaining) of the selected compartments in ascending order, from the
 // Philox block (q / 2, g, d, 1). Removes them from x and counts them in take.
-// pre, when given, holds the first kPreDraws draws (computed ahead in parallel).
-constexpr int kPreDraws = 4;
+// pre, when given, holds the first kPreDraws draws (computed ahead in parallel);
+// an event that needs no more than those (every movement of up to five
+// animals) has all its picks multiplied out at once, since draw q picks among
+// tot - q individuals whatever the earlier picks were, and only the walk over
+// the compartments stays serial.
+constexpr int kPreDraws = 6;
 
 template <int NC>
 __device__ __forceinline__ void draw_individuals(int32_t *x, int32_t *take, uint32_t mask, int32_t n, long long tot,
@@ -1020,6 +1024,26 @@ __device__ __forceinline__ void draw_individuals(int32_t *x, int32_t *take, uint
         take[c] = 0;
         run += ((mask >> c) & 1u) ? x[c] : 0;
         cum[c] = run;
+    }
+    if (pre && n <= kPreDraws) {
+        uint64_t pick[kPreDraws];
+#pragma unroll
+        for (int q = 0; q < kPreDraws; ++q) pick[q] = q < n ? __umul64hi(pre[q], (uint64_t)(tot - q)) : 0ull;
+#pragma unroll
+        for (int q = 0; q < kPreDraws; ++q) {
+            if (q >= n) break;
+            int chosen = 0;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) chosen += (uint64_t)cum[c] <= pick[q] ? 1 : 0;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const int hit = c == chosen ? 1 : 0;
+                x[c] -= hit;
+                take[c] += hit;
+                cum[c] -= c >= chosen ? 1 : 0;
+            }
+        }
+        return;
     }
     Word4 o{0, 0, 0, 0};
     for (int32_t q = 0; q < n; ++q) {
