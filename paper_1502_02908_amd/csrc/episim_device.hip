@@ -1341,10 +1341,16 @@ __global__ __launch_bounds__(kBlock) void k_day(Model m, DevState s, DevEvents e
     const int32_t npe = ssa ? ev.priv_ev_off[k + 1] - pe0 : 0;
     const int32_t set = s.inst[(int64_t)blockIdx.x * kBlock];
     const bool group = s.unit_group[blockIdx.x] != 0;
+    // the unit's nodes among the slots of a day whose remaining events run in
+    // LDS: their final counts go to the day's staging buffer (one per thread)
+    const bool staged = ssa && ev.unit_stage_off;
+    const int32_t st0 = staged ? ev.unit_stage_off[k] : 0;
+    const int32_t nst = staged ? ev.unit_stage_off[k + 1] - st0 : 0;
     if (!block_ok(s.status)) return;
     const uint32_t key0 = s.seed[set], key1 = s.repid[set];
     const bool lds = npe <= kBlock;
     const bool has = lds && (int)threadIdx.x < npe;
+    const int32_t stage_entry = (int)threadIdx.x < nst ? ev.unit_stage[st0 + threadIdx.x] : -1;
     PrivEv mine{0u, 0u, 0, 0, 0, 0};
     if (has) {
         const int64_t e = pe0 + threadIdx.x;
@@ -1359,6 +1365,16 @@ __global__ __launch_bounds__(kBlock) void k_day(Model m, DevState s, DevEvents e
     if (!ssa) return;
     if (!lds) {
         private_tasks<NC>(m, s, ev, d, blockIdx.x, s.Np / kLaneUnit, 0, 1, 1, s.status);
+        if (nst > 0) {
+            __syncthreads();
+            fresh_l1();
+            if (stage_entry >= 0) {
+                const int64_t ls = (int64_t)blockIdx.x * kBlock + (stage_entry & 0xff);
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    ev.stage[(stage_entry >> 8) * NC + c] = comp_on<NC>(m, c) ? load_state(&s.u[(int64_t)c * s.L + ls]) : 0;
+            }
+        }
         return;
     }
     // flush_block's barriers make the parked events and counts visible
@@ -1370,6 +1386,10 @@ __global__ __launch_bounds__(kBlock) void k_day(Model m, DevState s, DevEvents e
 #pragma unroll
         for (int c = 0; c < NC; ++c)
             if (comp_on<NC>(m, c)) s.u[(int64_t)c * s.L + l] = sh_x[c][threadIdx.x];
+    }
+    if (stage_entry >= 0) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) ev.stage[(stage_entry >> 8) * NC + c] = comp_on<NC>(m, c) ? sh_x[c][stage_entry & 0xff] : 0;
     }
 }
 
@@ -1769,9 +1789,9 @@ __device__ __forceinline__ void slot_event(const Model &m, const DevState &s, co
 }
 
 // The day's level events are contiguous (e0 .. e0 + ne - 1, by level, then
-// task); the launch carries the day's offsets so that staging is one round
-// trip for the event fields, slot keys and level bounds, and one more for the
-// slots' counts.
+// task); the launch carries the day's offsets, and the day kernel has staged
+// the slots' counts in slot order, so that staging is one round trip for the
+// event fields, slot keys, level bounds and counts.
 template <int NC>
 __global__ __launch_bounds__(kEvBlock) void k_event_day(Model m, DevState s, DevEvents ev, int32_t d, int32_t lv0,
                                                         int32_t nl, int32_t s0, int32_t ns, int64_t e0,
@@ -1793,13 +1813,13 @@ __global__ __launch_bounds__(kEvBlock) void k_event_day(Model m, DevState s, Dev
         sh_ss[i] = (int16_t)ev.slot_src[e0 + i];
         sh_sd[i] = (int16_t)ev.slot_dst[e0 + i];
     }
+    // the slots' counts, staged by the day kernel that ran before (no wait for slot_pos)
     for (int i = threadIdx.x; i < ns; i += kEvBlock) {
-        const int32_t pos = ev.slot_pos[s0 + i];
         sh_k0[i] = ev.slot_key[3 * (s0 + i)];
         sh_k1[i] = ev.slot_key[3 * (s0 + i) + 1];
         sh_set[i] = (int32_t)ev.slot_key[3 * (s0 + i) + 2];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) sh_u[i * NC + c] = comp_on<NC>(m, c) ? load_state(&s.u[(int64_t)c * s.L + pos]) : 0;
+        for (int c = 0; c < NC; ++c) sh_u[i * NC + c] = ev.stage[i * NC + c];
     }
     __syncthreads();
     if (*(volatile unsigned long long *)s.status != STATUS_OK) return;  // same value in every thread here

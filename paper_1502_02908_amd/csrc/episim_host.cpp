@@ -367,7 +367,7 @@ int64_t order_nodes(const sim_problem *p, int layout, int64_t heavy, int64_t gro
 // Device buffer layout of one handle.
 struct Layout {
     size_t u, phi, node_id, inst, inst_off, seed, coef, alpha, beta, repid, status, ev_g, ev_gm, ev_node,
-        ev_dest, ev_n, ev_meta, ev_smap, task_off, priv_off, priv_ev_off, day_slot_off, slot_pos, slot_key, lvl_ev_off, ev_slot_src, ev_slot_dst, lvl_off, lvl_ptr, prevalence, transitions, totals, snap_u, snap_v, rec_slot, slots,
+        ev_dest, ev_n, ev_meta, ev_smap, task_off, priv_off, priv_ev_off, day_slot_off, slot_pos, unit_stage_off, unit_stage, stage, slot_key, lvl_ev_off, ev_slot_src, ev_slot_dst, lvl_off, lvl_ptr, prevalence, transitions, totals, snap_u, snap_v, rec_slot, slots,
         u0, v0, heavy_pos, unit_heavy, unit_group, pos_region, regional, goal_ref, goal_part, total;
 };
 
@@ -408,6 +408,9 @@ Layout layout_for(int64_t Np, int64_t n_nodes, int64_t n_inst, int64_t Nc, int64
     l.priv_ev_off = take(sizeof(int32_t) * (D * n_units + 1));
     l.day_slot_off = take(sizeof(int32_t) * (D + 1));
     l.slot_pos = take(sizeof(int32_t) * n_day_slots);
+    l.unit_stage_off = take(sizeof(int32_t) * (D * n_units + 1));
+    l.unit_stage = take(sizeof(int32_t) * n_day_slots);
+    l.stage = take(sizeof(int32_t) * kDaySlotCap * MAXC);
     l.slot_key = take(sizeof(uint32_t) * 3 * n_day_slots);
     l.lvl_ev_off = take(sizeof(int64_t) * (n_levels + 1));
     l.ev_slot_src = take(sizeof(int32_t) * n_events);
@@ -456,6 +459,7 @@ struct Packed {
     std::vector<uint8_t> unit_heavy;
     std::vector<uint8_t> unit_group;  // units whose first herd is walked by the whole workgroup
     std::vector<int32_t> day_slot_off, slot_pos, ev_slot_src, ev_slot_dst;  // days run in LDS
+    std::vector<int32_t> unit_stage_off, unit_stage;  // their slots by (day, unit)
     std::vector<uint32_t> slot_key;     // per slot: Philox key (seed, replicate id) and set of its node
     std::vector<int64_t> lvl_ev_off;    // event offsets of each level
     int64_t n_tasks = 0, n_units = 0;
@@ -706,6 +710,24 @@ int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, P
             }
             pk->day_slot_off[d + 1] = (int32_t)pk->slot_pos.size();
         }
+    }
+    // The slots of such a day by unit: the unit's day kernel hands their
+    // counts over in the day's staging buffer (local position | slot << 8).
+    pk->unit_stage_off.assign((size_t)pk->D * U + 1, 0);
+    if (pk->layout == LAYOUT_LANES) {
+        const int64_t G = unit_positions(pk->layout);
+        for (int32_t d = 0; d < pk->D; ++d)
+            for (int32_t i = pk->day_slot_off[d]; i < pk->day_slot_off[d + 1]; ++i)
+                pk->unit_stage_off[(size_t)d * U + pk->slot_pos[i] / G + 1]++;
+        for (size_t i = 0; i + 1 < pk->unit_stage_off.size(); ++i) pk->unit_stage_off[i + 1] += pk->unit_stage_off[i];
+        pk->unit_stage.resize(pk->unit_stage_off.back());
+        std::vector<int32_t> fill(pk->unit_stage_off.begin(), pk->unit_stage_off.end() - 1);
+        for (int32_t d = 0; d < pk->D; ++d)
+            for (int32_t i = pk->day_slot_off[d]; i < pk->day_slot_off[d + 1]; ++i) {
+                const int32_t pos = pk->slot_pos[i];
+                pk->unit_stage[fill[(size_t)d * U + pos / G]++] =
+                    (int32_t)(pos % G) | ((i - pk->day_slot_off[d]) << 8);
+            }
     }
     pk->rec_slot.assign(std::max(pk->D, 1), -1);
     for (int k = 0; k < p0->n_record; ++k) pk->rec_slot[p0->record_days[k]] = k;
@@ -1006,6 +1028,10 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
     ev.priv_ev_off = at<int32_t>(h->ws, l.priv_ev_off);
     ev.day_slot_off = at<int32_t>(h->ws, l.day_slot_off);
     ev.slot_pos = at<int32_t>(h->ws, l.slot_pos);
+    // null without days in LDS: the day kernel then reads no staging lists
+    ev.unit_stage_off = pk.unit_stage.empty() ? nullptr : at<int32_t>(h->ws, l.unit_stage_off);
+    ev.unit_stage = pk.unit_stage.empty() ? nullptr : at<int32_t>(h->ws, l.unit_stage);
+    ev.stage = at<int32_t>(h->ws, l.stage);
     ev.slot_key = at<uint32_t>(h->ws, l.slot_key);
     ev.lvl_ev_off = at<int64_t>(h->ws, l.lvl_ev_off);
     ev.slot_src = at<int32_t>(h->ws, l.ev_slot_src);
@@ -1042,6 +1068,8 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
         {(void *)ev.priv_ev_off, pk.priv_ev_off.data(), sizeof(int32_t) * pk.priv_ev_off.size()},
         {(void *)ev.day_slot_off, pk.day_slot_off.data(), sizeof(int32_t) * pk.day_slot_off.size()},
         {(void *)ev.slot_pos, pk.slot_pos.data(), sizeof(int32_t) * pk.slot_pos.size()},
+        {at<int32_t>(h->ws, l.unit_stage_off), pk.unit_stage_off.data(), sizeof(int32_t) * pk.unit_stage_off.size()},
+        {at<int32_t>(h->ws, l.unit_stage), pk.unit_stage.data(), sizeof(int32_t) * pk.unit_stage.size()},
         {(void *)ev.slot_key, pk.slot_key.data(), sizeof(uint32_t) * pk.slot_key.size()},
         {(void *)ev.lvl_ev_off, pk.lvl_ev_off.data(), sizeof(int64_t) * pk.lvl_ev_off.size()},
         {(void *)ev.slot_src, pk.ev_slot_src.data(), sizeof(int32_t) * pk.ev_slot_src.size()},

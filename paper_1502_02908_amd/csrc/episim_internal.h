@@ -113,6 +113,9 @@ struct DevEvents {
     // slot of its node / destination on such a day, -1 otherwise
     const int32_t *day_slot_off;
     const int32_t *slot_pos;
+    const int32_t *unit_stage_off;  // [D * n_units + 1]: slots of day d held by unit u (one lane per node):
+    const int32_t *unit_stage;      // local position | slot << 8
+    int32_t *stage;                 // [kDaySlotCap * MAXC]: their counts after the day kernel, [slot][c]
     const uint32_t *slot_key;   // [3 per slot] Philox key (seed, replicate id) and set of the slot's node
     const int64_t *lvl_ev_off;  // event offsets of each level
     const int32_t *slot_src;
