@@ -265,7 +265,9 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the per-node hot path "
-              "is measured on a single MI355X; see DESIGN.md for how it would shard.", file=sys.stderr)
+              "is measured on a single MI355X. Independent trajectories would shard across GPUs with no "
+              "communication; one trajectory would shard by node ranges, exchanging the counts of "
+              "cross-range movements once per event level.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -1025,22 +1025,26 @@ __device__ __forceinline__ void draw_individuals(int32_t *x, int32_t *take, uint
         run += ((mask >> c) & 1u) ? x[c] : 0;
         cum[c] = run;
     }
-    if (pre && n <= kPreDraws) {
-        uint64_t pick[kPreDraws];
+    if (pre && n <= kPreDraws && tot <= 0x7fffffffLL) {
+        // the running sums and picks fit 32 bits (the same comparisons)
+        uint32_t pick[kPreDraws], cum32[NC];
 #pragma unroll
-        for (int q = 0; q < kPreDraws; ++q) pick[q] = q < n ? __umul64hi(pre[q], (uint64_t)(tot - q)) : 0ull;
+        for (int c = 0; c < NC; ++c) cum32[c] = (uint32_t)cum[c];
+#pragma unroll
+        for (int q = 0; q < kPreDraws; ++q)
+            pick[q] = q < n ? (uint32_t)__umul64hi(pre[q], (uint64_t)(tot - q)) : 0u;
 #pragma unroll
         for (int q = 0; q < kPreDraws; ++q) {
             if (q >= n) break;
             int chosen = 0;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) chosen += (uint64_t)cum[c] <= pick[q] ? 1 : 0;
+            for (int c = 0; c < NC; ++c) chosen += cum32[c] <= pick[q] ? 1 : 0;
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 const int hit = c == chosen ? 1 : 0;
                 x[c] -= hit;
                 take[c] += hit;
-                cum[c] -= c >= chosen ? 1 : 0;
+                cum32[c] -= c >= chosen ? 1u : 0u;
             }
         }
         return;
