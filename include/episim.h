@@ -133,9 +133,13 @@ typedef struct sim_device_opts {
     void *workspace;
     size_t workspace_bytes;
     int32_t events_mode;   /* SIM_EVENTS_* */
-    int32_t block;         /* threads per workgroup for node kernels: 0 = default (256) */
+    int32_t block;         /* threads per workgroup for node kernels: 0 or 256 (the kernels are built for 256) */
     int32_t launch;        /* SIM_LAUNCH_*: how days are issued */
-    int32_t reserved;
+    int32_t group_herds;   /* with one lane per node and per-day launches, the largest herds per instance of
+                              at least 8192 nodes whose chains a whole workgroup walks: 0 = default (4),
+                              negative = none, at most 16 */
+    int32_t small_level;   /* per-day launches: event levels of at most this many (event, replicate) tasks
+                              run several per launch in one workgroup: 0 = default (512) */
 } sim_device_opts;
 
 #define SIM_LAUNCH_KERNELS    0  /* one launch per day phase and per event level (default) */

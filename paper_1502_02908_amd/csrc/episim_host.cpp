@@ -276,10 +276,12 @@ constexpr int64_t kSoloHerds = 128;
 // (herd, replicate) chain is walked by a wavefront of its own; they are placed
 // first, the remaining positions of their units stay empty.
 constexpr int64_t kHeavyHerds = 32;
-// With one lane per node and per-day launches, the kGroupHerds largest herds
-// of a large instance get a workgroup each: the herd sits at the unit's first
-// position and its chain is walked by all four wavefronts of the workgroup.
+// With one lane per node and per-day launches, the largest herds of a large
+// instance (kGroupHerds unless the options say otherwise) get a workgroup
+// each: the herd sits at the unit's first position and its chain is walked by
+// all four wavefronts of the workgroup.
 constexpr int64_t kGroupHerds = 4;
+constexpr int32_t kMaxGroupHerds = 16;
 
 // One group of herds, ranked largest first, placed from position base: solo
 // wavefronts first (one lane per node, large groups only), then dealt over the
@@ -469,7 +471,7 @@ struct Packed {
 // n_slots > 0 builds a slot handle of one network: n_slots columns of 64
 // replicate lanes, parameters supplied later slot by slot.
 int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, Packed *pk, std::string *err,
-                 int32_t n_slots = 0, int32_t launch = SIM_LAUNCH_KERNELS) {
+                 int32_t n_slots = 0, int32_t launch = SIM_LAUNCH_KERNELS, int32_t group_herds = 0) {
     if (n < 1 || !ps) return *err = "no problems", SIM_EINVAL;
     for (int32_t k = 0; k < n; ++k) {
         int rc = validate(ps[k], err);
@@ -507,7 +509,8 @@ int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, P
         const int64_t heavy = (pk->layout == LAYOUT_TILE && launch == SIM_LAUNCH_KERNELS)
                                   ? std::min<int64_t>(kHeavyHerds, ps[k]->n_nodes / 64) : 0;
         const int64_t group = (pk->layout == LAYOUT_LANES && launch == SIM_LAUNCH_KERNELS &&
-                               ps[k]->n_nodes >= 64 * kSoloHerds) ? kGroupHerds : 0;
+                               ps[k]->n_nodes >= 64 * kSoloHerds && group_herds >= 0)
+                                  ? (group_herds > 0 ? group_herds : kGroupHerds) : 0;
         std::vector<int32_t> preg;
         const int64_t np_k = order_nodes(ps[k], pk->layout, heavy, group, &pos_node[k], &preg);
         pk->pos_region.insert(pk->pos_region.end(), preg.begin(), preg.end());
@@ -760,6 +763,7 @@ struct sim_handle {
     bool own_ws = false;
     hipStream_t stream = nullptr;
     int32_t launch = SIM_LAUNCH_KERNELS;
+    int64_t small_level = kSmallLevel;  // per-day launches: levels run several per launch up to this size
     int32_t day = 0;
     std::string err;
     // kernel timing (sim_kernel_times)
@@ -893,9 +897,12 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
     if (o) opts = *o;
     if (opts.launch != SIM_LAUNCH_KERNELS && opts.launch != SIM_LAUNCH_PERSISTENT)
         return g_create_error = "unknown launch mode", SIM_EINVAL;
+    if (opts.block != 0 && opts.block != 256) return g_create_error = "block must be 0 or 256", SIM_EINVAL;
+    if (opts.group_herds > kMaxGroupHerds) return g_create_error = "group_herds must be at most 16", SIM_EINVAL;
+    if (opts.small_level < 0) return g_create_error = "small_level must not be negative", SIM_EINVAL;
     Packed pk;
     if (n_slots > 0 && opts.events_mode != SIM_EVENTS_LEVELS) return g_create_error = "slot handles run event levels", SIM_EINVAL;
-    int rc = build_packed(ps, n, opts.events_mode, &pk, &g_create_error, n_slots, opts.launch);
+    int rc = build_packed(ps, n, opts.events_mode, &pk, &g_create_error, n_slots, opts.launch, opts.group_herds);
     if (rc != SIM_OK) return rc;
     const sim_problem *p = ps[0];
 
@@ -915,6 +922,7 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
     h->n_nodes = pk.n_nodes;
     h->stream = (hipStream_t)opts.stream;
     h->launch = opts.launch;
+    h->small_level = opts.small_level > 0 ? opts.small_level : kSmallLevel;
     h->lane_of = pk.lane_of;
     h->node_id = pk.node_id;
     h->lvl_off = pk.lvl_off;
@@ -1148,8 +1156,9 @@ int sim_plan_levels(int64_t n_events, const int32_t *ev_day, const int32_t *ev_k
 size_t sim_workspace_bytes_batch(const sim_problem *const *problems, int32_t n_problems, const sim_device_opts *o) {
     std::string err;
     Packed pk;
+    if (o && ((o->block != 0 && o->block != 256) || o->group_herds > kMaxGroupHerds || o->small_level < 0)) return 0;
     if (build_packed(problems, n_problems, o ? o->events_mode : SIM_EVENTS_LEVELS, &pk, &err, 0,
-                     o ? o->launch : SIM_LAUNCH_KERNELS) != SIM_OK)
+                     o ? o->launch : SIM_LAUNCH_KERNELS, o ? o->group_herds : 0) != SIM_OK)
         return 0;
     return layout_of(pk, problems[0]).total;
 }
@@ -1210,14 +1219,14 @@ int sim_run(sim_handle *h, int32_t n_days) {
             }
             while (lv < lv_end) {
                 const int64_t size = (h->lvl_off[lv + 1] - h->lvl_off[lv]) * h->RL;
-                if (size > kSmallLevel) {
+                if (size > h->small_level) {
                     e = timed(h, SIM_K_EVENTS, [&] {
                         return launch_events(h->model, h->st, h->ev, d, h->lvl_off[lv], h->lvl_off[lv + 1], h->stream);
                     });
                     ++lv;
                 } else {
                     int32_t stop = lv + 1;
-                    while (stop < lv_end && (h->lvl_off[stop + 1] - h->lvl_off[stop]) * h->RL <= kSmallLevel) ++stop;
+                    while (stop < lv_end && (h->lvl_off[stop + 1] - h->lvl_off[stop]) * h->RL <= h->small_level) ++stop;
                     const int32_t a = lv;
                     e = timed(h, SIM_K_EVENTS, [&] { return launch_event_levels(h->model, h->st, h->ev, d, a, stop, h->stream); });
                     lv = stop;

@@ -49,7 +49,7 @@ class sim_problem(C.Structure):
 class sim_device_opts(C.Structure):
     _fields_ = [("stream", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
                 ("events_mode", C.c_int32), ("block", C.c_int32), ("launch", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("group_herds", C.c_int32), ("small_level", C.c_int32)]
 
 
 class sim_output(C.Structure):
@@ -150,10 +150,13 @@ def _marshal(p):
     return s, arr
 
 
-def workspace_bytes(p, events_mode=EVENTS_LEVELS):
+def workspace_bytes(p, events_mode=EVENTS_LEVELS, launch=LAUNCH_KERNELS, group_herds=0, small_level=0):
     s, keep = _marshal(p)
     o = sim_device_opts()
     o.events_mode = events_mode
+    o.launch = launch
+    o.group_herds = group_herds
+    o.small_level = small_level
     return int(lib().sim_workspace_bytes(C.byref(s), C.byref(o)))
 
 
@@ -183,7 +186,7 @@ class Simulator:
     R replicates each, state on the device."""
 
     def __init__(self, p, *, events_mode=EVENTS_LEVELS, launch=LAUNCH_KERNELS, stream=None,
-                 torch_workspace=True, device=0):
+                 torch_workspace=True, device=0, group_herds=0, small_level=0):
         probs = list(p) if isinstance(p, (list, tuple)) else [p]
         self.p = probs[0]
         self.n_inst = len(probs)
@@ -200,6 +203,9 @@ class Simulator:
         opts = sim_device_opts()
         opts.events_mode = events_mode
         opts.launch = launch
+        opts.group_herds = group_herds
+        opts.small_level = small_level
+        self.opts = dict(events_mode=events_mode, launch=launch, group_herds=group_herds, small_level=small_level)
         if torch is not None:
             torch.cuda.set_device(device)
             if stream is None:

@@ -1,0 +1,90 @@
+"""Choice of launch shape and level grouping for one workload, by timing.
+
+Every setting of sim_device_opts gives the same trajectory bit for bit: the
+random streams are keyed by node, event and day (include/episim.h), never by
+launch shape, grouping or node order. So a setting can be chosen on speed
+alone. The tuner runs the workload once with the default settings up to a
+day typical of the horizon (half of it by default), keeps that state, and
+then, for each candidate, loads the state into a handle built with the
+candidate's settings and times the same window of days (once untimed, then
+timed). It also checks that every candidate ends the window in the same state.
+
+Candidates vary what the per-day schedule leaves open:
+  launch       per-day kernels, or one cooperative kernel for the whole run;
+  group_herds  how many of the largest herds of a large one-lane-per-node
+               instance get a whole workgroup for their chains (0: default 4,
+               negative: none);
+  small_level  up to which size event levels run several per launch in one
+               workgroup (0: default 512).
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .sim import LAUNCH_KERNELS, LAUNCH_PERSISTENT, Simulator
+
+CANDIDATES = (
+    dict(launch=LAUNCH_KERNELS),
+    dict(launch=LAUNCH_KERNELS, group_herds=-1),
+    dict(launch=LAUNCH_KERNELS, group_herds=8),
+    dict(launch=LAUNCH_KERNELS, small_level=128),
+    dict(launch=LAUNCH_KERNELS, small_level=4096),
+    dict(launch=LAUNCH_PERSISTENT),
+)
+
+
+@dataclass
+class Tuning:
+    best: dict                                  # the fastest candidate's options
+    table: list = field(default_factory=list)   # (options, ms per day of the window) per candidate
+    start_day: int = 0
+    window: int = 0
+
+    def summary(self):
+        rows = [dict(opts=o, ms_per_day=round(ms, 4)) for o, ms in self.table]
+        return dict(best=self.best, start_day=self.start_day, window=self.window, candidates=rows)
+
+
+def _sync_time(sim, n_days):
+    sim.sync()
+    t0 = time.perf_counter()
+    sim.run(n_days)
+    sim.sync()
+    return time.perf_counter() - t0
+
+
+def autotune(p, *, start_day=None, window=None, candidates=CANDIDATES) -> Tuning:
+    """Time each candidate's settings over days [start_day, start_day + window)
+    of problem p (a farmnet.Problem) from the state the default settings reach
+    at start_day; return the fastest. Raises if two candidates end the window
+    in different states (they must not)."""
+    D = p.n_days
+    start = D // 2 if start_day is None else int(start_day)
+    if not 0 <= start < D:
+        raise ValueError("start_day must lie in [0, n_days)")
+    win = min(60, D - start) if window is None else int(window)
+    if not 1 <= win <= D - start:
+        raise ValueError("window must lie in [1, n_days - start_day]")
+    with Simulator(p) as sim:
+        if start:
+            sim.run(start)
+        u0, v0, day = sim.get_state()
+    table, ends = [], []
+    for cand in candidates:
+        with Simulator(p, **cand) as sim:
+            sim.set_state(u0, v0, day)
+            _sync_time(sim, win)           # untimed: code objects, caches
+            sim.set_state(u0, v0, day)
+            dt = _sync_time(sim, win)
+            u, v, d_end = sim.get_state()
+        table.append((dict(cand), 1e3 * dt / win))
+        ends.append((u, v.view(np.int64), d_end))
+    ref = ends[0]
+    for (cand, _), (u, v, d_end) in zip(table, ends):
+        if d_end != ref[2] or not np.array_equal(u, ref[0]) or not np.array_equal(v, ref[1]):
+            raise RuntimeError(f"candidate {cand} ended the window in another state")
+    best = min(table, key=lambda row: row[1])[0]
+    return Tuning(best=best, table=table, start_day=start, window=win)

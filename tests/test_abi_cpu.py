@@ -259,3 +259,17 @@ def test_slot_handle_sizing_and_rejects():
     s, keep = S._marshal(net)
     assert P.lib().sim_slots_create(C.byref(s), 0, None, C.byref(h)) == S.SIM_EINVAL
     assert not h.value
+
+
+def test_device_options_validated_before_device():
+    p = _base()
+    assert S.workspace_bytes(p) > 0
+    assert S.workspace_bytes(p, group_herds=17) == 0
+    assert S.workspace_bytes(p, small_level=-1) == 0
+    s, keep = S._marshal(p)
+    for field, value in (("block", 128), ("group_herds", 17), ("small_level", -5), ("launch", 7)):
+        o = S.sim_device_opts()
+        setattr(o, field, value)
+        h = C.c_void_p()
+        assert P.lib().sim_create(C.byref(s), C.byref(o), C.byref(h)) == S.SIM_EINVAL, field
+        assert P.lib().sim_last_error(None).decode()
