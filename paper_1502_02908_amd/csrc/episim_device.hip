@@ -439,11 +439,14 @@ __device__ __forceinline__ int clock_exact_scan(double clock, const double (&tau
 // the set bits below the lane) and its own pick from that state, until no pick
 // changes. Lane i is settled after i + 1 passes whatever the guesses were, so
 // the result is the one attempt-by-attempt walk gives; with many individuals
-// the rates barely move and one or two passes settle every lane. The waiting
-// times then follow in parallel, and only the clock is summed attempt by
-// attempt in order (binary64 addition rounds each partial sum). The attempts
-// whose sum stays below the window end fire; they form a prefix of the lanes
-// because the clock never decreases. Every lane holds the same chain state.
+// the rates barely move and one or two passes settle every lane (and only the
+// lanes up to the first attempt surely past the window end need to). The
+// waiting times then follow in parallel, and the clock's partial sums, which
+// binary64 addition rounds one by one, come from an exact integer prefix sum
+// (clock_by_scan) or, where that does not apply, attempt by attempt. The
+// attempts whose sum stays below the window end fire; they form a prefix of
+// the lanes because the clock never decreases. Every lane holds the same
+// chain state.
 // Counts are exact integers in binary64 and the rates, running sums, targets
 // and waiting times are the same functions of the same state as in a walk
 // attempt by attempt, so the bits agree.
@@ -756,7 +759,9 @@ __device__ __forceinline__ void chain_uniform(const Model &m, typename Rules::St
 // so while m < 64 chains are live the wavefront computes 64/m blocks per
 // chain in parallel (their -log rand and rand), parks them in LDS, and each
 // live lane then walks its own in order. With all 64 lanes live each lane
-// draws its own block. Every lane of the wavefront must call this.
+// draws its own block; with one chain left, or at most kFewChains of which one
+// still expects many attempts, the whole wavefront walks them one after
+// another (pairs_walk_block). Every lane of the wavefront must call this.
 constexpr uint32_t kFewChains = 4;
 
 template <class Rules>
