@@ -273,3 +273,12 @@ def test_device_options_validated_before_device():
         h = C.c_void_p()
         assert P.lib().sim_create(C.byref(s), C.byref(o), C.byref(h)) == S.SIM_EINVAL, field
         assert P.lib().sim_last_error(None).decode()
+
+
+def test_tuner_rejects_bad_windows_before_device():
+    from paper_1502_02908_amd.tune import autotune
+    p = _base()
+    for kw in (dict(start_day=p.n_days), dict(start_day=-1), dict(start_day=5, window=0),
+               dict(start_day=5, window=p.n_days)):
+        with pytest.raises(ValueError):
+            autotune(p, **kw)
