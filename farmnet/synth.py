@@ -181,7 +181,7 @@ def sise3_network(n_nodes=37000, n_days=1461, seed=2, u=1.0, median=60.0, sigma=
                   max_size=10000, seeded_frac=0.01, seeded_I=0.10,
                   e1_per_node_day=3707.0 / 37221.0, e2_per_node_day=235.0 / 37221.0,
                   in_degree_exponent=2.1, age_days=(100, 400), record_days=None,
-                  model_kw=None):
+                  model_kw=None, shifted_moves=0.0):
     """Age-structured farm network. Births (ENTER into S1) and exits arrive at a
     per-animal rate chosen so that births, exits and the two aging transfers
     per birth (INTERNAL 1->2 after age_days[0], 2->3 after age_days[1]) add up
@@ -189,7 +189,12 @@ def sise3_network(n_nodes=37000, n_days=1461, seed=2, u=1.0, median=60.0, sigma=
     the source in proportion to herd size and the destination in proportion to
     a Pareto weight whose density falls as w^-in_degree_exponent. Within a
     day, single-node events come first (births, aging, exits, each by node),
-    then movements in random order."""
+    then movements in random order. With shifted_moves > 0, that fraction of
+    the movements of calves and young stock carries the aging shift of its
+    class, so the animals land one age class up at the destination (an
+    external transfer whose column moves individuals between compartments,
+    Sec. 3.2); 0 draws no extra numbers, so the default networks do not
+    change."""
     rng = np.random.default_rng(seed)
     size = _lognormal_sizes(rng, n_nodes, median, sigma, 1, max_size)
     cls = np.zeros((n_nodes, 3), np.int64)
@@ -264,12 +269,16 @@ def sise3_network(n_nodes=37000, n_days=1461, seed=2, u=1.0, median=60.0, sigma=
             t[same] = (t[same] + 1 + rng.integers(0, n_nodes - 1, same.sum())) % n_nodes
             c = rng.choice(3, nm, p=move_cls_p)
             n = rng.integers(1, 6, nm)
+            if shifted_moves > 0.0:
+                sh = np.where((c < 2) & (rng.random(nm) < shifted_moves), c, -1)
+            else:
+                sh = np.full(nm, -1)
             ok = _keep_prefix(s * 3 + c, n, lambda k: T[k // 3, k % 3])
-            s, t, c, n = s[ok], t[ok], c[ok], n[ok]
+            s, t, c, n, sh = s[ok], t[ok], c[ok], n[ok], sh[ok]
             np.subtract.at(T, (s, c), n)
-            np.add.at(T, (t, c), n)
+            np.add.at(T, (t, c + (sh >= 0)), n)
             if len(s):
-                blocks.append(_block(d, EXTERNAL, s, t, n, 1 + c, -1))
+                blocks.append(_block(d, EXTERNAL, s, t, n, 1 + c, sh))
     model = sise3_model(u=u, **(model_kw or {}))
     return Problem(n_nodes=n_nodes, n_rep=1, n_days=n_days, u0=u0, v0=np.zeros(n_nodes),
                    seed=seed, record_days=record_days, name=f"sise3_{n_nodes}x{n_days}",

@@ -67,6 +67,39 @@ def test_phi_closed_form(day0):
     assert ok, worst
 
 
+def test_two_node_shifted_external_transfers():
+    """External transfers whose shift column moves the drawn animals into
+    other compartments at the destination (Sec. 3.2): the exact master
+    equation of the two-node system, and the same samples reject the law in
+    which the shift is ignored."""
+    import dataclasses
+    ok, pv = laws.check_two_node_shifted()
+    assert ok, pv
+    p, snap = laws.two_node_shifted_samples()
+    unshifted = dataclasses.replace(p, ev_shift=np.full_like(p.ev_shift, -1))
+    pv = laws.two_node_pvalues(snap, laws.two_node_exact(unshifted))
+    assert min(pv) < 1e-8, pv
+
+
+def test_prevalence_is_binomial_in_pure_recovery():
+    ok, pv = laws.check_prevalence_law()
+    assert ok, pv
+
+
+def test_prevalence_is_taken_after_the_events():
+    # rates zero; select column 2 = {I}: node 0 loses its two infected, node 1
+    # sends its one infected to node 2 (every draw forced), so after day 0's
+    # events only node 2 holds an infected animal
+    m = synth.sis_model()
+    u0 = [[0, 2], [3, 1], [5, 0]]
+    ev = [(0, EXIT, 0, -1, 2, 1, -1), (0, EXTERNAL, 1, 2, 1, 2, -1)]
+    p = synth.events_only(u0, ev, n_days=2)
+    p.E = np.concatenate([m["E"], [[0], [1]]], axis=1).astype(np.int32)
+    r = O.run(p)
+    assert r["prevalence"][:, 0].tolist() == [1, 1]
+    assert r["u"][0].tolist() == [[0, 0], [3, 0], [5, 1]]
+
+
 def test_hypergeometric_removal():
     ok, pv = laws.check_hypergeometric()
     assert ok, pv

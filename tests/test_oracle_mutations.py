@@ -43,6 +43,18 @@ MUTATIONS = {
                        "if (0) continue;\n            if (pick")], laws.check_multivariate_walk),
     # moved animals dropped instead of added at the destination
     "lost_move": ([("xt[to] += m[c];", "(void)to;")], laws.check_conservation),
+    # an external transfer lands its animals unshifted (the shift applied to internal ones only)
+    "external_shift_ignored": ([("int32_t to = c + (sh >= 0 ? p->Nsh",
+                                 "int32_t to = c + (sh >= 0 && kind == EV_INTERNAL ? p->Nsh")],
+                               laws.check_two_node_shifted),
+    # the same slip seen by the class totals of a farm network with shifted moves
+    "external_shift_ignored_totals": ([("int32_t to = c + (sh >= 0 ? p->Nsh",
+                                        "int32_t to = c + (sh >= 0 && kind == EV_INTERNAL ? p->Nsh")],
+                                      laws.check_conservation),
+    # prevalence counting nodes by their size instead of their infected
+    "prevalence_counts_size": ([("if (p->phi_I_mask & (1u << c)) I += ur[(size_t)i * Nc + c];",
+                                 "if (p->phi_N_mask & (1u << c)) I += ur[(size_t)i * Nc + c];")],
+                               laws.check_prevalence_law),
     # phi fed by the state before the events (the other reading of eq:numstep5)
     "phi_before_events": ([("if (!p->phi_pre_events) {", "if (0) {"),
                            ("ntr[i] = ssa_node(p, r, i, d, ur + (size_t)i * Nc, vr[i]);",
