@@ -220,7 +220,15 @@ def sise3_network(n_nodes=37000, n_days=1461, seed=2, u=1.0, median=60.0, sigma=
     w = (1.0 - rng.random(n_nodes)) ** (-1.0 / (in_degree_exponent - 1.0))
     dst_cdf = np.cumsum(w)
     dst_cdf /= dst_cdf[-1]
-    draw = lambda cdf, m: np.minimum(np.searchsorted(cdf, rng.random(m), side="right"), n_nodes - 1)
+    def draw(cdf, m):
+        # node whose cdf interval holds each uniform; the uniforms are searched
+        # in ascending order (far fewer cache misses on a large cdf) and the
+        # answers put back in draw order
+        x = rng.random(m)
+        o = np.argsort(x, kind="stable")
+        out = np.empty(m, np.int64)
+        out[o] = np.searchsorted(cdf, x[o], side="right")
+        return np.minimum(out, n_nodes - 1)
     exit_cls_p = np.array([0.1, 0.2, 0.7])
     move_cls_p = np.array([0.2, 0.3, 0.5])
     pending12 = [[] for _ in range(n_days)]
@@ -319,6 +327,35 @@ def prior_draws(n, seed):
     coef[:, 1::2] = gam
     beta = rng.uniform(*PRIOR_BOX["beta"], (n, 4))
     return coef, np.ones(n), beta
+
+
+def batched_replicates(R=256, n_days=730, seed=4):
+    """The batched workload of the fitting pattern (Sec. 4.3): R replicates of
+    the 37,000-node network over its first n_days days, each with its own
+    prior-box parameter vector (seed) and replicate id r."""
+    base = config2(n_days=n_days)
+    coef, alpha, beta = prior_draws(R, seed=seed)
+    return base.with_replicates(R, coef=coef, alpha=alpha, beta=beta, replicate_id=np.arange(R, dtype=np.uint32))
+
+
+def uneven_sizes(n_inst=64, seed=4, lo=1e3, hi=2e5):
+    """Node counts of the uneven instances, log-uniform in [lo, hi]."""
+    rng = np.random.default_rng(seed)
+    return np.exp(rng.uniform(np.log(lo), np.log(hi), n_inst)).astype(int)
+
+
+def uneven_instance(j, n_nodes, n_days=730, seed=4, n_inst=64):
+    """Instance j of the uneven-instances workload: config 2's generator at
+    n_nodes nodes with seed 4000 + j, one trajectory with row j of the
+    prior-box draws."""
+    coef, alpha, beta = prior_draws(n_inst, seed=seed)
+    return sise3_network(n_nodes=int(n_nodes), n_days=n_days, seed=4000 + j).with_replicates(
+        1, coef=coef[j:j + 1], alpha=alpha[j:j + 1], beta=beta[j:j + 1])
+
+
+def uneven_instances(n_inst=64, n_days=730, seed=4):
+    """The 64 uneven instances (1k-200k nodes) of the batched workload."""
+    return [uneven_instance(j, n, n_days, seed, n_inst) for j, n in enumerate(uneven_sizes(n_inst, seed))]
 
 
 SERVING_SIZES = (1000, 37000, 250000)
