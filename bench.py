@@ -74,6 +74,51 @@ def counter_traffic(kernel, workload):
     return int(v) if v else None
 
 
+# Clock of the MI355X compute units (2.4 GHz peak engine clock) and its VALU
+# width: 256 compute units x 4 SIMDs x 16 lanes issue one lane-operation per
+# cycle each (binary64 add/mul and int32 operations alike), 39.3e12 per
+# second; the fp64 vector peak of 78.6 TFLOP/s counts a fused multiply-add
+# as two.
+CLOCK_GHZ = 2.4
+VALU_PEAK_OPS = 256 * 4 * 16 * CLOCK_GHZ * 1e9
+# Lane-operations one SSA attempt of the SISe3 / S<->I models requires: a
+# Philox4x32-10 block (10 rounds of two 32x32->64 products, low and high
+# word, and four xors, plus 18 key additions: 98), two 53-bit uniforms (10),
+# -log(u) (bit split and fold 7, (m-1)/(m+1) with a division of about 10
+# operations, ten Horner steps of a multiply and an add, and the
+# reconstruction: 50), the waiting time (a division: 10) and the clock test
+# (2), the target (1), the inversion over the running sums (12), the state
+# update (2) and the dependent rates with the re-summed lambda (11).
+OPS_PER_ATTEMPT = 98 + 10 + 50 + 10 + 2 + 1 + 12 + 2 + 11
+
+
+def chain_probe(P, synth, torch, half=1000, days=40):
+    """Time per attempt of one long chain walked by a wavefront (the serial
+    critical path of a plain step): the synthetic model of Sec. 4.2 with a
+    single node of S = I = half (lambda = 2 half per day, no events), its day
+    kernel's duration less that of a node with no transitions, over the
+    attempts of a day (transitions + 1)."""
+    def day_us(S0):
+        p = synth.flip_model(n_nodes=1, S0=S0, I0=S0, n_days=days)
+        with P.Simulator(p) as sim:
+            sim.run(0)
+            sim.sync()
+            sim.set_state(p.u0[None], p.v0[None], 0)
+            sim.kernel_times(-1)
+            sim.kernel_times(1)
+            sim.run(0)
+            kt = sim.kernel_times(0)
+            trans = int(sim.trajectory()["transitions"].sum())
+        ms, n = kt["day"]
+        return ms * 1e3 / n, trans / days
+    t_big, per_day = day_us(half)
+    t_empty, _ = day_us(0)
+    us = (t_big - t_empty) / (per_day + 1.0)
+    return dict(us_per_attempt=us, cycles_per_attempt=us * 1e3 * CLOCK_GHZ, attempts_per_day=per_day + 1.0,
+                day_kernel_us=t_big, empty_day_kernel_us=t_empty,
+                probe=f"one node of the synthetic S<->I model with S = I = {half}, {days} days")
+
+
 def batched_leg(P, synth, torch, steps, plain_sample):
     """Trajectories per second, batched against the plain per-trajectory loop:
     256 replicates of the 37k-node network over its first 730 days, each with
@@ -81,11 +126,10 @@ def batched_leg(P, synth, torch, steps, plain_sample):
     one handle (replicate tiles), against the same trajectories run one handle
     and one launch sequence each (timed on plain_sample of them)."""
     import numpy as np
-    base = synth.config2(n_days=730)
     R = 256
-    coef, alpha, beta = synth.prior_draws(R, seed=4)
-    rid = np.arange(R, dtype=np.uint32)
-    pb = base.with_replicates(R, coef=coef, alpha=alpha, beta=beta, replicate_id=rid)
+    pb = synth.batched_replicates(R=R, n_days=730, seed=4)
+    base = pb.with_replicates(1)
+    coef, alpha, beta, rid = pb.coef, pb.alpha, pb.beta, pb.replicate_id
     sim = P.Simulator(pb)
     u0 = np.tile(pb.u0[None], (R, 1, 1))
     v0 = np.tile(pb.v0[None], (R, 1))
@@ -136,12 +180,9 @@ def instances_leg(P, synth, torch, n_inst=64, days=730):
     parameters, over 730 days, packed into one handle against the same
     instances run one handle each."""
     import numpy as np
-    rng = np.random.default_rng(4)
-    sizes = np.exp(rng.uniform(np.log(1e3), np.log(2e5), n_inst)).astype(int)
-    coef, alpha, beta = synth.prior_draws(n_inst, seed=4)
+    sizes = synth.uneven_sizes(n_inst, seed=4)
     t0 = time.perf_counter()
-    insts = [synth.sise3_network(n_nodes=int(n), n_days=days, seed=4000 + j).with_replicates(
-        1, coef=coef[j:j + 1], alpha=alpha[j:j + 1], beta=beta[j:j + 1]) for j, n in enumerate(sizes)]
+    insts = synth.uneven_instances(n_inst, n_days=days, seed=4)
     print(f"[bench] {n_inst} instances ({int(sizes.sum())} nodes) generated in {time.perf_counter() - t0:.0f} s",
           file=sys.stderr, flush=True)
     sim = P.Simulator(insts)
@@ -212,36 +253,83 @@ def serving_leg(P, synth, torch, rate, seconds, budget_gb):
     return out
 
 
-def cpu_baseline(p, seconds):
-    """The oracle on the host's cores over a bounded sample of the workload:
-    the whole horizon if one run fits in `seconds`, else its first days."""
+def plan_stats(P, synth, workload):
+    """Levels per day of the dependency pass (host side of sim_create) and
+    the events of each level, as a histogram over the days."""
+    import numpy as np
+    from farmnet import EXTERNAL
+    p = WORKLOADS[workload]["make"](synth)
+    lv, task = P.plan_levels(p.ev_day, p.ev_kind, p.ev_node, p.ev_dest, p.n_nodes, tasks=True)
+    D = p.n_days
+    per_day = np.zeros(D, np.int64)
+    np.maximum.at(per_day, p.ev_day, lv)
+    ev_per_day = np.bincount(p.ev_day, minlength=D)
+    moves = np.bincount(p.ev_day[p.ev_kind == EXTERNAL], minlength=D)
+    print(f"# dependency levels per day, {WORKLOADS[workload]['desc']}: {p.n_events} events, "
+          f"{int(task.max()) + 1 if len(task) else 0} tasks")
+    print(f"events per day: mean {ev_per_day.mean():.1f}, max {ev_per_day.max()}; "
+          f"external transfers per day: mean {moves.mean():.1f}, max {moves.max()}")
+    print(f"levels per day: mean {per_day.mean():.2f}, median {np.median(per_day):.0f}, max {per_day.max()}")
+    print("levels  days")
+    for k, n in enumerate(np.bincount(per_day)):
+        if n:
+            print(f"{k:6d}  {n}")
+    sizes = np.bincount(lv.astype(np.int64) + p.ev_day.astype(np.int64) * (per_day.max() + 1))
+    sizes = sizes[sizes > 0]
+    print(f"events per (day, level): mean {sizes.mean():.1f}, median {np.median(sizes):.0f}, max {sizes.max()}")
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(p, seconds, runs=5):
+    """The oracle on the host over a bounded sample of the workload: a window
+    of days from the middle of the horizon (the state at its start computed
+    first, untimed, by the oracle itself), timed once on one thread and once
+    fork-join over the host's cores (at most 16, the CPU share of one GPU),
+    each the median of `runs` runs after a warm-up run. The window is sized
+    so that the timed runs take about `seconds` in all."""
+    import numpy as np
     from oracle import oracle as O
-    threads = min(os.cpu_count() or 1, 16)
-    days = p.n_days
-    q = p
-    # size the sample from a short probe run
-    probe_days = max(1, min(p.n_days, 20))
+    cores = max(1, min(os.cpu_count() or 1, 16))
+    start = p.n_days // 2
+    pre = O.run(p, d_begin=0, d_end=start, threads=cores)
+    # size the window from a short probe on one thread
+    probe = min(5, p.n_days - start)
     t0 = time.perf_counter()
-    O.run(p.truncated(probe_days), threads=threads)
-    per_day = (time.perf_counter() - t0) / probe_days
-    if per_day * p.n_days > seconds:
-        days = max(probe_days, int(seconds / per_day))
-        q = p.truncated(days)
-    runs, t_total, trans = 0, 0.0, 0
-    while t_total < seconds or runs == 0:
-        t0 = time.perf_counter()
-        r = O.run(q, threads=threads)
-        t_total += time.perf_counter() - t0
-        trans += int(r["transitions"].sum())
-        runs += 1
-        if runs >= 20:
-            break
-    nd = q.n_nodes * q.n_days * q.n_rep * runs
-    what = "the full workload" if days == p.n_days else f"the first {days} of its {p.n_days} days"
-    return dict(value=nd / t_total, unit="node-days/s", cores=threads, kind="oracle",
-                sample=f"{what} ({p.n_nodes} nodes), {runs} run(s), "
-                       f"oracle fork-join over {threads} threads, {t_total:.1f} s",
-                transitions_per_s=trans / t_total)
+    O.run(p, d_begin=start, d_end=start + probe, u=pre["u"], v=pre["v"], threads=1)
+    per_day_1 = (time.perf_counter() - t0) / probe
+    share = seconds / (runs * (1.0 + 1.0 / max(cores / 2.0, 1.0)))
+    days = int(max(probe, min(p.n_days - start, share / per_day_1)))
+
+    def leg(threads):
+        O.run(p, d_begin=start, d_end=start + days, u=pre["u"], v=pre["v"], threads=threads)  # warm-up
+        times, trans = [], 0
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            r = O.run(p, d_begin=start, d_end=start + days, u=pre["u"], v=pre["v"], threads=threads)
+            times.append(time.perf_counter() - t0)
+            trans = int(r["transitions"].sum())
+        med = float(np.median(times))
+        nd = p.n_nodes * p.n_rep * days
+        return dict(value=nd / med, transitions_per_s=trans / med, median_s=med, runs=runs)
+
+    one = leg(1)
+    many = leg(cores)
+    return dict(value=many["value"], unit="node-days/s", cores=cores, kind="oracle",
+                sample=f"days {start}-{start + days - 1} of {p.n_days} ({p.n_nodes} nodes, state at day {start} "
+                       f"from the oracle), median of {runs} runs after a warm-up, fork-join over {cores} threads "
+                       f"(SSA and phi node loops; events serial)",
+                transitions_per_s=many["transitions_per_s"], cpu_model=cpu_model(), host_threads=os.cpu_count(),
+                single_thread=dict(value=one["value"], unit="node-days/s", cores=1,
+                                   transitions_per_s=one["transitions_per_s"]))
 
 
 def main():
@@ -260,6 +348,8 @@ def main():
     ap.add_argument("--serving-budget-gb", type=float, default=96.0, help="HBM budget for the slots")
     ap.add_argument("--plain-sample", type=int, default=6)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--plan-stats", action="store_true",
+                    help="only print the dependency pass's levels per day and events per level (host only)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (profiler calibration)")
     args = ap.parse_args()
@@ -271,11 +361,14 @@ def main():
         sys.exit(2)
 
     import numpy as np
-    import torch
 
     import paper_1502_02908_amd as P
     from farmnet import synth
 
+    if args.plan_stats:
+        plan_stats(P, synth, args.workload)
+        return
+    import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     if args.calibrate_copy:
@@ -317,6 +410,7 @@ def main():
         print(f"[bench] step {k}: {times[-1] * 1e3:.2f} ms", file=sys.stderr, flush=True)
     traj = sim.trajectory()
     trans_per_step = int(traj["transitions"].sum())
+    most = traj["max_transitions"].max(axis=1).astype(np.int64)   # the day's longest chain
     total = sum(times)
     node_days = p.n_nodes * p.n_days * p.n_rep * args.steps
     value = node_days / total
@@ -358,6 +452,31 @@ def main():
                         for k, v in kt.items() if v[1]}
     sim.close()
 
+    # the serial critical path: each day's longest SSA chain, walked attempt
+    # after attempt, at the per-attempt time of a single long chain
+    probe = chain_probe(P, synth, torch)
+    chain_ms = float((most + 1).sum()) * probe["us_per_attempt"] / 1e3
+    step_ms = total / args.steps * 1e3
+    critical = dict(longest_chain_attempts_per_step=int((most + 1).sum()),
+                    longest_chain_per_day=dict(max=int(most.max()), median=float(np.median(most)),
+                                               p99=float(np.percentile(most, 99))),
+                    us_per_attempt=round(probe["us_per_attempt"], 5),
+                    cycles_per_attempt=round(probe["cycles_per_attempt"], 1),
+                    chain_ms_per_step=round(chain_ms, 3), step_ms=round(step_ms, 3),
+                    frac=round(chain_ms / step_ms, 4), probe=probe["probe"])
+    roofline["binding"] = ("serial SSA chain of the day's largest herd (critical_path.frac of the step), "
+                           "not HBM")
+    # SSA-heavy workloads: VALU lane-operations of the attempts against the VALU peak
+    alu = None
+    if args.workload in ("synthetic-1k", "sise3-37k-u10"):
+        attempts = trans_per_step + p.n_nodes * p.n_rep * p.n_days   # at most one rejected attempt per node-day
+        day_s = kt["day"][0] / 1e3 / steps_timed
+        ops = attempts * OPS_PER_ATTEMPT
+        alu = dict(bound="alu", achieved=round(ops / day_s / 1e12, 4), peak=round(VALU_PEAK_OPS / 1e12, 2),
+                   unit="T lane-ops/s", frac=round(ops / day_s / VALU_PEAK_OPS, 5), traffic=None,
+                   kernel="day", per_unit=f"{OPS_PER_ATTEMPT} lane-ops per SSA attempt x {attempts} attempts "
+                                          f"(transitions + node-days) per step, over the day kernels' time")
+
     batched = None
     if not args.no_batched and args.workload == "sise3-37k":
         batched = batched_leg(P, synth, torch, max(1, min(args.steps, 3)), args.plain_sample)
@@ -380,7 +499,9 @@ def main():
                     events=p.n_events, launch=args.launch, step="one full-horizon simulation"),
         transitions_per_s=round(trans_per_step * args.steps / total, 1),
         transitions_per_step=trans_per_step,
-        roofline=roofline, kernels=kernel_breakdown, batched=batched, cpu_baseline=cpu)
+        roofline=roofline, critical_path=critical, kernels=kernel_breakdown, batched=batched, cpu_baseline=cpu)
+    if alu:
+        line["alu_roofline"] = alu
     if instances:
         line["instances"] = instances
     if serving:

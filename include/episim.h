@@ -154,6 +154,8 @@ typedef struct sim_device_opts {
  *   regional[D*R*n_regions*Nc]
  *                         X summed over the nodes of each region after day d's events, [d][r][j][c]
  *                         (the inner sum of eq:goal for one sample trajectory)
+ *   max_transitions[D*R]  the most SSA transitions one node applied on day d, [d][r]: the
+ *                         length of the day's longest chain of Algorithm 1's inner loop
  * Days not yet simulated read as 0. */
 typedef struct sim_output {
     int32_t *prevalence;
@@ -162,6 +164,7 @@ typedef struct sim_output {
     int32_t *snap_u;
     double *snap_v;
     int64_t *regional;
+    int32_t *max_transitions;
 } sim_output;
 
 typedef struct sim_handle sim_handle;
@@ -193,8 +196,11 @@ size_t sim_workspace_bytes_batch(const sim_problem *const *problems, int32_t n_p
                                  const sim_device_opts *o);
 
 /* Enqueue days [day, day + n_days) on the handle's stream (n_days = 0: to the
- * horizon). Asynchronous: device-side errors (SIM_EINFEASIBLE) are reported
- * by the next synchronising call. SIM_ESTATE past the horizon. */
+ * horizon): each day is one pass of Algorithm 1's outer loop (Sec. 3.1, the
+ * splitting eq:numstep3 -> eq:numstep4 -> eq:numstep5): the SSA of every node
+ * over the window, the day's events in list order, then the phi update.
+ * Asynchronous: device-side errors (SIM_EINFEASIBLE) are reported by the next
+ * synchronising call. SIM_ESTATE past the horizon. */
 int sim_run(sim_handle *h, int32_t n_days);
 
 /* Wait for the handle's work; returns the first device-side error, if any.
@@ -202,10 +208,16 @@ int sim_run(sim_handle *h, int32_t n_days);
  * replicate and day. */
 int sim_sync(sim_handle *h);
 
-/* Copy the daily records (all D days) to the caller's buffers; synchronises. */
+/* Copy the daily records (all D days) to the caller's buffers; synchronises.
+ * The records are the outputs of Algorithm 1's loop read after each day's
+ * events: node prevalence and compartment totals of X (Sec. 2.2), the SSA
+ * transitions of the day (Sec. 3.3), snapshots of X and Y (Sec. 2.3). */
 int sim_trajectory(sim_handle *h, sim_output *out);
 
 /* Checkpoint: u[R*Nn*Nc] ([r][i][c]), v[R*Nn], and the next day to simulate.
+ * The state (X, Y) at a window boundary is all Algorithm 1 carries from one
+ * window to the next (the clock is redrawn in every window, Sec. 3.3), so a
+ * run resumed from it is bit-identical to one that never stopped.
  * Synchronises. sim_set_state restores; the records of days >= day are
  * recomputed by later runs. */
 int sim_get_state(sim_handle *h, int32_t *u, double *v, int32_t *day);

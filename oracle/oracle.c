@@ -104,6 +104,7 @@ typedef struct oracle_output {
     int32_t *snap_u;       /* [n_record*R*Nn*Nc] */
     double *snap_v;        /* [n_record*R*Nn] */
     int64_t *regional;     /* [D*R*n_regions*Nc] compartment sums over the nodes of each region (or NULL) */
+    int32_t *max_trans;    /* [D*R] largest number of SSA transitions of one node on the day (or NULL) */
     /* error report: smallest (event index, replicate) that was infeasible */
     int64_t err_event;
     int32_t err_rep;
@@ -381,8 +382,13 @@ int oracle_run(const oracle_problem *p, int32_t *u, double *v, int32_t d_begin, 
             #pragma omp parallel for schedule(dynamic, 64) if (threads > 1)
             for (int32_t i = 0; i < Nn; ++i)
                 ntr[i] = ssa_node(p, r, i, d, ur + (size_t)i * Nc, vr[i]);
-            int64_t trans = 0;
-            for (int32_t i = 0; i < Nn; ++i) trans += ntr[i];
+            int64_t trans = 0, most = 0;
+            for (int32_t i = 0; i < Nn; ++i) {
+                trans += ntr[i];
+                if (ntr[i] > most) most = ntr[i];
+            }
+            /* the longest chain of the day: the straggler of the stochastic step */
+            if (out->max_trans) out->max_trans[(size_t)dd * R + r] = (int32_t)most;
             /* eq:numstep5 as written feeds phi with the state before the
              * events (the variant reading; the default follows Algorithm 1) */
             if (p->phi_pre_events) {

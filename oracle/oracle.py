@@ -40,7 +40,7 @@ class _Output(C.Structure):
     _fields_ = [
         ("prevalence", _i32p), ("transitions", _i64p), ("totals", _i64p),
         ("n_record", C.c_int32), ("record_days", _i32p),
-        ("snap_u", _i32p), ("snap_v", _f64p), ("regional", _i64p),
+        ("snap_u", _i32p), ("snap_v", _f64p), ("regional", _i64p), ("max_trans", _i32p),
         ("err_event", C.c_int64), ("err_rep", C.c_int32), ("err_day", C.c_int32),
     ]
 
@@ -154,10 +154,11 @@ def run(p, d_begin=0, d_end=None, u=None, v=None, threads=1, record_days=None, r
         snap_u=np.zeros((len(rec), R, Nn, Nc), np.int32),
         snap_v=np.zeros((len(rec), R, Nn), np.float64),
         regional=np.zeros((D, R, J, Nc), np.int64),
+        max_transitions=np.zeros((D, R), np.int32),
     )
     o = _Output(_ptr(out["prevalence"], _i32p), _ptr(out["transitions"], _i64p), _ptr(out["totals"], _i64p),
                 len(rec), _ptr(rec, _i32p), _ptr(out["snap_u"], _i32p), _ptr(out["snap_v"], _f64p),
-                _ptr(out["regional"], _i64p) if J else None, -1, -1, -1)
+                _ptr(out["regional"], _i64p) if J else None, _ptr(out["max_transitions"], _i32p), -1, -1, -1)
     rc = lib(lib_path).oracle_run(C.byref(prob), _ptr(u, _i32p), _ptr(v, _f64p), d_begin, d_end, threads, C.byref(o))
     del keep
     out.update(u=u, v=v, rc=rc, err_event=o.err_event, err_rep=o.err_rep, err_day=o.err_day,

@@ -869,7 +869,14 @@ template <int NC>
 struct Tally {
     long long prev, trans;
     long long tot[NC];
+    int32_t most;  // most SSA transitions of one lane's chain (the day's straggler)
 };
+
+__device__ __forceinline__ int32_t wave_max(int32_t v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    return v;
+}
 
 // Sum tallies over the workgroup and add them to the records of one set
 // (every lane of the workgroup belongs to the same trajectory).
@@ -877,8 +884,11 @@ template <int NC>
 __device__ void flush_block(const Model &m, const DevState &s, const Tally<NC> &t, int32_t set, int32_t d_rec,
                             int32_t d_ssa, int32_t region) {
     __shared__ long long part[kWaves][2 + NC];
+    __shared__ int32_t part_most[kWaves];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t S = (int64_t)s.n_inst * s.R;
+    const int32_t most = wave_max(t.most);
+    if (lane == 0) part_most[wave] = most;
     long long v[2 + NC];
     v[0] = t.prev;
     v[1] = t.trans;
@@ -898,7 +908,13 @@ __device__ void flush_block(const Model &m, const DevState &s, const Tally<NC> &
         if (i == 0 && d_rec >= 0) {
             if (sum) atomicAdd(&s.prevalence[d_rec * S + set], (int32_t)sum);
         } else if (i == 1 && d_ssa >= 0) {
-            if (sum) atomicAdd((unsigned long long *)&s.transitions[d_ssa * S + set], (unsigned long long)sum);
+            if (sum) {
+                atomicAdd((unsigned long long *)&s.transitions[d_ssa * S + set], (unsigned long long)sum);
+                int32_t m_all = 0;
+#pragma unroll
+                for (int q = 0; q < kWaves; ++q) m_all = max(m_all, part_most[q]);
+                atomicMax(&s.max_fired[d_ssa * S + set], m_all);
+            }
         } else if (i >= 2 && d_rec >= 0 && comp_on<NC>(m, i - 2)) {
             if (sum) atomicAdd((unsigned long long *)&s.totals[(d_rec * S + set) * m.nc + (i - 2)],
                                (unsigned long long)sum);
@@ -916,10 +932,12 @@ template <int NC>
 __device__ void flush_tile(const Model &m, const DevState &s, const Tally<NC> &t, int32_t set, int32_t d_rec,
                            int32_t d_ssa, int32_t region) {
     __shared__ long long part[kWaves][64][2 + NC];
+    __shared__ int32_t part_most[kWaves][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t S = (int64_t)s.n_inst * s.R;
     part[wave][lane][0] = t.prev;
     part[wave][lane][1] = t.trans;
+    part_most[wave][lane] = t.most;
 #pragma unroll
     for (int c = 0; c < NC; ++c) part[wave][lane][2 + c] = t.tot[c];
     __syncthreads();
@@ -942,8 +960,13 @@ __device__ void flush_tile(const Model &m, const DevState &s, const Tally<NC> &t
                                   (unsigned long long)v[2 + c]);
                 }
         }
-        if (d_ssa >= 0 && v[1])
+        if (d_ssa >= 0 && v[1]) {
             atomicAdd((unsigned long long *)&s.transitions[d_ssa * S + set], (unsigned long long)v[1]);
+            int32_t m_all = 0;
+#pragma unroll
+            for (int q = 0; q < kWaves; ++q) m_all = max(m_all, part_most[q][lane]);
+            atomicMax(&s.max_fired[d_ssa * S + set], m_all);
+        }
     }
     __syncthreads();
 }
@@ -1200,6 +1223,7 @@ __device__ __forceinline__ void day_wave(const Model &m, const DevState &s, int6
     else
         run_chains<Rules>(m, ch, active, node, (uint32_t)d, key0, key1, status, set);
     t.trans += ch.fired;
+    t.most = max(t.most, (int32_t)ch.fired);
     if (hooks.after_ssa(ch, active) && active && ch.fired) {
 #pragma unroll
         for (int c = 0; c < NC; ++c)
@@ -1443,7 +1467,10 @@ __device__ __forceinline__ void heavy_chain(const Model &m, const DevState &s, c
                                   (unsigned long long)t.tot[c]);
                 }
         }
-        if (ssa && t.trans) atomicAdd((unsigned long long *)&s.transitions[d * S + set], (unsigned long long)t.trans);
+        if (ssa && t.trans) {
+            atomicAdd((unsigned long long *)&s.transitions[d * S + set], (unsigned long long)t.trans);
+            atomicMax(&s.max_fired[d * S + set], t.most);
+        }
     }
     if (!ssa) return;
     // the herd's private task of the day (at most one per node and day), run
@@ -1960,6 +1987,7 @@ __global__ __launch_bounds__(kBlock) void k_slot_init(DevState s, int32_t nc, co
         const int64_t row = (i >> 6) * S + (int64_t)slot * 64 + (i & 63);
         s.prevalence[row] = 0;
         s.transitions[row] = 0;
+        s.max_fired[row] = 0;
         for (int c = 0; c < nc; ++c) s.totals[row * nc + c] = 0;
     }
 }
@@ -2049,7 +2077,6 @@ __global__ __launch_bounds__(kBlock) void k_persist(Model m, DevState s, DevEven
             }
             grid.sync();
             fresh_l1();
-        fresh_l1();
         }
     }
 }

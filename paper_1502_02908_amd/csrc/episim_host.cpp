@@ -369,7 +369,7 @@ int64_t order_nodes(const sim_problem *p, int layout, int64_t heavy, int64_t gro
 // Device buffer layout of one handle.
 struct Layout {
     size_t u, phi, node_id, inst, inst_off, seed, coef, alpha, beta, repid, status, ev_g, ev_gm, ev_node,
-        ev_dest, ev_n, ev_meta, ev_smap, task_off, priv_off, priv_ev_off, day_slot_off, slot_pos, unit_stage_off, unit_stage, stage, slot_key, lvl_ev_off, ev_slot_src, ev_slot_dst, lvl_off, lvl_ptr, prevalence, transitions, totals, snap_u, snap_v, rec_slot, slots,
+        ev_dest, ev_n, ev_meta, ev_smap, task_off, priv_off, priv_ev_off, day_slot_off, slot_pos, unit_stage_off, unit_stage, stage, slot_key, lvl_ev_off, ev_slot_src, ev_slot_dst, lvl_off, lvl_ptr, prevalence, transitions, totals, max_fired, snap_u, snap_v, rec_slot, slots,
         u0, v0, heavy_pos, unit_heavy, unit_group, pos_region, regional, goal_ref, goal_part, total;
 };
 
@@ -422,6 +422,7 @@ Layout layout_for(int64_t Np, int64_t n_nodes, int64_t n_inst, int64_t Nc, int64
     l.prevalence = take(sizeof(int32_t) * D * S);
     l.transitions = take(sizeof(int64_t) * D * S);
     l.totals = take(sizeof(int64_t) * D * S * Nc);
+    l.max_fired = take(sizeof(int32_t) * D * S);
     l.snap_u = take(sizeof(int32_t) * n_record * R * n_nodes * Nc);
     l.snap_v = take(sizeof(double) * n_record * R * n_nodes);
     l.rec_slot = take(sizeof(int32_t) * D);
@@ -1012,6 +1013,7 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
     s.prevalence = at<int32_t>(h->ws, l.prevalence);
     s.transitions = at<int64_t>(h->ws, l.transitions);
     s.totals = at<int64_t>(h->ws, l.totals);
+    s.max_fired = at<int32_t>(h->ws, l.max_fired);
     s.snap_u = at<int32_t>(h->ws, l.snap_u);
     s.snap_v = at<double>(h->ws, l.snap_v);
     s.rec_slot = at<int32_t>(h->ws, l.rec_slot);
@@ -1188,6 +1190,7 @@ int sim_run(sim_handle *h, int32_t n_days) {
     int rc = check_device(hipMemsetAsync(h->st.prevalence + (size_t)d0 * S, 0, sizeof(int32_t) * n_days * S, h->stream), &h->err, "clear");
     if (!rc) rc = check_device(hipMemsetAsync(h->st.transitions + (size_t)d0 * S, 0, sizeof(int64_t) * n_days * S, h->stream), &h->err, "clear");
     if (!rc) rc = check_device(hipMemsetAsync(h->st.totals + (size_t)d0 * S * h->Nc, 0, sizeof(int64_t) * n_days * S * h->Nc, h->stream), &h->err, "clear");
+    if (!rc) rc = check_device(hipMemsetAsync(h->st.max_fired + (size_t)d0 * S, 0, sizeof(int32_t) * n_days * S, h->stream), &h->err, "clear");
     if (!rc && h->st.n_regions > 0) {
         const size_t per_day = (size_t)S * h->st.n_regions * h->Nc;
         rc = check_device(hipMemsetAsync(h->st.regional + (size_t)d0 * per_day, 0, sizeof(int64_t) * n_days * per_day, h->stream),
@@ -1284,6 +1287,7 @@ int sim_trajectory(sim_handle *h, sim_output *out) {
         {out->snap_u, h->st.snap_u, sizeof(int32_t) * h->n_record * (size_t)h->R * h->n_nodes * h->Nc},
         {out->snap_v, h->st.snap_v, sizeof(double) * h->n_record * (size_t)h->R * h->n_nodes},
         {out->regional, h->st.regional, sizeof(int64_t) * DS * h->st.n_regions * h->Nc},
+        {out->max_transitions, h->st.max_fired, sizeof(int32_t) * DS},
     };
     for (const Down &d : downs) {
         if (!d.dst || d.bytes == 0) continue;

@@ -87,6 +87,7 @@ struct DevState {
     int32_t *prevalence;        // [D][sets]
     int64_t *transitions;       // [D][sets]
     int64_t *totals;            // [D][sets][nc]
+    int32_t *max_fired;         // [D][sets] most SSA transitions of one node on the day
     int32_t *snap_u;            // [n_record][R][n_nodes][nc]
     double *snap_v;             // [n_record][R][n_nodes]
     const int32_t *rec_slot;    // [D] snapshot slot of day d, or -1

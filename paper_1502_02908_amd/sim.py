@@ -54,7 +54,7 @@ class sim_device_opts(C.Structure):
 
 class sim_output(C.Structure):
     _fields_ = [("prevalence", _i32p), ("transitions", _i64p), ("totals", _i64p),
-                ("snap_u", _i32p), ("snap_v", _f64p), ("regional", _i64p)]
+                ("snap_u", _i32p), ("snap_v", _f64p), ("regional", _i64p), ("max_transitions", _i32p)]
 
 
 # every symbol of include/episim.h with its C signature
@@ -241,12 +241,12 @@ class Simulator:
         S = self.n_inst * R
         out = dict(prevalence=np.zeros((D, S), np.int32), transitions=np.zeros((D, S), np.int64),
                    totals=np.zeros((D, S, Nc), np.int64), snap_u=np.zeros((K, R, Nn, Nc), np.int32),
-                   snap_v=np.zeros((K, R, Nn), np.float64))
+                   snap_v=np.zeros((K, R, Nn), np.float64), max_transitions=np.zeros((D, S), np.int32))
         if self.n_regions:
             out["regional"] = np.zeros((D, S, self.n_regions, Nc), np.int64)
         o = sim_output(_p(out["prevalence"], _i32p), _p(out["transitions"], _i64p), _p(out["totals"], _i64p),
                        _p(out["snap_u"], _i32p), _p(out["snap_v"], _f64p),
-                       _p(out["regional"], _i64p) if self.n_regions else None)
+                       _p(out["regional"], _i64p) if self.n_regions else None, _p(out["max_transitions"], _i32p))
         self._check(lib().sim_trajectory(self._h, C.byref(o)))
         return out
 

@@ -38,7 +38,7 @@ def first_mismatch(a, b):
 
 
 def assert_parity(g, o, check_phi_bits=True):
-    for k in ("u", "prevalence", "transitions", "totals", "snap_u"):
+    for k in ("u", "prevalence", "transitions", "totals", "snap_u", "max_transitions"):
         a, b = np.asarray(g[k]), np.asarray(o[k])
         assert a.shape == b.shape, (k, a.shape, b.shape)
         mm = first_mismatch(a, b)

@@ -93,6 +93,23 @@ def check_flip_clock(lib_path=None):
     return pv > P_MIN, pv
 
 
+def check_max_transitions(lib_path=None, n_nodes=20, R=2000, half=100):
+    """The longest chain of a day (the most transitions of one node): in the
+    synthetic model with S = I = half per node, lambda = 2 half never changes,
+    so each node's transitions in a day are Poisson(2 half), independent over
+    nodes and days, and their maximum over n nodes has cdf F(x)^n."""
+    p = synth.flip_model(n_nodes=n_nodes, S0=half, I0=half, n_days=2).with_replicates(R)
+    r = O.run(p, lib_path=lib_path)
+    m = r["max_transitions"].ravel()
+    x = np.arange(0, 6 * half)
+    cdf_max = stats.poisson.cdf(x, 2 * half) ** n_nodes
+    pmf = np.diff(np.r_[0.0, cdf_max])
+    counts = np.bincount(np.minimum(m, len(x) - 1), minlength=len(x))[:len(x)]
+    pv = gof(counts, pmf / pmf.sum())
+    ok = pv > P_MIN and (r["max_transitions"] <= r["transitions"]).all()
+    return ok, pv
+
+
 # ---------------------------------------------------------------------------
 # Exact master equation of a two-node system over whole days: the per-node
 # chain over [d, d+1) with phi frozen (eq:numstep3) is exp(Q), the events are

@@ -23,6 +23,11 @@ def test_flip_model_transitions_are_poisson_2000():
     assert ok, pv
 
 
+def test_longest_chain_of_a_day():
+    ok, pv = laws.check_max_transitions()
+    assert ok, pv
+
+
 def test_two_node_exact_master_equation():
     ok, pv = laws.check_two_node()
     assert ok, pv

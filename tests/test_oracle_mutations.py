@@ -51,6 +51,9 @@ MUTATIONS = {
     "external_shift_ignored_totals": ([("int32_t to = c + (sh >= 0 ? p->Nsh",
                                         "int32_t to = c + (sh >= 0 && kind == EV_INTERNAL ? p->Nsh")],
                                       laws.check_conservation),
+    # the day's longest chain taken from one node instead of the maximum over nodes
+    "max_transitions_one_node": ([("if (ntr[i] > most) most = ntr[i];", "if (i == 0) most = ntr[i];")],
+                                 laws.check_max_transitions),
     # prevalence counting nodes by their size instead of their infected
     "prevalence_counts_size": ([("if (p->phi_I_mask & (1u << c)) I += ur[(size_t)i * Nc + c];",
                                  "if (p->phi_N_mask & (1u << c)) I += ur[(size_t)i * Nc + c];")],
