@@ -307,6 +307,21 @@ int sim_slot_state(sim_handle *h, int32_t slot, int32_t *u, double *v);
 int sim_goal(sim_handle *h, int32_t instance, const int64_t *reference, int32_t d_begin, int32_t d_end,
              double *G2, double *VG2);
 
+/* sim_goal for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, checks and results, bit for bit, but the staged reference,
+ * the per-day terms and their sums live in a static array of the library in
+ * each GPU's memory (8 MiB, held until the process ends), and the days are
+ * added in order on the device. Nothing is allocated, on the device or by the
+ * runtime on its behalf. The current device must be the one the handle was
+ * created on. SIM_EINVAL if the range needs more than the array holds
+ * (8 bytes per regional sum and day, plus 16 per day). Every call on one GPU
+ * uses the same array and overwrites all of it that it reads: calls that
+ * overlap on one GPU (other threads, other streams) race and must be
+ * serialised by the caller. Synchronises the handle's stream. */
+int sim_goal_noalloc(sim_handle *h, int32_t instance, const int64_t *reference, int32_t d_begin, int32_t d_end,
+                     double *G2, double *VG2);
+
 /* Release all resources. NULL is a no-op. */
 void sim_destroy(sim_handle *h);
 

@@ -16,17 +16,24 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <mutex>
 
 #include "../../include/episim.h"
 #include "episim_internal.h"
 
 #pragma clang fp contract(off)
 
+// Intermediate buffers of the entry points that allocate nothing (the goal
+// function's staged reference and day terms): a fixed array in every GPU's
+// memory, kept until the process ends. Calls on one GPU share it.
+static __device__ __align__(256) unsigned char scratch[episim::kScratchBytes];
+
 namespace episim {
 namespace {
 
 constexpr int kBlock = 256;
 static_assert(kBlock == kLaneUnit, "a workgroup of one-lane-per-node kernels is one unit");
+constexpr int kMaxScratchDevices = 64;
 constexpr int kWaves = kBlock / 64;
 constexpr int kEvKindMask = 3;
 constexpr int kEvBlock = 1024;  // workgroup that runs a group of small event levels
@@ -1964,6 +1971,20 @@ __global__ __launch_bounds__(kBlock) void k_goal(DevState s, int32_t nc, int64_t
     }
 }
 
+// The per-day terms of k_goal added in day order, as sim_goal adds them on the
+// host: out[0] = (((0 + part[0]) + part[1]) + ...), out[1] likewise over
+// part[n .. 2n). One thread.
+__global__ __launch_bounds__(64) void k_goal_sum(const double *part, int32_t n, double *out) {
+    if (threadIdx.x != 0) return;
+    double g = 0.0, v = 0.0;
+    for (int32_t k = 0; k < n; ++k) {
+        g = g + part[k];
+        v = v + part[n + k];
+    }
+    out[0] = g;
+    out[1] = v;
+}
+
 // Start a slot: write its table entry, clear its error word and its records,
 // and load every replicate lane of it with the network's initial state.
 __global__ __launch_bounds__(kBlock) void k_slot_init(DevState s, int32_t nc, const int32_t *u0, const double *v0,
@@ -2222,6 +2243,34 @@ int launch_slot_init(const DevState &s, int32_t nc, const int32_t *u0, const dou
     SlotInfo in = info;
     void *args[] = {&ss, &n, &a, &b, &sl, &in};
     return (int)hipLaunchKernel((void *)&k_slot_init, dim3(grid), dim3(kBlock), args, 0, (hipStream_t)stream);
+}
+
+int launch_goal_sum(const double *part, int32_t n, double *out, void *stream) {
+    const double *pp = part;
+    int32_t nn = n;
+    double *o = out;
+    void *args[] = {&pp, &nn, &o};
+    return (int)hipLaunchKernel((void *)&k_goal_sum, dim3(1), dim3(64), args, 0, (hipStream_t)stream);
+}
+
+int scratch_address(void **out) {
+    static std::mutex lock;
+    static void *cached[kMaxScratchDevices] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return (int)e;
+    if (dev < 0 || dev >= kMaxScratchDevices) return (int)hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(lock);
+    if (!cached[dev]) {
+        // the array's name is a host-side stand-in: its device address on this
+        // GPU comes from the runtime, and only that address is ever used
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return (int)e;
+        cached[dev] = ptr;
+    }
+    *out = cached[dev];
+    return (int)hipSuccess;
 }
 
 int launch_goal(const DevState &s, int32_t nc, int64_t s0, int32_t N, const int64_t *ref, int32_t d_begin,

@@ -763,6 +763,7 @@ struct sim_handle {
     void *ws = nullptr;
     bool own_ws = false;
     hipStream_t stream = nullptr;
+    int device = -1;                    // the GPU current at sim_create, which holds the handle's memory
     int32_t launch = SIM_LAUNCH_KERNELS;
     int64_t small_level = kSmallLevel;  // per-day launches: levels run several per launch up to this size
     int32_t day = 0;
@@ -922,6 +923,7 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
     h->L = pk.Np * pk.RL;
     h->n_nodes = pk.n_nodes;
     h->stream = (hipStream_t)opts.stream;
+    if (hipGetDevice(&h->device) != hipSuccess) h->device = -1;
     h->launch = opts.launch;
     h->small_level = opts.small_level > 0 ? opts.small_level : kSmallLevel;
     h->lane_of = pk.lane_of;
@@ -1408,6 +1410,51 @@ int sim_goal(sim_handle *h, int32_t instance, const int64_t *reference, int32_t 
         *G2 += host[k];
         *VG2 += host[n + k];
     }
+    return SIM_OK;
+}
+
+int sim_goal_noalloc(sim_handle *h, int32_t instance, const int64_t *reference, int32_t d_begin, int32_t d_end,
+                     double *G2, double *VG2) {
+    if (!h || !reference || !G2 || !VG2) return SIM_EINVAL;
+    h->err.clear();
+    if (h->st.n_regions <= 0) return h->err = "the problem has no regions", SIM_ESTATE;
+    if (instance < 0 || instance >= h->n_inst) return h->err = "instance out of range", SIM_EINVAL;
+    if (d_begin < 0 || d_end > h->D || d_end < d_begin) return h->err = "days out of range", SIM_EINVAL;
+    if (d_end > h->day) return h->err = fmt("day %d has not been simulated", d_end - 1), SIM_ESTATE;
+    const int32_t n = d_end - d_begin;
+    const size_t per_day = (size_t)h->st.n_regions * h->Nc;
+    // the staged reference, the day terms and the two sums, each 256-byte aligned
+    const size_t ref_bytes = align_up(sizeof(int64_t) * per_day * n);
+    const size_t part_bytes = align_up(sizeof(double) * 2 * (size_t)n);
+    const size_t need = ref_bytes + part_bytes + sizeof(double) * 2;
+    if (need > kScratchBytes)
+        return h->err = fmt("%d days of %zu regional sums need %zu bytes of scratch; at most %zu", n,
+                            per_day, need, kScratchBytes), SIM_EINVAL;
+    int dev = -1;
+    int rc = check_device(hipGetDevice(&dev), &h->err, "current device");
+    if (rc) return rc;
+    if (dev != h->device)
+        return h->err = fmt("device %d is current; the handle lives on device %d", dev, h->device), SIM_EINVAL;
+    void *base = nullptr;
+    rc = check_device((hipError_t)scratch_address(&base), &h->err, "scratch address");
+    if (rc) return rc;
+    int64_t *ref = at<int64_t>(base, 0);
+    double *part = at<double>(base, ref_bytes);
+    double *sums = at<double>(base, ref_bytes + part_bytes);
+    double host[2] = {0.0, 0.0};
+    if (n > 0) {
+        rc = check_device(hipMemcpyAsync(ref, reference + (size_t)d_begin * per_day, sizeof(int64_t) * n * per_day,
+                                         hipMemcpyHostToDevice, h->stream), &h->err, "upload reference");
+        if (!rc)
+            rc = check_device((hipError_t)launch_goal(h->st, h->Nc, (int64_t)instance * h->R, h->R, ref, d_begin, n,
+                                                      part, h->stream), &h->err, "goal kernel");
+        if (!rc) rc = check_device((hipError_t)launch_goal_sum(part, n, sums, h->stream), &h->err, "goal sum kernel");
+        if (!rc) rc = sim_sync(h);
+        if (!rc) rc = check_device(hipMemcpy(host, sums, sizeof host, hipMemcpyDeviceToHost), &h->err, "download");
+        if (rc) return rc;
+    }
+    *G2 = host[0];
+    *VG2 = host[1];
     return SIM_OK;
 }
 

@@ -158,6 +158,15 @@ int launch_slot_events(const Model &m, const DevState &s, const DevEvents &ev, i
                        int32_t k_end, int64_t max_count, void *stream);
 int launch_goal(const DevState &s, int32_t nc, int64_t s0, int32_t N, const int64_t *ref, int32_t d_begin,
                 int32_t n_days, double *part, void *stream);
+// The day terms part[0 .. n) and part[n .. 2n) added in day order into out[0]
+// and out[1] (one thread; the order of the host loop of sim_goal).
+int launch_goal_sum(const double *part, int32_t n, double *out, void *stream);
+// Bytes of the static device array that the entry points which allocate
+// nothing use for their intermediate buffers (one array per GPU, held until
+// the process ends), and its address on the current device (looked up once
+// per device, then cached).
+constexpr size_t kScratchBytes = (size_t)8 << 20;
+int scratch_address(void **out);
 int launch_slot_init(const DevState &s, int32_t nc, const int32_t *u0, const double *v0, int32_t slot,
                      const SlotInfo &info, void *stream);
 int launch_persistent(const Model &m, const DevState &s, const DevEvents &ev, int32_t d_begin,

@@ -72,6 +72,7 @@ SIGNATURES = {
     "sim_plan_levels": (C.c_int, [C.c_int64, _i32p, _i32p, _i32p, _i32p, C.c_int32, _i32p, _i32p]),
     "sim_kernel_times": (C.c_int, [C.c_void_p, C.c_int32, _f64p, _i64p]),
     "sim_goal": (C.c_int, [C.c_void_p, C.c_int32, _i64p, C.c_int32, C.c_int32, _f64p, _f64p]),
+    "sim_goal_noalloc": (C.c_int, [C.c_void_p, C.c_int32, _i64p, C.c_int32, C.c_int32, _f64p, _f64p]),
     "sim_create_batch": (C.c_int, [C.POINTER(C.POINTER(sim_problem)), C.c_int32, C.POINTER(sim_device_opts),
                                    C.POINTER(C.c_void_p)]),
     "sim_workspace_bytes_batch": (C.c_size_t, [C.POINTER(C.POINTER(sim_problem)), C.c_int32,
@@ -260,6 +261,18 @@ class Simulator:
         d_end = self.D if d_end is None else d_end
         self._check(lib().sim_goal(self._h, int(instance), _p(ref, _i64p), int(d_begin), int(d_end),
                                    C.byref(g), C.byref(vg)))
+        return g.value, vg.value
+
+    def goal_noalloc(self, reference, instance=0, d_begin=0, d_end=None):
+        """goal() through sim_goal_noalloc: the library's static device array
+        instead of the handle's workspace (nothing allocated)."""
+        ref = np.ascontiguousarray(reference, dtype=np.int64)
+        if ref.shape != (self.D, self.n_regions, self.Nc):
+            raise ValueError(f"reference must have shape {(self.D, self.n_regions, self.Nc)}")
+        g, vg = C.c_double(), C.c_double()
+        d_end = self.D if d_end is None else d_end
+        self._check(lib().sim_goal_noalloc(self._h, int(instance), _p(ref, _i64p), int(d_begin), int(d_end),
+                                           C.byref(g), C.byref(vg)))
         return g.value, vg.value
 
     def get_state(self):
