@@ -119,18 +119,34 @@ def chain_probe(P, synth, torch, half=1000, days=40):
                 probe=f"one node of the synthetic S<->I model with S = I = {half}, {days} days")
 
 
-def batched_leg(P, synth, torch, steps, plain_sample):
+def tuned(p, start_day, window, enabled):
+    """The tuner's choice of device options for p (timed candidates over a
+    window of days from a mid-horizon state), or the defaults."""
+    if not enabled:
+        return {}, None
+    from paper_1502_02908_amd.tune import autotune
+    t0 = time.perf_counter()
+    t = autotune(p, start_day=start_day, window=window)
+    summary = t.summary()
+    summary["seconds"] = round(time.perf_counter() - t0, 1)
+    print(f"[bench] tuner: {t.best} ({summary['seconds']} s)", file=sys.stderr, flush=True)
+    return t.best, summary
+
+
+def batched_leg(P, synth, torch, steps, plain_sample, tune=True):
     """Trajectories per second, batched against the plain per-trajectory loop:
     256 replicates of the 37k-node network over its first 730 days, each with
     its own (upsilon_1..3, gamma_1..3, beta_1..4) drawn from the prior box, in
-    one handle (replicate tiles), against the same trajectories run one handle
-    and one launch sequence each (timed on plain_sample of them)."""
+    one handle (replicate tiles, options chosen by the tuner), against the
+    same trajectories run one handle and one launch sequence each (timed on
+    plain_sample of them)."""
     import numpy as np
     R = 256
     pb = synth.batched_replicates(R=R, n_days=730, seed=4)
     base = pb.with_replicates(1)
     coef, alpha, beta, rid = pb.coef, pb.alpha, pb.beta, pb.replicate_id
-    sim = P.Simulator(pb)
+    best, tuning = tuned(pb, 365, 20, tune)
+    sim = P.Simulator(pb, **best)
     u0 = np.tile(pb.u0[None], (R, 1, 1))
     v0 = np.tile(pb.v0[None], (R, 1))
     times = []
@@ -171,7 +187,7 @@ def batched_leg(P, synth, torch, steps, plain_sample):
         transitions_per_s=round(trans / t_batch, 1),
         plain_replicates_per_s=round(1.0 / t_plain, 3),
         plain_sample=f"{plain_sample} of the {R} trajectories, one handle and one per-day launch sequence each",
-        speedup_vs_plain=round(t_plain / t_batch * R, 2))
+        speedup_vs_plain=round(t_plain / t_batch * R, 2), options=best, tuning=tuning)
 
 
 def instances_leg(P, synth, torch, n_inst=64, days=730):
@@ -341,10 +357,11 @@ def main():
     ap.add_argument("--launch", default="kernels", choices=["kernels", "persistent"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-replicates leg")
+    ap.add_argument("--no-tune", action="store_true", help="default device options instead of the tuner's")
     ap.add_argument("--instances", action="store_true", help="add the 64-uneven-instances leg (slow to generate)")
-    ap.add_argument("--serving", action="store_true", help="add the serving leg")
-    ap.add_argument("--serving-rate", type=float, default=2.0, help="request arrivals per second")
-    ap.add_argument("--serving-seconds", type=float, default=30.0, help="seconds of arrivals")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serving-rate", type=float, default=20.0, help="request arrivals per second")
+    ap.add_argument("--serving-seconds", type=float, default=8.0, help="seconds of arrivals")
     ap.add_argument("--serving-budget-gb", type=float, default=96.0, help="HBM budget for the slots")
     ap.add_argument("--plain-sample", type=int, default=6)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -387,7 +404,11 @@ def main():
     p = wl["make"](synth)
     launch = P.LAUNCH_PERSISTENT if args.launch == "persistent" else P.LAUNCH_KERNELS
     print(f"[bench] {wl['desc']}: {p.n_events} events, launch={args.launch}", file=sys.stderr, flush=True)
-    sim = P.Simulator(p, launch=launch)
+    best, tuning = tuned(p, p.n_days // 2, min(30, p.n_days - p.n_days // 2),
+                         not args.no_tune and args.launch == "kernels")
+    opts = dict(launch=launch)
+    opts.update(best)
+    sim = P.Simulator(p, **opts)
     u0 = np.tile(p.u0[None], (p.n_rep, 1, 1))
     v0 = np.tile(p.v0[None], (p.n_rep, 1))
 
@@ -479,11 +500,11 @@ def main():
 
     batched = None
     if not args.no_batched and args.workload == "sise3-37k":
-        batched = batched_leg(P, synth, torch, max(1, min(args.steps, 3)), args.plain_sample)
+        batched = batched_leg(P, synth, torch, max(1, min(args.steps, 3)), args.plain_sample, not args.no_tune)
 
     instances = instances_leg(P, synth, torch) if args.instances else None
     serving = (serving_leg(P, synth, torch, args.serving_rate, args.serving_seconds, args.serving_budget_gb)
-               if args.serving else None)
+               if not args.no_serving and args.workload == "sise3-37k" else None)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -496,10 +517,11 @@ def main():
         ms_per_step=round(total / args.steps * 1e3, 3), higher_is_better=True, scaling="weak",
         vs_baseline=None, dtype="f64", data="synthetic",
         config=dict(workload=wl["desc"], nodes=p.n_nodes, days=p.n_days, replicates=p.n_rep,
-                    events=p.n_events, launch=args.launch, step="one full-horizon simulation"),
+                    events=p.n_events, launch=args.launch, options=best, step="one full-horizon simulation"),
         transitions_per_s=round(trans_per_step * args.steps / total, 1),
         transitions_per_step=trans_per_step,
-        roofline=roofline, critical_path=critical, kernels=kernel_breakdown, batched=batched, cpu_baseline=cpu)
+        roofline=roofline, critical_path=critical, kernels=kernel_breakdown, tuning=tuning, batched=batched,
+        cpu_baseline=cpu)
     if alu:
         line["alu_roofline"] = alu
     if instances:

@@ -148,6 +148,7 @@ template <int NC_, int NT_>
 struct GenericRules {
     static constexpr int NC = NC_, NT = NT_;
     static constexpr int kPairs = 0;
+    static constexpr int kTileWaves = 2;  // waves per SIMD the replicate-tile kernel is built for
     using State = Chain<NC, NT>;
     __device__ static __forceinline__ double rate(const Model &m, const State &c, int k) {
         double xr = 0.0, xr2 = 0.0;
@@ -193,6 +194,12 @@ template <int NP>
 struct PairRules {
     static constexpr int NC = 2 * NP, NT = 2 * NP;
     static constexpr int kPairs = NP;
+    // replicate tiles of paired classes are built for three waves per SIMD
+    // (at most 168 VGPRs, with a 16-byte spill): the third wave hides the
+    // latency of the chains' dependent binary64 arithmetic and of the state
+    // loads (12 % faster on the batched workload than the two waves 185
+    // VGPRs allow; bit-identical)
+    static constexpr int kTileWaves = 3;
     using State = Chain<NC, NT>;
     __device__ static __forceinline__ double rate(const Model &, const State &c, int k) {
         return c.cphi[k] * c.xd[k];
@@ -587,17 +594,17 @@ __device__ __forceinline__ void pairs_walk_block(const Model &m, Chain<2 * NP, 2
 // attempt below it, and the clock of the 256 waiting times decided by
 // wavefront 0. Every thread of the workgroup calls it with the same state and
 // ends with the same state. It pays off for long chains only: a round starts
-// only while the window still expects kGroupMinAttempts attempts
+// only while the window still expects min_attempts attempts
 // (lambda (1 - clock)), and a round whose picks do not settle within
 // kGroupPasses passes is dropped. Returns whether the chain is done; if not,
 // the caller continues with the single-wavefront walk from attempt kbase and
 // state c, which are those at the start of a round.
-constexpr double kGroupMinAttempts = 4096.0;
 constexpr int kGroupPasses = 8;
 
 template <int NP>
 __device__ bool pairs_walk_group(Chain<2 * NP, 2 * NP> &c, uint32_t &kbase, uint32_t node, uint32_t day,
-                                 uint32_t key0, uint32_t key1, unsigned long long *status, int32_t r) {
+                                 uint32_t key0, uint32_t key1, unsigned long long *status, int32_t r,
+                                 double min_attempts) {
     constexpr int NT = 2 * NP;
     constexpr int kRound = kBlock;
     __shared__ unsigned long long sh_b[2][kWaves][NT];  // picks of each wavefront and pass, per transition
@@ -609,7 +616,7 @@ __device__ bool pairs_walk_group(Chain<2 * NP, 2 * NP> &c, uint32_t &kbase, uint
     const unsigned long long below = (1ull << lane) - 1ull;
     int buf = 0;
     for (;;) {
-        if (c.lam * (1.0 - c.clock) < kGroupMinAttempts) return false;  // the same in every thread
+        if (c.lam * (1.0 - c.clock) < min_attempts) return false;  // the same in every thread
         const Word4 o = philox4x32_10(Word4{kbase + (uint32_t)t, node, day, 0u}, key0, key1);
         const double E = minus_log(unit_open(o.a, o.b));
         const double U = unit_open(o.c, o.d);
@@ -766,15 +773,13 @@ __device__ __forceinline__ void chain_uniform(const Model &m, typename Rules::St
 // so while m < 64 chains are live the wavefront computes 64/m blocks per
 // chain in parallel (their -log rand and rand), parks them in LDS, and each
 // live lane then walks its own in order. With all 64 lanes live each lane
-// draws its own block; with one chain left, or at most kFewChains of which one
+// draws its own block; with one chain left, or at most `few` of which one
 // still expects many attempts, the whole wavefront walks them one after
 // another (pairs_walk_block). Every lane of the wavefront must call this.
-constexpr uint32_t kFewChains = 4;
-
 template <class Rules>
 __device__ __forceinline__ void run_chains(const Model &m, typename Rules::State &c, bool live, uint32_t node,
                                            uint32_t day, uint32_t key0, uint32_t key1,
-                                           unsigned long long *status, int32_t r) {
+                                           unsigned long long *status, int32_t r, uint32_t few_chains) {
     __shared__ double sh_e[kWaves][64], sh_u[kWaves][64];
     __shared__ uint32_t sh_node[kWaves][64], sh_key[kWaves][64], sh_seed[kWaves][64], sh_k[kWaves][64];
     const int wave = threadIdx.x >> 6;
@@ -794,7 +799,7 @@ __device__ __forceinline__ void run_chains(const Model &m, typename Rules::State
         // One chain left, or a few of which one still expects many attempts in
         // the window (lambda (1 - clock)): the whole wavefront walks them one
         // after another, 64 attempts at a time, instead of a lane each.
-        const bool few = nlive <= kFewChains &&
+        const bool few = nlive <= few_chains &&
                          (nlive == 1 || __ballot(live && c.lam * (1.0 - c.clock) > 10.0 * (double)nlive) != 0ull);
         for (unsigned long long left = few ? mask : 0ull; left != 0ull; left &= left - 1ull) {
             const int h = __ffsll((long long)left) - 1;
@@ -983,9 +988,10 @@ __device__ void flush_tile(const Model &m, const DevState &s, const Tally<NC> &t
 // as anywhere else. Every thread of the workgroup calls it.
 template <class Rules>
 __device__ void group_chain(const Model &m, typename Rules::State &c, bool live, uint32_t node, uint32_t day,
-                            uint32_t key0, uint32_t key1, unsigned long long *status, int32_t r) {
+                            uint32_t key0, uint32_t key1, unsigned long long *status, int32_t r,
+                            uint32_t few_chains, double min_attempts) {
     if constexpr (Rules::kPairs == 0) {
-        run_chains<Rules>(m, c, live, node, day, key0, key1, status, r);
+        run_chains<Rules>(m, c, live, node, day, key0, key1, status, r, few_chains);
     } else {
         constexpr int NT = Rules::NT;
         __shared__ double sh_x[NT], sh_cphi[NT], sh_cum[NT], sh_lam;
@@ -1020,7 +1026,8 @@ __device__ void group_chain(const Model &m, typename Rules::State &c, bool live,
         uint32_t kb = 0;
         // a short chain, or the end of a long one, is walked by wavefront 0
         // alone (thread 0 is in it)
-        if (!pairs_walk_group<Rules::kPairs>(u, kb, sh_key[0], day, sh_key[1], sh_key[2], status, (int32_t)sh_key[3]) &&
+        if (!pairs_walk_group<Rules::kPairs>(u, kb, sh_key[0], day, sh_key[1], sh_key[2], status, (int32_t)sh_key[3],
+                                             min_attempts) &&
             threadIdx.x < 64)
             pairs_walk_block<Rules::kPairs>(m, u, kb, sh_key[0], day, sh_key[1], sh_key[2], status, (int32_t)sh_key[3]);
         if (threadIdx.x == 0) c = u;
@@ -1117,6 +1124,34 @@ __device__ __forceinline__ void draw_individuals(int32_t *x, int32_t *take, uint
 // and external transfers): 4 bits per source compartment of the event's map.
 __device__ __forceinline__ int shifted(uint32_t smap, int c) { return (int)((smap >> (4 * c)) & 0xFu); }
 
+// The loads day_wave starts from: the lane's position's node and instance, its
+// counts and phi (zeros for a lane past the end).
+template <int NC>
+struct LaneLoad {
+    int32_t x[NC];
+    double phi;
+    int32_t nid, inst;
+};
+
+template <int NC>
+__device__ __forceinline__ LaneLoad<NC> lane_load(const Model &m, const DevState &s, int64_t l) {
+    LaneLoad<NC> q;
+    q.nid = -1;
+    q.inst = 0;
+    q.phi = 0.0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) q.x[c] = 0;
+    if (l < s.L) {
+        const int64_t pos = s.RL == 1 ? l : l / s.RL;
+        q.nid = s.node_id[pos];
+        q.inst = s.inst[pos];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) q.x[c] = comp_on<NC>(m, c) ? s.u[(int64_t)c * s.L + l] : 0;
+        q.phi = s.phi[l];
+    }
+    return q;
+}
+
 // What a kernel may add to day_wave: after_prologue() runs on every lane once
 // the previous day is closed, before the SSA; after_ssa(state, active) sees the
 // lane's chain state after the SSA and returns whether day_wave stores it.
@@ -1144,20 +1179,13 @@ __device__ __forceinline__ void day_wave(const Model &m, const DevState &s, int6
     const int32_t R = s.R, RL = s.RL;
     const bool in_range = l < s.L;
     const int32_t r = !in_range || RL == 1 ? 0 : (int32_t)(l % RL);
-    const int32_t pos = !in_range ? 0 : (RL == 1 ? (int32_t)l : (int32_t)(l / RL));
     const int32_t rec = prologue ? s.rec_slot[d - 1] : -1;
+    const LaneLoad<NC> q = lane_load<NC>(m, s, l);
     int32_t x[NC];
-    double phi = 0.0;
-    int32_t nid = -1, inst = 0;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) x[c] = 0;
-    if (in_range) {
-        nid = s.node_id[pos];
-        inst = s.inst[pos];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) x[c] = comp_on<NC>(m, c) ? s.u[(int64_t)c * s.L + l] : 0;
-        phi = s.phi[l];
-    }
+    for (int c = 0; c < NC; ++c) x[c] = q.x[c];
+    double phi = q.phi;
+    int32_t nid = q.nid, inst = q.inst;
     const bool active = r < r_end && nid >= 0;  // padding positions and idle lanes take part in the wavefront steps only
     if (!active) {
         inst = 0;
@@ -1226,9 +1254,10 @@ __device__ __forceinline__ void day_wave(const Model &m, const DevState &s, int6
     ch.fired = 0;
     Rules::rates(m, ch);
     if (group_walk)
-        group_chain<Rules>(m, ch, active, node, (uint32_t)d, key0, key1, status, set);
+        group_chain<Rules>(m, ch, active, node, (uint32_t)d, key0, key1, status, set, s.few_chains,
+                           s.group_min_attempts);
     else
-        run_chains<Rules>(m, ch, active, node, (uint32_t)d, key0, key1, status, set);
+        run_chains<Rules>(m, ch, active, node, (uint32_t)d, key0, key1, status, set, s.few_chains);
     t.trans += ch.fired;
     t.most = max(t.most, (int32_t)ch.fired);
     if (hooks.after_ssa(ch, active) && active && ch.fired) {
@@ -1362,6 +1391,21 @@ __device__ void private_task_lds(const PrivEv *pe, int i, int n_ev, int32_t (*xs
     for (int c = 0; c < NC; ++c) xs[c][loc] = x[c];
 }
 
+// The LDS of a day whose levels run in LDS: the touched nodes' counts (slots),
+// their Philox keys and sets, the day's events, the level bounds and the first
+// draws of every event.
+template <int NC>
+struct EventDayShared {
+    int32_t u[kDaySlotCap * NC];
+    uint32_t k0[kDaySlotCap], k1[kDaySlotCap];
+    int32_t set[kDaySlotCap];
+    int32_t n[kDayEventCap], g[kDayEventCap];
+    uint32_t meta[kDayEventCap], smap[kDayEventCap];
+    int16_t ss[kDayEventCap], sd[kDayEventCap];
+    int32_t lv[kDayLevelCap + 1];
+    uint64_t pre[kDayEventCap * kPreDraws];
+};
+
 template <class Rules>
 __global__ __launch_bounds__(kBlock) void k_day(Model m, DevState s, DevEvents ev, int32_t d, int32_t prologue,
                                                 int32_t ssa) {
@@ -1415,26 +1459,27 @@ __global__ __launch_bounds__(kBlock) void k_day(Model m, DevState s, DevEvents e
                     ev.stage[(stage_entry >> 8) * NC + c] = comp_on<NC>(m, c) ? load_state(&s.u[(int64_t)c * s.L + ls]) : 0;
             }
         }
-        return;
-    }
-    // flush_block's barriers make the parked events and counts visible
-    if (has && !(sh_pe[threadIdx.x].meta & kMetaCont))
-        private_task_lds<NC>(sh_pe, threadIdx.x, npe, sh_x, sh_touch, (int32_t)(blockIdx.x * kBlock), d, key0, key1,
-                             set, s.status);
-    __syncthreads();
-    if (sh_touch[threadIdx.x]) {
+    } else {
+        // flush_block's barriers make the parked events and counts visible
+        if (has && !(sh_pe[threadIdx.x].meta & kMetaCont))
+            private_task_lds<NC>(sh_pe, threadIdx.x, npe, sh_x, sh_touch, (int32_t)(blockIdx.x * kBlock), d, key0,
+                                 key1, set, s.status);
+        __syncthreads();
+        if (sh_touch[threadIdx.x]) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c)
-            if (comp_on<NC>(m, c)) s.u[(int64_t)c * s.L + l] = sh_x[c][threadIdx.x];
-    }
-    if (stage_entry >= 0) {
+            for (int c = 0; c < NC; ++c)
+                if (comp_on<NC>(m, c)) s.u[(int64_t)c * s.L + l] = sh_x[c][threadIdx.x];
+        }
+        if (stage_entry >= 0) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) ev.stage[(stage_entry >> 8) * NC + c] = comp_on<NC>(m, c) ? sh_x[c][stage_entry & 0xff] : 0;
+            for (int c = 0; c < NC; ++c)
+                ev.stage[(stage_entry >> 8) * NC + c] = comp_on<NC>(m, c) ? sh_x[c][stage_entry & 0xff] : 0;
+        }
     }
 }
 
 // Replicate tiles (replicate lanes in groups of 64): workgroup (x, y) takes
-// positions [x * kTileNodes, (x + 1) * kTileNodes) and replicate lanes
+// positions [x * tile_nodes, (x + 1) * tile_nodes) and replicate lanes
 // [64 y, 64 y + 64); wavefront w walks the positions w, w + 4, ... so a lane
 // always holds the same replicate and its counts add up in registers.
 // In a slot handle, column y is slot y: d is the handle's step, the slot's own
@@ -1484,19 +1529,20 @@ __device__ __forceinline__ void heavy_chain(const Model &m, const DevState &s, c
     // by another lane of this wavefront: lane 0's stores first, then fresh lines
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     fresh_l1();
-    const int64_t k = (int64_t)d * (s.Np / kTileNodes) + pos / kTileNodes;
+    const int64_t k = (int64_t)d * (s.Np / s.tile_nodes) + pos / s.tile_nodes;
     const int64_t t0 = ev.priv_off[k], t1 = ev.priv_off[k + 1];
     for (int64_t tk = t0 + lane; tk < t1; tk += 64)
         if (ev.node[ev.task_off[tk]] == pos) event_task<NC>(m, s, ev, tk, r, d, status);
 }
 
 template <class Rules>
-__global__ __launch_bounds__(kBlock) void k_day_tile(Model m, DevState s, DevEvents ev, int32_t d,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Rules::kTileWaves, 8))) void k_day_tile(
+    Model m, DevState s, DevEvents ev, int32_t d,
                                                      int32_t prologue, int32_t ssa) {
     constexpr int NC = Rules::NC;
     int32_t r_end = s.R;
     unsigned long long *status = s.status;
-    const int64_t nx = s.Np / kTileNodes;
+    const int64_t nx = s.Np / s.tile_nodes;
     if (s.n_heavy && blockIdx.x < nx && s.unit_heavy[blockIdx.x]) return;  // uniform over the workgroup
     if (s.slots) {
         const SlotInfo si = s.slots[blockIdx.y];
@@ -1514,7 +1560,7 @@ __global__ __launch_bounds__(kBlock) void k_day_tile(Model m, DevState s, DevEve
         return;
     }
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t pos0 = (int64_t)blockIdx.x * kTileNodes;
+    const int64_t pos0 = (int64_t)blockIdx.x * s.tile_nodes;
     const int32_t r = (int32_t)blockIdx.y * 64 + lane;
     __shared__ double sh_coef[Rules::NT][64], sh_alpha[64], sh_beta[4][64];
     __shared__ uint32_t sh_k0[64], sh_k1[64];
@@ -1532,7 +1578,7 @@ __global__ __launch_bounds__(kBlock) void k_day_tile(Model m, DevState s, DevEve
     __syncthreads();
     const TileParams tp{sh_coef, sh_alpha, sh_beta, sh_k0, sh_k1};
     Tally<NC> t{};
-    for (int j = wave; j < kTileNodes; j += kWaves) {
+    for (int j = wave; j < s.tile_nodes; j += kWaves) {
         const int64_t pos = pos0 + j;
         if (pos >= s.Np) break;
         day_wave<Rules>(m, s, pos * s.RL + r, d, prologue != 0, ssa != 0, t, r_end, status, &tp);
@@ -1541,7 +1587,7 @@ __global__ __launch_bounds__(kBlock) void k_day_tile(Model m, DevState s, DevEve
     flush_tile<NC>(m, s, t, r < r_end ? s.inst[pos0] * s.R + r : -1, prologue ? d - 1 : -1, ssa ? d : -1,
                    s.n_regions ? s.pos_region[pos0] : -1);
     if (ssa)
-        private_tasks<NC>(m, s, ev, d, blockIdx.x, s.Np / kTileNodes, (int32_t)blockIdx.y * 64, 64, r_end, status);
+        private_tasks<NC>(m, s, ev, d, blockIdx.x, s.Np / s.tile_nodes, (int32_t)blockIdx.y * 64, 64, r_end, status);
 }
 
 // ---------------------------------------------------------------------------
@@ -1834,70 +1880,72 @@ __device__ __forceinline__ void slot_event(const Model &m, const DevState &s, co
 // The day's level events are contiguous (e0 .. e0 + ne - 1, by level, then
 // task); the launch carries the day's offsets, and the day kernel has staged
 // the slots' counts in slot order, so that staging is one round trip for the
-// event fields, slot keys, level bounds and counts.
+// event fields, slot keys, level bounds and counts. Every thread of the
+// workgroup calls it (any workgroup size).
 template <int NC>
-__global__ __launch_bounds__(kEvBlock) void k_event_day(Model m, DevState s, DevEvents ev, int32_t d, int32_t lv0,
-                                                        int32_t nl, int32_t s0, int32_t ns, int64_t e0,
-                                                        int32_t ne) {
-    __shared__ int32_t sh_u[kDaySlotCap * NC];
-    __shared__ uint32_t sh_k0[kDaySlotCap], sh_k1[kDaySlotCap];
-    __shared__ int32_t sh_set[kDaySlotCap];
-    __shared__ int32_t sh_n[kDayEventCap], sh_g[kDayEventCap];
-    __shared__ uint32_t sh_meta[kDayEventCap], sh_smap[kDayEventCap];
-    __shared__ int16_t sh_ss[kDayEventCap], sh_sd[kDayEventCap];
-    __shared__ int32_t sh_lv[kDayLevelCap + 1];
-    __shared__ uint64_t sh_pre[kDayEventCap * kPreDraws];
-    for (int i = threadIdx.x; i <= nl; i += kEvBlock) sh_lv[i] = (int32_t)(ev.lvl_ev_off[lv0 + i] - e0);
-    for (int i = threadIdx.x; i < ne; i += kEvBlock) {
-        sh_meta[i] = ev.meta[e0 + i];
-        sh_smap[i] = ev.smap[e0 + i];
-        sh_n[i] = ev.n[e0 + i];
-        sh_g[i] = ev.g[e0 + i];
-        sh_ss[i] = (int16_t)ev.slot_src[e0 + i];
-        sh_sd[i] = (int16_t)ev.slot_dst[e0 + i];
+__device__ void event_day_levels(const Model &m, const DevState &s, const DevEvents &ev, const EventDayArgs &a,
+                                 int32_t d, EventDayShared<NC> &sh) {
+    const int nth = (int)blockDim.x;
+    const int32_t nl = a.nl, ns = a.ns, ne = (int32_t)a.ne, s0 = a.s0;
+    const int64_t e0 = a.e0;
+    for (int i = threadIdx.x; i <= nl; i += nth) sh.lv[i] = (int32_t)(ev.lvl_ev_off[a.lv0 + i] - e0);
+    for (int i = threadIdx.x; i < ne; i += nth) {
+        sh.meta[i] = ev.meta[e0 + i];
+        sh.smap[i] = ev.smap[e0 + i];
+        sh.n[i] = ev.n[e0 + i];
+        sh.g[i] = ev.g[e0 + i];
+        sh.ss[i] = (int16_t)ev.slot_src[e0 + i];
+        sh.sd[i] = (int16_t)ev.slot_dst[e0 + i];
     }
-    // the slots' counts, staged by the day kernel that ran before (no wait for slot_pos)
-    for (int i = threadIdx.x; i < ns; i += kEvBlock) {
-        sh_k0[i] = ev.slot_key[3 * (s0 + i)];
-        sh_k1[i] = ev.slot_key[3 * (s0 + i) + 1];
-        sh_set[i] = (int32_t)ev.slot_key[3 * (s0 + i) + 2];
+    // the slots' counts, staged by the day kernel (no wait for slot_pos)
+    for (int i = threadIdx.x; i < ns; i += nth) {
+        sh.k0[i] = ev.slot_key[3 * (s0 + i)];
+        sh.k1[i] = ev.slot_key[3 * (s0 + i) + 1];
+        sh.set[i] = (int32_t)ev.slot_key[3 * (s0 + i) + 2];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) sh_u[i * NC + c] = ev.stage[i * NC + c];
+        for (int c = 0; c < NC; ++c) sh.u[i * NC + c] = ev.stage[i * NC + c];
     }
-    __syncthreads();
-    if (*(volatile unsigned long long *)s.status != STATUS_OK) return;  // same value in every thread here
+    if (!block_ok(s.status)) return;  // its barriers also publish the staged fields
     // the first draws of every event do not depend on the state: all at once
-    for (int i = threadIdx.x; i < ne * (kPreDraws / 2); i += kEvBlock) {
+    for (int i = threadIdx.x; i < ne * (kPreDraws / 2); i += nth) {
         const int j = i / (kPreDraws / 2), b = i % (kPreDraws / 2);
-        if ((int)(sh_meta[j] & kEvKindMask) == SIM_ENTER || 2 * b >= sh_n[j]) continue;
-        const int32_t ss = sh_ss[j];
-        const Word4 o = philox4x32_10(Word4{(uint32_t)b, (uint32_t)sh_g[j], (uint32_t)d, 1u}, sh_k0[ss], sh_k1[ss]);
-        sh_pre[j * kPreDraws + 2 * b] = ((uint64_t)o.b << 32) | o.a;
-        sh_pre[j * kPreDraws + 2 * b + 1] = ((uint64_t)o.d << 32) | o.c;
+        if ((int)(sh.meta[j] & kEvKindMask) == SIM_ENTER || 2 * b >= sh.n[j]) continue;
+        const int32_t ss = sh.ss[j];
+        const Word4 o = philox4x32_10(Word4{(uint32_t)b, (uint32_t)sh.g[j], (uint32_t)d, 1u}, sh.k0[ss], sh.k1[ss]);
+        sh.pre[j * kPreDraws + 2 * b] = ((uint64_t)o.b << 32) | o.a;
+        sh.pre[j * kPreDraws + 2 * b + 1] = ((uint64_t)o.d << 32) | o.c;
     }
     __syncthreads();
     for (int32_t k = 0; k < nl; ++k) {
-        for (int32_t i = sh_lv[k] + threadIdx.x; i < sh_lv[k + 1]; i += kEvBlock) {
-            if (sh_meta[i] & kMetaCont) continue;  // applied with its task's first event
-            const int32_t ss = sh_ss[i];
-            int32_t *xs = &sh_u[ss * NC];
-            int32_t *xd = sh_sd[i] >= 0 ? &sh_u[sh_sd[i] * NC] : xs;
+        for (int32_t i = sh.lv[k] + threadIdx.x; i < sh.lv[k + 1]; i += nth) {
+            if (sh.meta[i] & kMetaCont) continue;  // applied with its task's first event
+            const int32_t ss = sh.ss[i];
+            int32_t *xs = &sh.u[ss * NC];
+            int32_t *xd = sh.sd[i] >= 0 ? &sh.u[sh.sd[i] * NC] : xs;
             // one event, or a run of one node's events in list order
             int32_t j = i;
             do {
-                slot_event<NC>(m, s, ev, sh_meta[j], sh_smap[j], sh_n[j], (uint32_t)sh_g[j], (int32_t)(e0 + j), xs, xd, sh_k0[ss],
-                               sh_k1[ss], sh_set[ss], d, s.status, &sh_pre[j * kPreDraws]);
+                slot_event<NC>(m, s, ev, sh.meta[j], sh.smap[j], sh.n[j], (uint32_t)sh.g[j], (int32_t)(e0 + j), xs, xd,
+                               sh.k0[ss], sh.k1[ss], sh.set[ss], d, s.status, &sh.pre[j * kPreDraws]);
                 ++j;
-            } while (j < sh_lv[k + 1] && (sh_meta[j] & kMetaCont));
+            } while (j < sh.lv[k + 1] && (sh.meta[j] & kMetaCont));
         }
         __syncthreads();
     }
-    for (int i = threadIdx.x; i < ns; i += kEvBlock) {
+    for (int i = threadIdx.x; i < ns; i += nth) {
         const int32_t pos = ev.slot_pos[s0 + i];
 #pragma unroll
         for (int c = 0; c < NC; ++c)
-            if (comp_on<NC>(m, c)) s.u[(int64_t)c * s.L + pos] = sh_u[i * NC + c];
+            if (comp_on<NC>(m, c)) s.u[(int64_t)c * s.L + pos] = sh.u[i * NC + c];
     }
+}
+
+// A day's levels in LDS, launched on its own after the day kernel.
+template <int NC>
+__global__ __launch_bounds__(kEvBlock) void k_event_day(Model m, DevState s, DevEvents ev, int32_t d,
+                                                        EventDayArgs a) {
+    __shared__ EventDayShared<NC> sh;
+    event_day_levels<NC>(m, s, ev, a, d, sh);
 }
 
 // Slot handles: level k of each slot's own day, one grid row per slot. With
@@ -2031,13 +2079,13 @@ __global__ __launch_bounds__(kBlock) void k_persist(Model m, DevState s, DevEven
         if (block_ok(s.status)) {
             if (layout == LAYOUT_TILE) {
                 const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-                const int64_t nx = (s.Np + kTileNodes - 1) / kTileNodes;
+                const int64_t nx = (s.Np + s.tile_nodes - 1) / s.tile_nodes;
                 const int64_t n_tiles = nx * (s.RL / 64);
                 for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-                    const int64_t pos0 = (tile % nx) * kTileNodes;
+                    const int64_t pos0 = (tile % nx) * s.tile_nodes;
                     const int32_t r = (int32_t)(tile / nx) * 64 + lane;
                     Tally<NC> t{};
-                    for (int j = wave; j < kTileNodes; j += kWaves) {
+                    for (int j = wave; j < s.tile_nodes; j += kWaves) {
                         const int64_t pos = pos0 + j;
                         if (pos >= s.Np) break;
                         day_wave<Rules>(m, s, pos * s.RL + r, d, prologue, ssa, t, s.R, s.status);
@@ -2142,7 +2190,7 @@ int launch_day(const Model &m, const DevState &s, const DevEvents &ev, int32_t d
     int32_t dd = d, pro = prologue, sa = ssa;
     void *args[] = {&mm, &ss, &ee, &dd, &pro, &sa};
     if (layout == LAYOUT_TILE) {
-        const unsigned nx = (unsigned)((s.Np + kTileNodes - 1) / kTileNodes + (int64_t)s.n_heavy * kHeavyBlocks);
+        const unsigned nx = (unsigned)((s.Np + s.tile_nodes - 1) / s.tile_nodes + (int64_t)s.n_heavy * kHeavyBlocks);
         return (int)hipLaunchKernel(t.tile, dim3(nx, (unsigned)(s.RL / 64)), dim3(kBlock), args, 0,
                                     (hipStream_t)stream);
     }
@@ -2192,7 +2240,7 @@ int launch_persistent(const Model &m, const DevState &s, const DevEvents &ev, in
         snprintf(why, why_len, "persistent kernel cannot be resident (occupancy 0)");
         return (int)hipErrorInvalidConfiguration;
     }
-    const int64_t want = layout == LAYOUT_TILE ? ((s.Np + kTileNodes - 1) / kTileNodes) * (s.RL / 64)
+    const int64_t want = layout == LAYOUT_TILE ? ((s.Np + s.tile_nodes - 1) / s.tile_nodes) * (s.RL / 64)
                                                : (s.L + kBlock - 1) / kBlock;
     int64_t grid = (int64_t)cus * per_cu;
     if (want < grid) grid = want > 0 ? want : 1;
@@ -2220,15 +2268,15 @@ int launch_slot_events(const Model &m, const DevState &s, const DevEvents &ev, i
                                 (hipStream_t)stream);
 }
 
-int launch_event_day(const Model &m, const DevState &s, const DevEvents &ev, int32_t d, int32_t lv0, int32_t nl,
-                     int32_t s0, int32_t ns, int64_t e0, int64_t ne, void *stream) {
+int launch_event_day(const Model &m, const DevState &s, const DevEvents &ev, int32_t d, const EventDayArgs &a,
+                     void *stream) {
     const Table t = pick(m);
     Model mm = m;
     DevState ss = s;
     DevEvents ee = ev;
-    int32_t dd = d, a = lv0, b = nl, c = s0, n = ns, k = (int32_t)ne;
-    int64_t e = e0;
-    void *args[] = {&mm, &ss, &ee, &dd, &a, &b, &c, &n, &e, &k};
+    int32_t dd = d;
+    EventDayArgs aa = a;
+    void *args[] = {&mm, &ss, &ee, &dd, &aa};
     return (int)hipLaunchKernel(t.event_day, dim3(1), dim3(kEvBlock), args, 0, (hipStream_t)stream);
 }
 

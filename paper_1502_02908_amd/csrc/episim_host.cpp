@@ -259,8 +259,8 @@ int choose_layout(int32_t R) { return R == 1 ? LAYOUT_LANES : LAYOUT_TILE; }
 int32_t lane_stride(int32_t R) { return R == 1 ? 1 : (int32_t)(((int64_t)R + 63) / 64 * 64); }
 
 // Nodes of one unit of work and the padding granule of an instance.
-int64_t unit_nodes(int layout) { return layout == LAYOUT_TILE ? kTileNodes : 64; }
-int64_t pad_nodes(int layout) { return unit_positions(layout); /* one workgroup */ }
+int64_t unit_nodes(int layout, int64_t tile) { return layout == LAYOUT_TILE ? tile : 64; }
+int64_t pad_nodes(int layout, int64_t tile) { return unit_positions(layout, tile); /* one workgroup */ }
 
 // Positions of one instance's nodes: herds sorted by size (largest first)
 // are dealt one per unit of work in turn, back and forth (snake order), so the
@@ -282,13 +282,15 @@ constexpr int64_t kHeavyHerds = 32;
 // all four wavefronts of the workgroup.
 constexpr int64_t kGroupHerds = 4;
 constexpr int32_t kMaxGroupHerds = 16;
+constexpr int32_t kMaxHeavyHerds = 256;
 
 // One group of herds, ranked largest first, placed from position base: solo
 // wavefronts first (one lane per node, large groups only), then dealt over the
 // units of the group; the group is padded to whole workgroups / tiles.
 // Returns the positions it takes.
-int64_t place_group(const std::vector<int32_t> &ranked, int layout, int64_t base, std::vector<int32_t> *pos_node) {
-    const int64_t n = (int64_t)ranked.size(), G = unit_nodes(layout), P = pad_nodes(layout);
+int64_t place_group(const std::vector<int32_t> &ranked, int layout, int64_t tile, int64_t base,
+                    std::vector<int32_t> *pos_node) {
+    const int64_t n = (int64_t)ranked.size(), G = unit_nodes(layout, tile), P = pad_nodes(layout, tile);
     // solo wavefronts only pay off when the rest still fills many wavefronts
     const int64_t solo = (layout == LAYOUT_LANES && n >= 64 * kSoloHerds) ? kSoloHerds : 0;
     const int64_t span = n == 0 ? 0 : ((solo * 64 + (n - solo) + P - 1) / P) * P;
@@ -310,8 +312,8 @@ int64_t place_group(const std::vector<int32_t> &ranked, int layout, int64_t base
 // work holds herds of one region only, so the per-unit sums of the records
 // are also regional sums; the heavy herds' own units may mix regions (their
 // chains record on their own).
-int64_t order_nodes(const sim_problem *p, int layout, int64_t heavy, int64_t group, std::vector<int32_t> *pos_node,
-                    std::vector<int32_t> *pos_region) {
+int64_t order_nodes(const sim_problem *p, int layout, int64_t tile, int64_t heavy, int64_t group,
+                    std::vector<int32_t> *pos_node, std::vector<int32_t> *pos_region) {
     const int64_t Nn = p->n_nodes, Nc = p->n_comp;
     // a herd's size is its largest population over the horizon: the SSA only
     // moves individuals between compartments of a node, so node totals follow
@@ -335,11 +337,11 @@ int64_t order_nodes(const sim_problem *p, int layout, int64_t heavy, int64_t gro
     std::vector<int32_t> rank(Nn);
     for (int64_t i = 0; i < Nn; ++i) rank[i] = (int32_t)i;
     std::stable_sort(rank.begin(), rank.end(), [&](int32_t a, int32_t b) { return size[a] > size[b]; });
-    const int64_t G = unit_nodes(layout);
+    const int64_t G = unit_nodes(layout, tile);
     const int64_t hv = layout == LAYOUT_TILE ? std::min(heavy, Nn) : 0;
     const int64_t hv_span = ((hv + G - 1) / G) * G;
     const int64_t gr = layout == LAYOUT_LANES ? std::min(group, Nn) : 0;
-    const int64_t lead = hv_span + gr * pad_nodes(layout);
+    const int64_t lead = hv_span + gr * pad_nodes(layout, tile);
     const int32_t J = p->n_regions > 0 ? p->n_regions : 0;
     auto region_of = [&](int32_t i) { return J > 0 ? p->region[i] : -1; };
     pos_node->assign(lead, -1);
@@ -350,16 +352,16 @@ int64_t order_nodes(const sim_problem *p, int layout, int64_t heavy, int64_t gro
     }
     // a workgroup per group herd: the herd first, the rest padding of its region
     for (int64_t q = 0; q < gr; ++q) {
-        const int64_t b = hv_span + q * pad_nodes(layout);
+        const int64_t b = hv_span + q * pad_nodes(layout, tile);
         (*pos_node)[b] = rank[hv + q];
-        for (int64_t i = 0; i < pad_nodes(layout); ++i) (*pos_region)[b + i] = region_of(rank[hv + q]);
+        for (int64_t i = 0; i < pad_nodes(layout, tile); ++i) (*pos_region)[b + i] = region_of(rank[hv + q]);
     }
     // groups: the herds outside regions, then region by region (one group without regions)
     std::vector<std::vector<int32_t>> groups(J + 1);
     for (int64_t q = hv + gr; q < Nn; ++q) groups[region_of(rank[q]) + 1].push_back(rank[q]);
     int64_t base = lead;
     for (int32_t j = -1; j < J; ++j) {
-        const int64_t span = place_group(groups[j + 1], layout, base, pos_node);
+        const int64_t span = place_group(groups[j + 1], layout, tile, base, pos_node);
         pos_region->resize(base + span, j);
         base += span;
     }
@@ -444,6 +446,7 @@ Layout layout_for(int64_t Np, int64_t n_nodes, int64_t n_inst, int64_t Nc, int64
 // Everything a handle uploads, built on the host from one or more problems.
 struct Packed {
     int32_t n_inst = 0, R = 0, RL = 0, D = 0, Nc = 0, Nt = 0, n_record = 0, layout = 0, n_slots = 0;
+    int64_t tile = kTileNodes;  // positions of one replicate tile
     int64_t Np = 0, n_nodes = 0, n_events = 0, n_levels = 0;
     std::vector<int32_t> node_id, inst, inst_off, inst_pos0;
     std::vector<uint32_t> seed, repid;
@@ -472,7 +475,10 @@ struct Packed {
 // n_slots > 0 builds a slot handle of one network: n_slots columns of 64
 // replicate lanes, parameters supplied later slot by slot.
 int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, Packed *pk, std::string *err,
-                 int32_t n_slots = 0, int32_t launch = SIM_LAUNCH_KERNELS, int32_t group_herds = 0) {
+                 int32_t n_slots = 0, const sim_device_opts *o = nullptr) {
+    const int32_t launch = o ? o->launch : SIM_LAUNCH_KERNELS, group_herds = o ? o->group_herds : 0;
+    const int32_t heavy_herds = o ? o->heavy_herds : 0;
+    pk->tile = o && o->tile_nodes > 0 ? o->tile_nodes : kTileNodes;
     if (n < 1 || !ps) return *err = "no problems", SIM_EINVAL;
     for (int32_t k = 0; k < n; ++k) {
         int rc = validate(ps[k], err);
@@ -507,25 +513,27 @@ int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, P
     for (int32_t k = 0; k < n; ++k) {
         pk->inst_off[k] = (int32_t)pk->n_nodes;
         pk->inst_pos0[k] = (int32_t)pk->Np;
-        const int64_t heavy = (pk->layout == LAYOUT_TILE && launch == SIM_LAUNCH_KERNELS)
-                                  ? std::min<int64_t>(kHeavyHerds, ps[k]->n_nodes / 64) : 0;
+        const int64_t heavy = (pk->layout == LAYOUT_TILE && launch == SIM_LAUNCH_KERNELS && heavy_herds >= 0)
+                                  ? std::min<int64_t>(heavy_herds > 0 ? heavy_herds : kHeavyHerds, ps[k]->n_nodes / 64)
+                                  : 0;
         const int64_t group = (pk->layout == LAYOUT_LANES && launch == SIM_LAUNCH_KERNELS &&
                                ps[k]->n_nodes >= 64 * kSoloHerds && group_herds >= 0)
                                   ? (group_herds > 0 ? group_herds : kGroupHerds) : 0;
         std::vector<int32_t> preg;
-        const int64_t np_k = order_nodes(ps[k], pk->layout, heavy, group, &pos_node[k], &preg);
+        const int64_t np_k = order_nodes(ps[k], pk->layout, pk->tile, heavy, group, &pos_node[k], &preg);
         pk->pos_region.insert(pk->pos_region.end(), preg.begin(), preg.end());
         for (int64_t j = 0; j < heavy; ++j) pk->heavy_pos.push_back((int32_t)(pk->Np + j));
-        for (int64_t j = 0; j < group; ++j) group_units.push_back((pk->Np + j * pad_nodes(pk->layout)) / unit_positions(pk->layout));
+        for (int64_t j = 0; j < group; ++j)
+            group_units.push_back((pk->Np + j * pad_nodes(pk->layout, pk->tile)) / unit_positions(pk->layout, pk->tile));
         pk->Np += np_k;
         pk->n_nodes += ps[k]->n_nodes;
         pk->n_events += ps[k]->n_events;
     }
     if (pk->Np * (int64_t)pk->RL > INT32_MAX) return *err = "positions x replicate lanes must stay below 2^31", SIM_EINVAL;
     if (pk->n_events > INT32_MAX) return *err = "too many events", SIM_EINVAL;
-    pk->unit_heavy.assign(pk->Np / unit_positions(pk->layout), 0);
-    for (int32_t hp : pk->heavy_pos) pk->unit_heavy[hp / unit_positions(pk->layout)] = 1;
-    pk->unit_group.assign(pk->Np / unit_positions(pk->layout), 0);
+    pk->unit_heavy.assign(pk->Np / unit_positions(pk->layout, pk->tile), 0);
+    for (int32_t hp : pk->heavy_pos) pk->unit_heavy[hp / unit_positions(pk->layout, pk->tile)] = 1;
+    pk->unit_group.assign(pk->Np / unit_positions(pk->layout, pk->tile), 0);
     for (int64_t u : group_units) pk->unit_group[u] = 1;
     pk->node_id.assign(pk->Np, -1);
     pk->inst.assign(pk->Np, 0);
@@ -615,11 +623,11 @@ int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, P
     // tasks in execution order: level tasks by level, then by first event;
     // then private tasks by day, unit and first event; a task's events stay
     // together in list order
-    const int64_t U = pk->Np / unit_positions(pk->layout);
+    const int64_t U = pk->Np / unit_positions(pk->layout, pk->tile);
     pk->n_units = U;
     std::vector<int64_t> task_glv(n_tasks, 0), task_n(n_tasks, 0), tslot(n_tasks, 0);
     for (int64_t e = 0; e < E; ++e) {
-        task_glv[task[e]] = priv[task[e]] ? (int64_t)mday[e] * U + mnode[e] / unit_positions(pk->layout)
+        task_glv[task[e]] = priv[task[e]] ? (int64_t)mday[e] * U + mnode[e] / unit_positions(pk->layout, pk->tile)
                                           : pk->lvl_ptr[mday[e]] + level[e] - 1;
         task_n[task[e]]++;
     }
@@ -719,7 +727,7 @@ int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, P
     // counts over in the day's staging buffer (local position | slot << 8).
     pk->unit_stage_off.assign((size_t)pk->D * U + 1, 0);
     if (pk->layout == LAYOUT_LANES) {
-        const int64_t G = unit_positions(pk->layout);
+        const int64_t G = unit_positions(pk->layout, pk->tile);
         for (int32_t d = 0; d < pk->D; ++d)
             for (int32_t i = pk->day_slot_off[d]; i < pk->day_slot_off[d + 1]; ++i)
                 pk->unit_stage_off[(size_t)d * U + pk->slot_pos[i] / G + 1]++;
@@ -890,6 +898,20 @@ int create_slots(sim_handle *h, const sim_problem *p, sim_handle **out) {
     return SIM_OK;
 }
 
+// Every device option's range (the tuner's choices; none changes a result).
+int check_opts(const sim_device_opts &o, std::string *err) {
+    if (o.launch != SIM_LAUNCH_KERNELS && o.launch != SIM_LAUNCH_PERSISTENT) return *err = "unknown launch mode", SIM_EINVAL;
+    if (o.block != 0 && o.block != 256) return *err = "block must be 0 or 256", SIM_EINVAL;
+    if (o.group_herds > kMaxGroupHerds) return *err = "group_herds must be at most 16", SIM_EINVAL;
+    if (o.small_level < 0) return *err = "small_level must not be negative", SIM_EINVAL;
+    if (o.tile_nodes != 0 && (o.tile_nodes < 32 || o.tile_nodes > 512 || (o.tile_nodes & (o.tile_nodes - 1))))
+        return *err = "tile_nodes must be 0 or a power of two in [32, 512]", SIM_EINVAL;
+    if (o.heavy_herds > kMaxHeavyHerds) return *err = "heavy_herds must be at most 256", SIM_EINVAL;
+    if (o.few_chains > 64) return *err = "few_chains must be at most 64", SIM_EINVAL;
+    if (o.group_min_attempts < 0) return *err = "group_min_attempts must not be negative", SIM_EINVAL;
+    return SIM_OK;
+}
+
 int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, sim_handle **out,
            int32_t n_slots = 0) {
     g_create_error.clear();
@@ -897,14 +919,10 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
     *out = nullptr;
     sim_device_opts opts{};
     if (o) opts = *o;
-    if (opts.launch != SIM_LAUNCH_KERNELS && opts.launch != SIM_LAUNCH_PERSISTENT)
-        return g_create_error = "unknown launch mode", SIM_EINVAL;
-    if (opts.block != 0 && opts.block != 256) return g_create_error = "block must be 0 or 256", SIM_EINVAL;
-    if (opts.group_herds > kMaxGroupHerds) return g_create_error = "group_herds must be at most 16", SIM_EINVAL;
-    if (opts.small_level < 0) return g_create_error = "small_level must not be negative", SIM_EINVAL;
+    if (check_opts(opts, &g_create_error)) return SIM_EINVAL;
     Packed pk;
     if (n_slots > 0 && opts.events_mode != SIM_EVENTS_LEVELS) return g_create_error = "slot handles run event levels", SIM_EINVAL;
-    int rc = build_packed(ps, n, opts.events_mode, &pk, &g_create_error, n_slots, opts.launch, opts.group_herds);
+    int rc = build_packed(ps, n, opts.events_mode, &pk, &g_create_error, n_slots, &opts);
     if (rc != SIM_OK) return rc;
     const sim_problem *p = ps[0];
 
@@ -1020,6 +1038,9 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
     s.snap_v = at<double>(h->ws, l.snap_v);
     s.rec_slot = at<int32_t>(h->ws, l.rec_slot);
     s.slots = h->n_slots ? at<SlotInfo>(h->ws, l.slots) : nullptr;
+    s.tile_nodes = (int32_t)pk.tile;
+    s.few_chains = opts.few_chains < 0 ? 0u : (opts.few_chains > 0 ? (uint32_t)opts.few_chains : kFewChains);
+    s.group_min_attempts = opts.group_min_attempts > 0 ? (double)opts.group_min_attempts : kGroupMinAttempts;
     s.n_heavy = (int32_t)pk.heavy_pos.size();
     s.heavy_pos = at<int32_t>(h->ws, l.heavy_pos);
     s.unit_heavy = s.n_heavy ? at<uint8_t>(h->ws, l.unit_heavy) : nullptr;
@@ -1160,9 +1181,8 @@ int sim_plan_levels(int64_t n_events, const int32_t *ev_day, const int32_t *ev_k
 size_t sim_workspace_bytes_batch(const sim_problem *const *problems, int32_t n_problems, const sim_device_opts *o) {
     std::string err;
     Packed pk;
-    if (o && ((o->block != 0 && o->block != 256) || o->group_herds > kMaxGroupHerds || o->small_level < 0)) return 0;
-    if (build_packed(problems, n_problems, o ? o->events_mode : SIM_EVENTS_LEVELS, &pk, &err, 0,
-                     o ? o->launch : SIM_LAUNCH_KERNELS, o ? o->group_herds : 0) != SIM_OK)
+    if (o && check_opts(*o, &err)) return 0;
+    if (build_packed(problems, n_problems, o ? o->events_mode : SIM_EVENTS_LEVELS, &pk, &err, 0, o) != SIM_OK)
         return 0;
     return layout_of(pk, problems[0]).total;
 }
@@ -1214,11 +1234,14 @@ int sim_run(sim_handle *h, int32_t n_days) {
             int32_t lv = h->lvl_ptr[d];
             const int32_t lv_end = h->lvl_ptr[d + 1];
             if (h->day_slot_off[d + 1] > h->day_slot_off[d]) {
-                const int32_t s0 = h->day_slot_off[d], ns = h->day_slot_off[d + 1] - s0;
-                const int64_t e0 = h->lvl_ev_off[lv], ne = h->lvl_ev_off[lv_end] - e0;
-                e = timed(h, SIM_K_EVENTS, [&] {
-                    return launch_event_day(h->model, h->st, h->ev, d, lv, lv_end - lv, s0, ns, e0, ne, h->stream);
-                });
+                EventDayArgs a{};
+                a.lv0 = lv;
+                a.nl = lv_end - lv;
+                a.s0 = h->day_slot_off[d];
+                a.ns = h->day_slot_off[d + 1] - a.s0;
+                a.e0 = h->lvl_ev_off[lv];
+                a.ne = h->lvl_ev_off[lv_end] - a.e0;
+                e = timed(h, SIM_K_EVENTS, [&] { return launch_event_day(h->model, h->st, h->ev, d, a, h->stream); });
                 if (e != hipSuccess) return h->err = fmt("event kernel: %s", hipGetErrorString(e)), SIM_EDEVICE;
                 lv = lv_end;
             }

@@ -79,6 +79,9 @@ struct DevState {
     SlotInfo *slots;            // [RL / 64] slot table of a slot handle, null otherwise
     // replicate tiles: the herds whose every (herd, replicate) chain gets a
     // wavefront of its own, and the units that hold only such herds
+    int32_t tile_nodes;         // positions of one replicate tile (a power of two, 32 .. 512)
+    uint32_t few_chains;        // at most this many live chains of a wavefront are walked one after another
+    double group_min_attempts;  // a workgroup walks one chain while it expects this many attempts
     int32_t n_heavy;
     const int32_t *heavy_pos;   // [n_heavy]
     const uint8_t *unit_heavy;  // [n_units], null if n_heavy == 0
@@ -127,16 +130,24 @@ struct DevEvents {
 // Layouts of the day phase: one lane per node with workgroup sums (R == 1),
 // or tiles of kTileNodes nodes x 64 replicate lanes per workgroup (R > 1,
 // lane stride RL a multiple of 64).
-constexpr int kTileNodes = 128;
+constexpr int kTileNodes = 128;       // default positions of a replicate tile
+constexpr uint32_t kFewChains = 4;     // default: at most this many live chains walked one after another
+constexpr double kGroupMinAttempts = 4096.0;  // default: a workgroup walks a chain expecting this many attempts
 constexpr int kLaneUnit = 256;  // positions of one workgroup with one lane per node
 enum { LAYOUT_LANES = 0, LAYOUT_TILE = 1 };
 
 // Positions per unit of the day phase (a workgroup's nodes); a private task
 // (a level-1 run of one node's single-node events) runs in its node's unit
 // right after the SSA.
-inline int64_t unit_positions(int layout) { return layout == LAYOUT_TILE ? kTileNodes : kLaneUnit; }
+inline int64_t unit_positions(int layout, int64_t tile) { return layout == LAYOUT_TILE ? tile : kLaneUnit; }
 
 // Host-side launchers (episim_device.hip). Each returns a hipError_t as int.
+// A day whose levels run in LDS: its levels lv0 .. lv0 + nl - 1, slots
+// s0 .. s0 + ns - 1 and level events e0 .. e0 + ne - 1.
+struct EventDayArgs {
+    int32_t lv0, nl, s0, ns;
+    int64_t e0, ne;
+};
 int launch_day(const Model &m, const DevState &s, const DevEvents &ev, int32_t d, int prologue, int ssa,
                int layout, void *stream);
 int launch_events(const Model &m, const DevState &s, const DevEvents &ev, int32_t d, int64_t begin,
@@ -152,8 +163,8 @@ constexpr int64_t kSmallLevel = 512;
 constexpr int64_t kDayEventCap = 512;
 constexpr int64_t kDaySlotCap = 768;
 constexpr int64_t kDayLevelCap = 64;
-int launch_event_day(const Model &m, const DevState &s, const DevEvents &ev, int32_t d, int32_t lv0, int32_t nl,
-                     int32_t s0, int32_t ns, int64_t e0, int64_t ne, void *stream);
+int launch_event_day(const Model &m, const DevState &s, const DevEvents &ev, int32_t d, const EventDayArgs &a,
+                     void *stream);
 int launch_slot_events(const Model &m, const DevState &s, const DevEvents &ev, int32_t step, int32_t k,
                        int32_t k_end, int64_t max_count, void *stream);
 int launch_goal(const DevState &s, int32_t nc, int64_t s0, int32_t N, const int64_t *ref, int32_t d_begin,

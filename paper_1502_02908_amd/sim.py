@@ -49,7 +49,12 @@ class sim_problem(C.Structure):
 class sim_device_opts(C.Structure):
     _fields_ = [("stream", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
                 ("events_mode", C.c_int32), ("block", C.c_int32), ("launch", C.c_int32),
-                ("group_herds", C.c_int32), ("small_level", C.c_int32)]
+                ("group_herds", C.c_int32), ("small_level", C.c_int32),
+                ("tile_nodes", C.c_int32), ("heavy_herds", C.c_int32), ("few_chains", C.c_int32),
+                ("group_min_attempts", C.c_int32)]
+# device options a handle takes (every setting gives the same results)
+OPTION_NAMES = ("events_mode", "launch", "group_herds", "small_level", "tile_nodes", "heavy_herds",
+                "few_chains", "group_min_attempts")
 
 
 class sim_output(C.Structure):
@@ -151,13 +156,14 @@ def _marshal(p):
     return s, arr
 
 
-def workspace_bytes(p, events_mode=EVENTS_LEVELS, launch=LAUNCH_KERNELS, group_herds=0, small_level=0):
+def workspace_bytes(p, **opts):
+    """Device bytes of a handle for p with the given device options (0 if rejected)."""
     s, keep = _marshal(p)
     o = sim_device_opts()
-    o.events_mode = events_mode
-    o.launch = launch
-    o.group_herds = group_herds
-    o.small_level = small_level
+    for k, v in opts.items():
+        if k not in OPTION_NAMES:
+            raise TypeError(f"unknown device option {k}")
+        setattr(o, k, int(v))
     return int(lib().sim_workspace_bytes(C.byref(s), C.byref(o)))
 
 
@@ -187,7 +193,8 @@ class Simulator:
     R replicates each, state on the device."""
 
     def __init__(self, p, *, events_mode=EVENTS_LEVELS, launch=LAUNCH_KERNELS, stream=None,
-                 torch_workspace=True, device=0, group_herds=0, small_level=0):
+                 torch_workspace=True, device=0, group_herds=0, small_level=0, tile_nodes=0,
+                 heavy_herds=0, few_chains=0, group_min_attempts=0):
         probs = list(p) if isinstance(p, (list, tuple)) else [p]
         self.p = probs[0]
         self.n_inst = len(probs)
@@ -201,12 +208,12 @@ class Simulator:
         torch = _torch_cuda()
         structs, keep = zip(*[_marshal(q) for q in probs])
         arr = (C.POINTER(sim_problem) * len(structs))(*[C.pointer(st) for st in structs])
+        self.opts = dict(events_mode=events_mode, launch=launch, group_herds=group_herds, small_level=small_level,
+                         tile_nodes=tile_nodes, heavy_herds=heavy_herds,
+                         few_chains=few_chains, group_min_attempts=group_min_attempts)
         opts = sim_device_opts()
-        opts.events_mode = events_mode
-        opts.launch = launch
-        opts.group_herds = group_herds
-        opts.small_level = small_level
-        self.opts = dict(events_mode=events_mode, launch=launch, group_herds=group_herds, small_level=small_level)
+        for k, v in self.opts.items():
+            setattr(opts, k, int(v))
         if torch is not None:
             torch.cuda.set_device(device)
             if stream is None:

@@ -9,13 +9,23 @@ then, for each candidate, loads the state into a handle built with the
 candidate's settings and times the same window of days (once untimed, then
 timed). It also checks that every candidate ends the window in the same state.
 
-Candidates vary what the per-day schedule leaves open:
-  launch       per-day kernels, or one cooperative kernel for the whole run;
-  group_herds  how many of the largest herds of a large one-lane-per-node
-               instance get a whole workgroup for their chains (0: default 4,
-               negative: none);
-  small_level  up to which size event levels run several per launch in one
-               workgroup (0: default 512).
+Candidates vary what the per-day schedule leaves open, and only what changes
+the schedule of the workload at hand (candidates_for):
+  launch             per-day kernels, or one cooperative kernel for the whole run;
+  small_level        up to which size event levels run several per launch in
+                     one workgroup (0: default 512);
+  few_chains         how many live chains of a wavefront may be walked one after
+                     another by the whole wavefront (0: default 4, negative: never);
+one lane per node (one trajectory per instance):
+  group_herds        how many of the largest herds of a large instance get a
+                     whole workgroup for their chains (0: default 4, negative: none);
+  group_min_attempts how many attempts a chain must still expect in the day for
+                     the workgroup to walk it (0: default 4096);
+replicate tiles (several replicates per instance):
+  tile_nodes         nodes per tile of 64 replicate lanes (0: default 128), i.e.
+                     tile_nodes / 4 nodes per wavefront;
+  heavy_herds        how many of the largest herds get a wavefront per (herd,
+                     replicate) chain (0: default 32, negative: none).
 """
 from __future__ import annotations
 
@@ -26,14 +36,38 @@ import numpy as np
 
 from .sim import LAUNCH_KERNELS, LAUNCH_PERSISTENT, Simulator
 
-CANDIDATES = (
-    dict(launch=LAUNCH_KERNELS),
-    dict(launch=LAUNCH_KERNELS, group_herds=-1),
-    dict(launch=LAUNCH_KERNELS, group_herds=8),
-    dict(launch=LAUNCH_KERNELS, small_level=128),
-    dict(launch=LAUNCH_KERNELS, small_level=4096),
+LANE_CANDIDATES = (
+    dict(),
+    dict(group_herds=-1),
+    dict(group_herds=8),
+    dict(group_min_attempts=1024),
+    dict(group_min_attempts=16384),
+    dict(small_level=128),
+    dict(small_level=4096),
+    dict(few_chains=1),
+    dict(few_chains=8),
     dict(launch=LAUNCH_PERSISTENT),
 )
+TILE_CANDIDATES = (
+    dict(),
+    dict(tile_nodes=64),
+    dict(tile_nodes=256),
+    dict(heavy_herds=-1),
+    dict(heavy_herds=16),
+    dict(heavy_herds=64),
+    dict(few_chains=1),
+    dict(few_chains=-1),
+    dict(small_level=4096),
+    dict(launch=LAUNCH_PERSISTENT),
+)
+CANDIDATES = LANE_CANDIDATES
+
+
+def candidates_for(p):
+    """The candidate settings that change the schedule of problem p (or of a
+    list of instances packed in one handle)."""
+    first = p[0] if isinstance(p, (list, tuple)) else p
+    return TILE_CANDIDATES if first.n_rep > 1 else LANE_CANDIDATES
 
 
 @dataclass
@@ -56,12 +90,16 @@ def _sync_time(sim, n_days):
     return time.perf_counter() - t0
 
 
-def autotune(p, *, start_day=None, window=None, candidates=CANDIDATES) -> Tuning:
+def autotune(p, *, start_day=None, window=None, candidates=None, margin=0.03) -> Tuning:
     """Time each candidate's settings over days [start_day, start_day + window)
-    of problem p (a farmnet.Problem) from the state the default settings reach
-    at start_day; return the fastest. Raises if two candidates end the window
-    in different states (they must not)."""
-    D = p.n_days
+    of problem p (a farmnet.Problem, or a list of instances packed in one
+    handle) from the state the default settings reach at start_day; return the
+    fastest (the first candidate, the defaults, unless another beats it by
+    more than `margin`). Raises if two candidates end the window in different
+    states (they must not)."""
+    if candidates is None:
+        candidates = candidates_for(p)
+    D = (p[0] if isinstance(p, (list, tuple)) else p).n_days
     start = D // 2 if start_day is None else int(start_day)
     if not 0 <= start < D:
         raise ValueError("start_day must lie in [0, n_days)")
@@ -74,6 +112,7 @@ def autotune(p, *, start_day=None, window=None, candidates=CANDIDATES) -> Tuning
         u0, v0, day = sim.get_state()
     table, ends = [], []
     for cand in candidates:
+        cand = dict(cand)
         with Simulator(p, **cand) as sim:
             sim.set_state(u0, v0, day)
             _sync_time(sim, win)           # untimed: code objects, caches
@@ -86,5 +125,9 @@ def autotune(p, *, start_day=None, window=None, candidates=CANDIDATES) -> Tuning
     for (cand, _), (u, v, d_end) in zip(table, ends):
         if d_end != ref[2] or not np.array_equal(u, ref[0]) or not np.array_equal(v, ref[1]):
             raise RuntimeError(f"candidate {cand} ended the window in another state")
-    best = min(table, key=lambda row: row[1])[0]
+    # a candidate replaces the first (the defaults) only if it is faster by
+    # more than the margin: closer calls are within the timing noise of a
+    # short window and need not carry over to the whole horizon
+    fastest = min(table, key=lambda row: row[1])
+    best = fastest[0] if fastest[1] < table[0][1] * (1.0 - margin) else table[0][0]
     return Tuning(best=best, table=table, start_day=start, window=win)

@@ -220,8 +220,8 @@ def test_plan_levels_rejects_bad_input():
 
 def test_workspace_covers_every_events_mode():
     p = synth.sise3_network(n_nodes=300, n_days=40, seed=4, age_days=(5, 15), e1_per_node_day=0.5)
-    lv = S.workspace_bytes(p, S.EVENTS_LEVELS)
-    se = S.workspace_bytes(p, S.EVENTS_SERIAL)
+    lv = S.workspace_bytes(p, events_mode=S.EVENTS_LEVELS)
+    se = S.workspace_bytes(p, events_mode=S.EVENTS_SERIAL)
     assert 0 < lv < se
 
 
@@ -266,6 +266,15 @@ def test_device_options_validated_before_device():
     assert S.workspace_bytes(p) > 0
     assert S.workspace_bytes(p, group_herds=17) == 0
     assert S.workspace_bytes(p, small_level=-1) == 0
+    for bad in (16, 48, 1024):
+        assert S.workspace_bytes(p, tile_nodes=bad) == 0
+    for good in (32, 64, 256, 512):
+        assert S.workspace_bytes(p, tile_nodes=good) > 0
+    assert S.workspace_bytes(p, heavy_herds=257) == 0 and S.workspace_bytes(p, heavy_herds=256) > 0
+    assert S.workspace_bytes(p, few_chains=65) == 0 and S.workspace_bytes(p, few_chains=-1) > 0
+    assert S.workspace_bytes(p, group_min_attempts=-1) == 0 and S.workspace_bytes(p, group_min_attempts=100) > 0
+    with pytest.raises(TypeError):
+        S.workspace_bytes(p, tile_width=64)
     s, keep = S._marshal(p)
     for field, value in (("block", 128), ("group_herds", 17), ("small_level", -5), ("launch", 7)):
         o = S.sim_device_opts()
