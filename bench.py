@@ -161,8 +161,27 @@ def batched_leg(P, synth, torch, steps, plain_sample, tune=True):
             times.append(time.perf_counter() - t0)
         print(f"[bench] batched {R} replicates: {(time.perf_counter() - t0) * 1e3:.1f} ms", file=sys.stderr, flush=True)
     trans = int(sim.trajectory()["transitions"].sum())
+    # the tile kernel's launches, timed with HIP events on the launch stream
+    sim.kernel_times(-1)
+    sim.kernel_times(1)
+    sim.set_state(u0, v0, 0)
+    sim.run(0)
+    kt = sim.kernel_times(0)
     sim.close()
     t_batch = sum(times) / len(times)
+    day_ms, day_n = kt["day"]
+    avg_s = day_ms / 1e3 / day_n
+    per_launch = R * base.n_nodes * 2 * (4 * base.n_comp + 8)
+    attempts = trans + R * base.n_nodes * base.n_days   # at most one rejected attempt per node-day
+    ops_per_launch = attempts * OPS_PER_ATTEMPT / day_n
+    roofline = dict(bound="hbm", achieved=round(per_launch / avg_s / 1e9, 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(per_launch / avg_s / 1e9 / HBM_PEAK_GBS, 5), traffic=None, kernel="day (replicate tiles)",
+                    avg_launch_us=round(avg_s * 1e6, 2),
+                    per_unit=f"64 B per replicate-node-day x {R * base.n_nodes} per launch",
+                    alu=dict(achieved=round(ops_per_launch / avg_s / 1e12, 3), peak=round(VALU_PEAK_OPS / 1e12, 2),
+                             unit="T lane-ops/s", frac=round(ops_per_launch / avg_s / VALU_PEAK_OPS, 4),
+                             per_unit=f"{OPS_PER_ATTEMPT} lane-ops per SSA attempt, attempts <= transitions + "
+                                      f"node-days"))
     plain = []
     pick = np.linspace(0, R - 1, plain_sample).astype(int)
     for r in pick:
@@ -187,7 +206,7 @@ def batched_leg(P, synth, torch, steps, plain_sample, tune=True):
         transitions_per_s=round(trans / t_batch, 1),
         plain_replicates_per_s=round(1.0 / t_plain, 3),
         plain_sample=f"{plain_sample} of the {R} trajectories, one handle and one per-day launch sequence each",
-        speedup_vs_plain=round(t_plain / t_batch * R, 2), options=best, tuning=tuning)
+        speedup_vs_plain=round(t_plain / t_batch * R, 2), roofline=roofline, options=best, tuning=tuning)
 
 
 def instances_leg(P, synth, torch, n_inst=64, days=730):
@@ -236,7 +255,7 @@ def instances_leg(P, synth, torch, n_inst=64, days=730):
                 speedup_vs_plain=round(t_plain / t_pack, 2))
 
 
-def serving_leg(P, synth, torch, rate, seconds, budget_gb):
+def serving_leg(P, synth, torch, rate, seconds, budget_gb, slot_lanes=16):
     """Requests over the three resident serving networks (1k, 37k and 250k
     nodes, 1461 days): Poisson arrivals at `rate` per second for `seconds`,
     horizons 365-1461 days, 1-64 replicates with prior-box parameters."""
@@ -248,8 +267,8 @@ def serving_leg(P, synth, torch, rate, seconds, budget_gb):
     print(f"[bench] serving: networks generated in {time.perf_counter() - t0:.0f} s, {len(reqs)} requests",
           file=sys.stderr, flush=True)
     demand = [net.n_nodes for net in nets]  # requests pick networks uniformly
-    slots, nbytes = plan_slots(nets, budget_gb * 2 ** 30, demand)
-    srv = Server(nets, slots, max_ahead=4)
+    slots, nbytes = plan_slots(nets, budget_gb * 2 ** 30, demand, slot_lanes=slot_lanes)
+    srv = Server(nets, slots, max_ahead=4, slot_lanes=slot_lanes)
     last = [time.perf_counter()]
 
     def progress(j, k):
@@ -262,7 +281,7 @@ def serving_leg(P, synth, torch, rate, seconds, budget_gb):
         srv.close()
     out = stats.summary(results)
     work = np.mean([nets[q["net"]].n_nodes * q["horizon"] * q["n_rep"] for q in reqs])
-    out.update(offered_rate=rate, arrival_seconds=seconds, hbm_budget_gb=budget_gb,
+    out.update(offered_rate=rate, arrival_seconds=seconds, hbm_budget_gb=budget_gb, slot_lanes=slot_lanes,
                slot_bytes_gb=[round(b / 2 ** 30, 2) for b in nbytes],
                mean_request_node_days=float(work),
                errors=sum(r.error is not None for r in results))
@@ -363,6 +382,8 @@ def main():
     ap.add_argument("--serving-rate", type=float, default=20.0, help="request arrivals per second")
     ap.add_argument("--serving-seconds", type=float, default=8.0, help="seconds of arrivals")
     ap.add_argument("--serving-budget-gb", type=float, default=96.0, help="HBM budget for the slots")
+    ap.add_argument("--serving-slot-lanes", type=int, default=16, choices=[16, 32, 64],
+                    help="replicate lanes per slot of the serving handles")
     ap.add_argument("--plain-sample", type=int, default=6)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--plan-stats", action="store_true",
@@ -503,7 +524,8 @@ def main():
         batched = batched_leg(P, synth, torch, max(1, min(args.steps, 3)), args.plain_sample, not args.no_tune)
 
     instances = instances_leg(P, synth, torch) if args.instances else None
-    serving = (serving_leg(P, synth, torch, args.serving_rate, args.serving_seconds, args.serving_budget_gb)
+    serving = (serving_leg(P, synth, torch, args.serving_rate, args.serving_seconds, args.serving_budget_gb,
+                           args.serving_slot_lanes)
                if not args.no_serving and args.workload == "sise3-37k" else None)
 
     cpu = None

@@ -151,6 +151,8 @@ typedef struct sim_device_opts {
                               negative = never, at most 64 */
     int32_t group_min_attempts; /* one lane per node with per-day launches: a workgroup walks one herd's chain
                               while it still expects this many attempts in the day: 0 = default (4096) */
+    int32_t slot_lanes;    /* slot handles: replicate lanes per slot, 16, 32 or 64 (0 = 64); n_slots times
+                              slot_lanes must be a multiple of 64 */
 } sim_device_opts;
 
 #define SIM_LAUNCH_KERNELS    0  /* one launch per day phase and per event level (default) */
@@ -255,7 +257,8 @@ int sim_kernel_times(sim_handle *h, int32_t enable, double *ms, int64_t *launche
  * The paper's fitting workload runs many trajectories, with different rate
  * parameters, over one event database (Sec. 4.3). A slot handle keeps one
  * network resident (nodes, initial state, events and their levels) and
- * n_slots slots of 64 replicate lanes each. Every slot runs its own request
+ * n_slots slots of slot_lanes (sim_device_opts; 64 by default) replicate
+ * lanes each. Every slot runs its own request
  * (its replicates, parameters and horizon) from its own day 0, while one
  * sim_slots_step advances all running slots by one day in shared launches:
  * the steps of the method (Alg. 1: SSA, then the day's events, then the phi
@@ -266,11 +269,11 @@ int sim_kernel_times(sim_handle *h, int32_t enable, double *ms, int64_t *launche
  * The network problem's n_rep, rates and replicate ids are not used and
  * n_record must be 0; events_mode must be SIM_EVENTS_LEVELS. All calls on one
  * handle must come from one thread. */
-size_t sim_slots_workspace_bytes(const sim_problem *network, int32_t n_slots);
+size_t sim_slots_workspace_bytes(const sim_problem *network, int32_t n_slots, const sim_device_opts *o);
 int sim_slots_create(const sim_problem *network, int32_t n_slots, const sim_device_opts *o, sim_handle **out);
 
 /* Start a request in a slot that is not running (free, or finished and
- * fetched or abandoned): n_rep in [1, 64] replicates with rate constants
+ * fetched or abandoned): n_rep in [1, slot_lanes] replicates with rate constants
  * coef[n_rep*Nt], shedding rates alpha[n_rep], decay rates beta[n_rep*4] and
  * replicate_id[n_rep] (NULL: 0..n_rep-1), for horizon days in [1, D]. The
  * parameters are copied before the call returns; the slot's lanes are loaded

@@ -247,7 +247,7 @@ struct PairRules {
 };
 
 // The single-chain walk for paired classes (defined below).
-template <int NP>
+template <int NP, bool FED = false>
 __device__ __forceinline__ void pairs_walk_block(const Model &m, Chain<2 * NP, 2 * NP> &c, uint32_t kbase,
                                                  uint32_t node, uint32_t day, uint32_t key0, uint32_t key1,
                                                  unsigned long long *status, int32_t r);
@@ -464,19 +464,51 @@ __device__ __forceinline__ int clock_exact_scan(double clock, const double (&tau
 // Counts are exact integers in binary64 and the rates, running sums, targets
 // and waiting times are the same functions of the same state as in a walk
 // attempt by attempt, so the bits agree.
-template <int NP>
+// With FED, every thread of a workgroup calls it: wavefront 0 walks the chain
+// while wavefront 1 computes the next round's draws (Philox, -log rand, rand)
+// into LDS, one round ahead, with a workgroup barrier per round; the draws do
+// not depend on the state, so the walk is the same.
+template <int NP, bool FED>
 __device__ __forceinline__ void pairs_walk_block(const Model &m, Chain<2 * NP, 2 * NP> &c, uint32_t kbase,
                                                  uint32_t node, uint32_t day, uint32_t key0, uint32_t key1,
                                                  unsigned long long *status, int32_t r) {
     constexpr int NT = 2 * NP;
     __shared__ double sh_tau[kWaves][64];
+    __shared__ double sh_draw[2][2][64];  // fed walk: [buffer][E, U][attempt of the round]
+    __shared__ int sh_go;                 // fed walk: 0 once wavefront 0 has ended the chain
     const uint32_t lane = threadIdx.x & 63u;
     const int wave = threadIdx.x >> 6;
     const unsigned long long below = (1ull << lane) - 1ull;
-    for (;;) {
-        const Word4 o = philox4x32_10(Word4{kbase + lane, node, day, 0u}, key0, key1);
-        const double E = minus_log(unit_open(o.a, o.b));
-        const double U = unit_open(o.c, o.d);
+    [[maybe_unused]] int rnd = 0;
+    if constexpr (FED) {
+        auto produce = [&](uint32_t kb, int b) {
+            const Word4 o = philox4x32_10(Word4{kb + lane, node, day, 0u}, key0, key1);
+            sh_draw[b][0][lane] = minus_log(unit_open(o.a, o.b));
+            sh_draw[b][1][lane] = unit_open(o.c, o.d);
+        };
+        if (wave == 1) produce(kbase, 0);
+        if (threadIdx.x == 0) sh_go = 1;
+        __syncthreads();
+        if (wave != 0) {
+            // the producer (and two idle wavefronts): one barrier per round of
+            // wavefront 0, which clears sh_go before the barrier of its last
+            for (;; ++rnd) {
+                if (wave == 1) produce(kbase + 64u * (uint32_t)(rnd + 1), (rnd + 1) & 1);
+                __syncthreads();
+                if (!sh_go) return;
+            }
+        }
+    }
+    for (;; ++rnd) {
+        double E, U;
+        if constexpr (FED) {
+            E = sh_draw[rnd & 1][0][lane];
+            U = sh_draw[rnd & 1][1][lane];
+        } else {
+            const Word4 o = philox4x32_10(Word4{kbase + lane, node, day, 0u}, key0, key1);
+            E = minus_log(unit_open(o.a, o.b));
+            U = unit_open(o.c, o.d);
+        }
         // guess: every attempt sees the round's starting state
         int j = 0;
         {
@@ -578,11 +610,13 @@ __device__ __forceinline__ void pairs_walk_block(const Model &m, Chain<2 * NP, 2
         if (A > 0 && !limit) c.clock = clock;
         c.fired = c.fired + A;
         pairs_rates_full<NP>(c);
-        if (limit) {
-            if (lane == 0) atomicMin(status, (STATUS_LIMIT_TAG << 32) | (unsigned long long)(uint32_t)r);
-            return;
+        if (limit && lane == 0) atomicMin(status, (STATUS_LIMIT_TAG << 32) | (unsigned long long)(uint32_t)r);
+        const bool done = limit || A < 64 || !(c.lam > 0.0);
+        if constexpr (FED) {
+            if (done && lane == 0) sh_go = 0;
+            __syncthreads();  // the producer's next round is in LDS; with sh_go = 0 the others leave
         }
-        if (A < 64 || !(c.lam > 0.0)) return;
+        if (done) return;
         kbase = kbase + 64;
     }
 }
@@ -775,13 +809,16 @@ __device__ __forceinline__ void chain_uniform(const Model &m, typename Rules::St
 // live lane then walks its own in order. With all 64 lanes live each lane
 // draws its own block; with one chain left, or at most `few` of which one
 // still expects many attempts, the whole wavefront walks them one after
-// another (pairs_walk_block). Every lane of the wavefront must call this.
+// another (pairs_walk_block). Node, day and key are each lane's own (lanes of
+// a slot handle may be at different days). Every lane of the wavefront must
+// call this.
 template <class Rules>
 __device__ __forceinline__ void run_chains(const Model &m, typename Rules::State &c, bool live, uint32_t node,
                                            uint32_t day, uint32_t key0, uint32_t key1,
                                            unsigned long long *status, int32_t r, uint32_t few_chains) {
     __shared__ double sh_e[kWaves][64], sh_u[kWaves][64];
     __shared__ uint32_t sh_node[kWaves][64], sh_key[kWaves][64], sh_seed[kWaves][64], sh_k[kWaves][64];
+    __shared__ uint32_t sh_day[kWaves][64];
     const int wave = threadIdx.x >> 6;
     const uint32_t lane = threadIdx.x & 63u;
     uint32_t kbase = 0;  // next attempt index of this lane's chain
@@ -816,13 +853,18 @@ __device__ __forceinline__ void run_chains(const Model &m, typename Rules::State
             u.fired = __builtin_amdgcn_readlane(c.fired, h);
             const uint32_t kb = (uint32_t)__builtin_amdgcn_readlane((int)kbase, h);
             const uint32_t nh = (uint32_t)__builtin_amdgcn_readlane((int)node, h);
+            const uint32_t dh = (uint32_t)__builtin_amdgcn_readlane((int)day, h);
+            const uint64_t st = (uint64_t)status;
+            unsigned long long *sth = (unsigned long long *)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane(
+                                                                  (int)(uint32_t)(st >> 32), h) << 32) |
+                                                              (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)st, h));
             const uint32_t k0 = (uint32_t)__builtin_amdgcn_readlane((int)key0, h);
             const uint32_t k1 = (uint32_t)__builtin_amdgcn_readlane((int)key1, h);
             const int32_t rh = __builtin_amdgcn_readlane(r, h);
             if constexpr (Rules::kPairs > 0) {
-                pairs_walk_block<Rules::kPairs>(m, u, kb, nh, day, k0, k1, status, rh);
+                pairs_walk_block<Rules::kPairs>(m, u, kb, nh, dh, k0, k1, sth, rh);
             } else {
-                chain_uniform<Rules>(m, u, kb, nh, day, k0, k1, status, rh);
+                chain_uniform<Rules>(m, u, kb, nh, dh, k0, k1, sth, rh);
             }
             if ((int)lane == h) c = u;
         }
@@ -831,6 +873,7 @@ __device__ __forceinline__ void run_chains(const Model &m, typename Rules::State
         const uint32_t rank = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
         if (live) {
             sh_node[wave][rank] = node;
+            sh_day[wave][rank] = day;
             sh_key[wave][rank] = key1;
             sh_seed[wave][rank] = key0;
             sh_k[wave][rank] = kbase;
@@ -840,7 +883,7 @@ __device__ __forceinline__ void run_chains(const Model &m, typename Rules::State
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         if (lane < nlive * per) {
             const uint32_t ch = lane % nlive, t = lane / nlive;
-            const Word4 o = philox4x32_10(Word4{sh_k[wave][ch] + t, sh_node[wave][ch], day, 0u},
+            const Word4 o = philox4x32_10(Word4{sh_k[wave][ch] + t, sh_node[wave][ch], sh_day[wave][ch], 0u},
                                           sh_seed[wave][ch], sh_key[wave][ch]);
             sh_e[wave][ch * per + t] = minus_log(unit_open(o.a, o.b));
             sh_u[wave][ch * per + t] = unit_open(o.c, o.d);
@@ -1025,11 +1068,11 @@ __device__ void group_chain(const Model &m, typename Rules::State &c, bool live,
         u.fired = 0;
         uint32_t kb = 0;
         // a short chain, or the end of a long one, is walked by wavefront 0
-        // alone (thread 0 is in it)
+        // (thread 0 is in it) while wavefront 1 draws one round ahead
         if (!pairs_walk_group<Rules::kPairs>(u, kb, sh_key[0], day, sh_key[1], sh_key[2], status, (int32_t)sh_key[3],
-                                             min_attempts) &&
-            threadIdx.x < 64)
-            pairs_walk_block<Rules::kPairs>(m, u, kb, sh_key[0], day, sh_key[1], sh_key[2], status, (int32_t)sh_key[3]);
+                                             min_attempts))
+            pairs_walk_block<Rules::kPairs, true>(m, u, kb, sh_key[0], day, sh_key[1], sh_key[2], status,
+                                                  (int32_t)sh_key[3]);
         if (threadIdx.x == 0) c = u;
     }
 }
@@ -1174,7 +1217,7 @@ __device__ __forceinline__ void day_wave(const Model &m, const DevState &s, int6
                                          bool prologue, bool ssa, Tally<Rules::NC> &t, int32_t r_end,
                                          unsigned long long *status, const TileParams *tp = nullptr,
                                          const Hooks &hooks = Hooks{}, int32_t uniform_set = -1,
-                                         bool group_walk = false) {
+                                         bool group_walk = false, bool lane_on = true) {
     constexpr int NC = Rules::NC, NT = Rules::NT;
     const int32_t R = s.R, RL = s.RL;
     const bool in_range = l < s.L;
@@ -1186,7 +1229,8 @@ __device__ __forceinline__ void day_wave(const Model &m, const DevState &s, int6
     for (int c = 0; c < NC; ++c) x[c] = q.x[c];
     double phi = q.phi;
     int32_t nid = q.nid, inst = q.inst;
-    const bool active = r < r_end && nid >= 0;  // padding positions and idle lanes take part in the wavefront steps only
+    // padding positions and idle lanes take part in the wavefront steps only
+    const bool active = lane_on && r < r_end && nid >= 0;
     if (!active) {
         inst = 0;
         phi = 0.0;
@@ -1237,7 +1281,10 @@ __device__ __forceinline__ void day_wave(const Model &m, const DevState &s, int6
         if (__double_as_longlong(phi) != __double_as_longlong(phi_in)) s.phi[l] = phi;
     }
     hooks.after_prologue();
-    if (!ssa) return;
+    // d, prologue and ssa may differ between the lanes of a slot handle's
+    // wavefront: a lane without the SSA today takes part with no live chain
+    if (__ballot(ssa) == 0ull) return;
+    const bool walks = active && ssa;
     typename Rules::State ch;
     const int lane_t = threadIdx.x & 63;
     const uint32_t key0 = active ? (tp ? tp->key0[lane_t] : s.seed[inst]) : 0u;
@@ -1254,18 +1301,18 @@ __device__ __forceinline__ void day_wave(const Model &m, const DevState &s, int6
     ch.fired = 0;
     Rules::rates(m, ch);
     if (group_walk)
-        group_chain<Rules>(m, ch, active, node, (uint32_t)d, key0, key1, status, set, s.few_chains,
+        group_chain<Rules>(m, ch, walks, node, (uint32_t)d, key0, key1, status, set, s.few_chains,
                            s.group_min_attempts);
     else
-        run_chains<Rules>(m, ch, active, node, (uint32_t)d, key0, key1, status, set, s.few_chains);
+        run_chains<Rules>(m, ch, walks, node, (uint32_t)d, key0, key1, status, set, s.few_chains);
     t.trans += ch.fired;
     t.most = max(t.most, (int32_t)ch.fired);
-    if (hooks.after_ssa(ch, active) && active && ch.fired) {
+    if (hooks.after_ssa(ch, walks) && walks && ch.fired) {
 #pragma unroll
         for (int c = 0; c < NC; ++c)
             if (comp_on<NC>(m, c)) s.u[(int64_t)c * s.L + l] = (int32_t)ch.xd[c];
     }
-    if (active && m.phi_pre) {
+    if (walks && m.phi_pre) {
         // eq:numstep5 as written: phi from the state after the SSA, before the events
         int32_t y[NC];
 #pragma unroll
@@ -1494,15 +1541,14 @@ constexpr int kHeavyBlocks = 64 / kWaves;
 
 template <class Rules>
 __device__ __forceinline__ void heavy_chain(const Model &m, const DevState &s, const DevEvents &ev, int64_t hb,
-                                            int32_t d, bool prologue, bool ssa, int32_t r_end,
+                                            int32_t r, int32_t d, bool prologue, bool ssa, bool on,
                                             unsigned long long *status) {
     constexpr int NC = Rules::NC;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63;
     const int32_t pos = s.heavy_pos[hb / kHeavyBlocks];
-    const int32_t r = (int32_t)blockIdx.y * 64 + (int32_t)(hb % kHeavyBlocks) * kWaves + wave;
+    if (!on) return;  // the same in every lane of the wavefront
     Tally<NC> t{};
-    day_wave<Rules>(m, s, lane == 0 ? (int64_t)pos * s.RL + r : s.L, d, prologue, ssa, t, r_end, status);
-    if (r >= r_end) return;
+    day_wave<Rules>(m, s, lane == 0 ? (int64_t)pos * s.RL + r : s.L, d, prologue, ssa, t, s.RL, status);
     const int32_t inst = s.inst[pos];
     const int64_t S = (int64_t)s.n_inst * s.R;
     const int64_t set = (int64_t)inst * s.R + r;
@@ -1535,36 +1581,71 @@ __device__ __forceinline__ void heavy_chain(const Model &m, const DevState &s, c
         if (ev.node[ev.task_off[tk]] == pos) event_task<NC>(m, s, ev, tk, r, d, status);
 }
 
-template <class Rules>
+// A lane r of a slot handle: its slot (slot_lanes lanes each), whether the
+// slot runs at handle step d, the slot's own day and its error word. A slot
+// whose request failed stops.
+struct SlotLane {
+    int32_t day, n_live;
+    bool on, prologue, ssa;
+    unsigned long long *status;
+};
+
+__device__ __forceinline__ SlotLane slot_lane(const DevState &s, int32_t d, int32_t r) {
+    const int32_t slot = r / s.slot_lanes;
+    const SlotInfo si = s.slots[slot];
+    SlotLane q;
+    q.day = d - si.t0;
+    q.n_live = si.n_rep;
+    q.status = s.status + slot;
+    q.on = si.t0 >= 0 && q.day >= 0 && q.day <= si.horizon && r - slot * s.slot_lanes < si.n_rep &&
+           *q.status == STATUS_OK;
+    q.prologue = q.on && q.day > 0;
+    q.ssa = q.on && q.day < si.horizon;
+    return q;
+}
+
+// With SLOTS (a slot handle), lane r belongs to slot r / slot_lanes, which runs
+// its own request from its own day 0: every lane takes its day, its phases
+// and its error word from its slot, and a failed slot stops without stopping
+// the others.
+template <class Rules, bool SLOTS>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Rules::kTileWaves, 8))) void k_day_tile(
-    Model m, DevState s, DevEvents ev, int32_t d,
-                                                     int32_t prologue, int32_t ssa) {
+    Model m, DevState s, DevEvents ev, int32_t d, int32_t prologue, int32_t ssa) {
     constexpr int NC = Rules::NC;
-    int32_t r_end = s.R;
-    unsigned long long *status = s.status;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t nx = s.Np / s.tile_nodes;
     if (s.n_heavy && blockIdx.x < nx && s.unit_heavy[blockIdx.x]) return;  // uniform over the workgroup
-    if (s.slots) {
-        const SlotInfo si = s.slots[blockIdx.y];
-        const int32_t ds = d - si.t0;
-        if (si.t0 < 0 || ds < 0 || ds > si.horizon) return;  // uniform over the workgroup
-        d = ds;
-        prologue = ds > 0;
-        ssa = ds < si.horizon;
-        r_end = (int32_t)blockIdx.y * 64 + si.n_rep;
-        status += blockIdx.y;
+    if constexpr (!SLOTS) {
+        if (!block_ok(s.status)) return;
     }
-    if (!block_ok(status)) return;
     if (blockIdx.x >= nx) {
-        heavy_chain<Rules>(m, s, ev, blockIdx.x - nx, d, prologue != 0, ssa != 0, r_end, status);
+        const int64_t hb = blockIdx.x - nx;
+        const int32_t rh = (int32_t)blockIdx.y * 64 + (int32_t)(hb % kHeavyBlocks) * kWaves + wave;
+        if constexpr (SLOTS) {
+            const SlotLane q = slot_lane(s, d, rh);
+            heavy_chain<Rules>(m, s, ev, hb, rh, q.day, q.prologue, q.ssa, q.on, q.status);
+        } else {
+            heavy_chain<Rules>(m, s, ev, hb, rh, d, prologue != 0, ssa != 0, rh < s.R, s.status);
+        }
         return;
     }
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t pos0 = (int64_t)blockIdx.x * s.tile_nodes;
     const int32_t r = (int32_t)blockIdx.y * 64 + lane;
+    bool on = r < s.R, pro = prologue != 0, walk = ssa != 0;
+    int32_t day = d;
+    unsigned long long *status = s.status;
+    if constexpr (SLOTS) {
+        const SlotLane q = slot_lane(s, d, r);
+        on = q.on;
+        pro = q.prologue;
+        walk = q.ssa;
+        day = q.day;
+        status = q.status;
+        if (!__syncthreads_or(on ? 1 : 0)) return;  // no lane of the column runs
+    }
     __shared__ double sh_coef[Rules::NT][64], sh_alpha[64], sh_beta[4][64];
     __shared__ uint32_t sh_k0[64], sh_k1[64];
-    if (wave == 0 && r < r_end) {
+    if (wave == 0 && on) {
         const int32_t inst = s.inst[pos0];  // every position of a tile belongs to one instance
         const int64_t set = (int64_t)inst * s.R + r;
 #pragma unroll
@@ -1581,13 +1662,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Rules::k
     for (int j = wave; j < s.tile_nodes; j += kWaves) {
         const int64_t pos = pos0 + j;
         if (pos >= s.Np) break;
-        day_wave<Rules>(m, s, pos * s.RL + r, d, prologue != 0, ssa != 0, t, r_end, status, &tp);
+        day_wave<Rules>(m, s, pos * s.RL + r, day, pro, walk, t, s.RL, status, &tp, NoHooks{}, -1, false, on);
     }
     // instances are padded to whole tiles: one instance per workgroup
-    flush_tile<NC>(m, s, t, r < r_end ? s.inst[pos0] * s.R + r : -1, prologue ? d - 1 : -1, ssa ? d : -1,
+    flush_tile<NC>(m, s, t, on ? s.inst[pos0] * s.R + r : -1, pro ? day - 1 : -1, walk ? day : -1,
                    s.n_regions ? s.pos_region[pos0] : -1);
-    if (ssa)
-        private_tasks<NC>(m, s, ev, d, blockIdx.x, s.Np / s.tile_nodes, (int32_t)blockIdx.y * 64, 64, r_end, status);
+    if constexpr (SLOTS) {
+        // each slot of the column at its own day (flush_tile's barriers publish the SSA results)
+        for (int32_t g = 0; g < 64 / s.slot_lanes; ++g) {
+            const int32_t r0 = (int32_t)blockIdx.y * 64 + g * s.slot_lanes;
+            const SlotLane q = slot_lane(s, d, r0);  // the same in every thread
+            if (q.ssa)
+                private_tasks<NC>(m, s, ev, q.day, blockIdx.x, nx, r0, s.slot_lanes, r0 + q.n_live, q.status);
+        }
+    } else {
+        if (ssa) private_tasks<NC>(m, s, ev, d, blockIdx.x, nx, (int32_t)blockIdx.y * 64, 64, s.R, s.status);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1959,14 +2049,15 @@ __global__ __launch_bounds__(kEvBlock) void k_slot_events(Model m, DevState s, D
     if (si.t0 < 0 || d < 0 || d >= si.horizon) return;  // uniform over the workgroup
     unsigned long long *status = s.status + blockIdx.y;
     if (!block_ok(status)) return;
+    const int32_t W = s.slot_lanes;
     const int32_t lv0 = ev.lvl_ptr[d], lv_day_end = ev.lvl_ptr[d + 1];
     const int64_t stride = (int64_t)gridDim.x * kEvBlock;
     for (int32_t kk = k; kk < k_end && lv0 + kk < lv_day_end; ++kk) {
         const int64_t begin = ev.lvl_off[lv0 + kk], end = ev.lvl_off[lv0 + kk + 1];
-        const int64_t count = (end - begin) * 64;
+        const int64_t count = (end - begin) * W;
         for (int64_t t = (int64_t)blockIdx.x * kEvBlock + threadIdx.x; t < count; t += stride) {
-            const int32_t rr = (int32_t)(t & 63);
-            if (rr < si.n_rep) event_task<NC>(m, s, ev, begin + (t >> 6), (int32_t)blockIdx.y * 64 + rr, d, status);
+            const int32_t rr = (int32_t)(t % W);
+            if (rr < si.n_rep) event_task<NC>(m, s, ev, begin + t / W, (int32_t)blockIdx.y * W + rr, d, status);
         }
         if (k_end > k + 1) {
             __syncthreads();
@@ -2043,17 +2134,17 @@ __global__ __launch_bounds__(kBlock) void k_slot_init(DevState s, int32_t nc, co
         s.slots[slot] = info;
         s.status[slot] = STATUS_OK;
     }
-    const int64_t S = s.RL;
-    for (int64_t i = t; i < s.Np * 64; i += stride) {
-        const int64_t pos = i >> 6;
-        const int32_t rr = (int32_t)(i & 63);
-        const int64_t l = pos * s.RL + (int64_t)slot * 64 + rr;
+    const int64_t S = s.RL, W = s.slot_lanes;
+    for (int64_t i = t; i < s.Np * W; i += stride) {
+        const int64_t pos = i / W;
+        const int32_t rr = (int32_t)(i % W);
+        const int64_t l = pos * s.RL + (int64_t)slot * W + rr;
         const bool live = rr < info.n_rep;
         for (int c = 0; c < nc; ++c) s.u[(int64_t)c * s.L + l] = live ? u0[(int64_t)c * s.Np + pos] : 0;
         s.phi[l] = live ? v0[pos] : 0.0;
     }
-    for (int64_t i = t; i < (int64_t)s.n_days * 64; i += stride) {
-        const int64_t row = (i >> 6) * S + (int64_t)slot * 64 + (i & 63);
+    for (int64_t i = t; i < (int64_t)s.n_days * W; i += stride) {
+        const int64_t row = (i / W) * S + (int64_t)slot * W + (i % W);
         s.prevalence[row] = 0;
         s.transitions[row] = 0;
         s.max_fired[row] = 0;
@@ -2153,7 +2244,8 @@ __global__ __launch_bounds__(kBlock) void k_persist(Model m, DevState s, DevEven
 template <class Rules>
 struct Kernels {
     static void *day() { return (void *)&k_day<Rules>; }
-    static void *tile() { return (void *)&k_day_tile<Rules>; }
+    static void *tile() { return (void *)&k_day_tile<Rules, false>; }
+    static void *tile_slots() { return (void *)&k_day_tile<Rules, true>; }
     static void *events() { return (void *)&k_events<Rules::NC>; }
     static void *levels() { return (void *)&k_event_levels<Rules::NC>; }
     static void *persist() { return (void *)&k_persist<Rules>; }
@@ -2162,14 +2254,14 @@ struct Kernels {
 };
 
 struct Table {
-    void *day, *events, *persist, *levels, *tile, *slot_events, *event_day;
+    void *day, *events, *persist, *levels, *tile, *slot_events, *event_day, *tile_slots;
 };
 
 template <class Rules>
 Table table() {
     return {Kernels<Rules>::day(),    Kernels<Rules>::events(), Kernels<Rules>::persist(),
             Kernels<Rules>::levels(), Kernels<Rules>::tile(),   Kernels<Rules>::slot_events(),
-            Kernels<Rules>::event_day()};
+            Kernels<Rules>::event_day(), Kernels<Rules>::tile_slots()};
 }
 
 Table pick(const Model &m) {
@@ -2191,7 +2283,7 @@ int launch_day(const Model &m, const DevState &s, const DevEvents &ev, int32_t d
     void *args[] = {&mm, &ss, &ee, &dd, &pro, &sa};
     if (layout == LAYOUT_TILE) {
         const unsigned nx = (unsigned)((s.Np + s.tile_nodes - 1) / s.tile_nodes + (int64_t)s.n_heavy * kHeavyBlocks);
-        return (int)hipLaunchKernel(t.tile, dim3(nx, (unsigned)(s.RL / 64)), dim3(kBlock), args, 0,
+        return (int)hipLaunchKernel(s.slots ? t.tile_slots : t.tile, dim3(nx, (unsigned)(s.RL / 64)), dim3(kBlock), args, 0,
                                     (hipStream_t)stream);
     }
     const unsigned grid = (unsigned)((s.L + kBlock - 1) / kBlock);
@@ -2264,7 +2356,7 @@ int launch_slot_events(const Model &m, const DevState &s, const DevEvents &ev, i
     DevEvents ee = ev;
     int32_t a = step, b = k, c = k_end;
     void *args[] = {&mm, &ss, &ee, &a, &b, &c};
-    return (int)hipLaunchKernel(t.slot_events, dim3(gx, (unsigned)(s.RL / 64)), dim3(kEvBlock), args, 0,
+    return (int)hipLaunchKernel(t.slot_events, dim3(gx, (unsigned)(s.RL / s.slot_lanes)), dim3(kEvBlock), args, 0,
                                 (hipStream_t)stream);
 }
 
@@ -2282,7 +2374,7 @@ int launch_event_day(const Model &m, const DevState &s, const DevEvents &ev, int
 
 int launch_slot_init(const DevState &s, int32_t nc, const int32_t *u0, const double *v0, int32_t slot,
                      const SlotInfo &info, void *stream) {
-    const int64_t work = std::max<int64_t>(s.Np * 64, (int64_t)s.n_days * 64);
+    const int64_t work = std::max<int64_t>(s.Np * s.slot_lanes, (int64_t)s.n_days * s.slot_lanes);
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((work + kBlock - 1) / kBlock, 8192));
     DevState ss = s;
     int32_t n = nc, sl = slot;

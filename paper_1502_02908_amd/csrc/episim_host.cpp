@@ -447,6 +447,7 @@ Layout layout_for(int64_t Np, int64_t n_nodes, int64_t n_inst, int64_t Nc, int64
 struct Packed {
     int32_t n_inst = 0, R = 0, RL = 0, D = 0, Nc = 0, Nt = 0, n_record = 0, layout = 0, n_slots = 0;
     int64_t tile = kTileNodes;  // positions of one replicate tile
+    int32_t slot_lanes = 64;    // replicate lanes of one slot of a slot handle
     int64_t Np = 0, n_nodes = 0, n_events = 0, n_levels = 0;
     std::vector<int32_t> node_id, inst, inst_off, inst_pos0;
     std::vector<uint32_t> seed, repid;
@@ -494,10 +495,13 @@ int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, P
     if (n_slots < 0 || (n_slots > 0 && n != 1)) return *err = "a slot handle holds one network", SIM_EINVAL;
     if (n_slots > 0 && p0->n_record > 0) return *err = "slot handles keep no snapshots (n_record must be 0)", SIM_EINVAL;
     if (n_slots > 0 && p0->n_regions > 0) return *err = "slot handles keep no regional records", SIM_EINVAL;
-    if ((int64_t)n_slots * 64 > 65535 * 64) return *err = "too many slots", SIM_EINVAL;
+    const int32_t W = o && o->slot_lanes > 0 ? o->slot_lanes : 64;
+    if (n_slots > 65535) return *err = "too many slots", SIM_EINVAL;
+    if (((int64_t)n_slots * W) % 64) return *err = "n_slots times slot_lanes must be a multiple of 64", SIM_EINVAL;
     pk->n_inst = n;
     pk->n_slots = n_slots;
-    pk->R = n_slots > 0 ? 64 * n_slots : p0->n_rep;
+    pk->slot_lanes = W;
+    pk->R = n_slots > 0 ? W * n_slots : p0->n_rep;
     pk->D = p0->n_days;
     pk->Nc = p0->n_comp;
     pk->Nt = p0->n_trans;
@@ -795,6 +799,7 @@ struct sim_handle {
         bool fetch_pending = false;
     };
     int32_t n_slots = 0;
+    int32_t slot_lanes = 64;  // replicate lanes per slot
     int32_t step = 0;
     std::vector<Slot> slots;
     std::deque<hipEvent_t> in_flight;  // one event per enqueued step, oldest first
@@ -909,6 +914,8 @@ int check_opts(const sim_device_opts &o, std::string *err) {
     if (o.heavy_herds > kMaxHeavyHerds) return *err = "heavy_herds must be at most 256", SIM_EINVAL;
     if (o.few_chains > 64) return *err = "few_chains must be at most 64", SIM_EINVAL;
     if (o.group_min_attempts < 0) return *err = "group_min_attempts must not be negative", SIM_EINVAL;
+    if (o.slot_lanes != 0 && o.slot_lanes != 16 && o.slot_lanes != 32 && o.slot_lanes != 64)
+        return *err = "slot_lanes must be 0, 16, 32 or 64", SIM_EINVAL;
     return SIM_OK;
 }
 
@@ -1039,6 +1046,8 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
     s.rec_slot = at<int32_t>(h->ws, l.rec_slot);
     s.slots = h->n_slots ? at<SlotInfo>(h->ws, l.slots) : nullptr;
     s.tile_nodes = (int32_t)pk.tile;
+    s.slot_lanes = pk.slot_lanes;
+    h->slot_lanes = pk.slot_lanes;
     s.few_chains = opts.few_chains < 0 ? 0u : (opts.few_chains > 0 ? (uint32_t)opts.few_chains : kFewChains);
     s.group_min_attempts = opts.group_min_attempts > 0 ? (double)opts.group_min_attempts : kGroupMinAttempts;
     s.n_heavy = (int32_t)pk.heavy_pos.size();
@@ -1499,10 +1508,11 @@ void sim_destroy(sim_handle *h) {
     delete h;
 }
 
-size_t sim_slots_workspace_bytes(const sim_problem *network, int32_t n_slots) {
+size_t sim_slots_workspace_bytes(const sim_problem *network, int32_t n_slots, const sim_device_opts *o) {
     std::string err;
     Packed pk;
-    if (n_slots < 1 || build_packed(&network, 1, SIM_EVENTS_LEVELS, &pk, &err, n_slots) != SIM_OK) return 0;
+    if (o && check_opts(*o, &err)) return 0;
+    if (n_slots < 1 || build_packed(&network, 1, SIM_EVENTS_LEVELS, &pk, &err, n_slots, o) != SIM_OK) return 0;
     return layout_of(pk, network).total;
 }
 
@@ -1523,7 +1533,7 @@ int sim_slot_start(sim_handle *h, int32_t slot, int32_t n_rep, int32_t horizon, 
     if (slot < 0 || slot >= h->n_slots) return h->err = fmt("slot %d out of range", slot), SIM_EINVAL;
     sim_handle::Slot &sl = h->slots[slot];
     if (sl.state == SLOT_RUNNING) return h->err = fmt("slot %d is running", slot), SIM_ESTATE;
-    if (n_rep < 1 || n_rep > 64) return h->err = "n_rep must be in [1, 64]", SIM_EINVAL;
+    if (n_rep < 1 || n_rep > h->slot_lanes) return h->err = fmt("n_rep must be in [1, %d]", h->slot_lanes), SIM_EINVAL;
     if (horizon < 1 || horizon > h->D) return h->err = fmt("horizon must be in [1, %d]", h->D), SIM_EINVAL;
     if (!coef || !alpha || !beta) return h->err = "a parameter array is NULL", SIM_EINVAL;
     if (int rc = check_params(h->Nt, n_rep, coef, alpha, beta, &h->err)) return rc;
@@ -1537,7 +1547,7 @@ int sim_slot_start(sim_handle *h, int32_t slot, int32_t n_rep, int32_t horizon, 
     std::memcpy(sa, alpha, sizeof(double) * n_rep);
     std::memcpy(sb, beta, sizeof(double) * n_rep * 4);
     for (int32_t r = 0; r < n_rep; ++r) sr[r] = replicate_id ? replicate_id[r] : (uint32_t)r;
-    const int64_t set0 = (int64_t)slot * 64;
+    const int64_t set0 = (int64_t)slot * h->slot_lanes;
     DevState &s = h->st;
     struct Up {
         void *dst;
@@ -1589,7 +1599,7 @@ int sim_slots_step(sim_handle *h, int32_t *finished, int32_t *n_finished) {
         if (d >= sl.horizon) continue;
         for (int32_t k = 0; k < h->lvl_ptr[d + 1] - h->lvl_ptr[d]; ++k) {
             const int32_t lv = h->lvl_ptr[d] + k;
-            size[k] = std::max(size[k], (h->lvl_off[lv + 1] - h->lvl_off[lv]) * 64);  // tasks x lanes
+            size[k] = std::max(size[k], (h->lvl_off[lv + 1] - h->lvl_off[lv]) * h->slot_lanes);  // tasks x lanes
         }
     }
     hipError_t e = timed(h, SIM_K_DAY, [&] { return launch_day(h->model, h->st, h->ev, T, 1, 1, LAYOUT_TILE, h->stream); });
@@ -1643,7 +1653,8 @@ int sim_slot_fetch(sim_handle *h, int32_t slot, int32_t *prevalence, int64_t *tr
     sim_handle::Slot &sl = h->slots[slot];
     if (sl.state != SLOT_DONE) return h->err = fmt("slot %d has no finished run to fetch", slot), SIM_ESTATE;
     if (sl.fetch_pending) return h->err = fmt("slot %d: the previous fetch has not been collected", slot), SIM_ESTATE;
-    const size_t S = (size_t)h->RL, n = (size_t)sl.n_rep, H = (size_t)sl.horizon, c0 = (size_t)slot * 64, Nc = h->Nc;
+    const size_t S = (size_t)h->RL, n = (size_t)sl.n_rep, H = (size_t)sl.horizon, c0 = (size_t)slot * h->slot_lanes,
+                 Nc = h->Nc;
     const DevState &s = h->st;
     hipError_t e = hipSuccess;
     if (prevalence)
@@ -1677,7 +1688,7 @@ int sim_slot_query(sim_handle *h, int32_t slot) {
     sl.fetch_pending = false;
     const unsigned long long st = *error_word(h, slot);
     if (st == STATUS_OK) return SIM_OK;
-    const long long rep = (long long)((st & 0xffffffffull) % 64);
+    const long long rep = (long long)(st & 0xffffffffull) - (long long)slot * h->slot_lanes;
     if ((st >> 32) == STATUS_LIMIT_TAG) {
         h->err = fmt("slot %d: a node exceeded %d SSA transitions in one day (replicate %lld)", slot, SIM_MAX_FIRED, rep);
         return SIM_ELIMIT;
@@ -1698,7 +1709,7 @@ int sim_slot_state(sim_handle *h, int32_t slot, int32_t *u, double *v) {
     if (sl.n_rep == 0) return h->err = fmt("slot %d never started", slot), SIM_ESTATE;
     int rc = check_device(hipStreamSynchronize(h->stream), &h->err, "synchronize");
     if (rc) return rc;
-    const size_t n = (size_t)sl.n_rep, Np = (size_t)h->Np, c0 = (size_t)slot * 64;
+    const size_t n = (size_t)sl.n_rep, Np = (size_t)h->Np, c0 = (size_t)slot * h->slot_lanes;
     std::vector<int32_t> du((size_t)h->Nc * Np * n);
     std::vector<double> dv(Np * n);
     for (int c = 0; c < h->Nc && !rc; ++c)

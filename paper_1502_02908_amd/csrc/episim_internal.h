@@ -47,8 +47,8 @@ struct Model {
 };
 
 // One slot of a slot handle: the handle step at which the slot's day 0 runs
-// (-1: never started), its replicate count (lanes 64 slot .. 64 slot + n_rep - 1)
-// and its horizon in days.
+// (-1: never started), its replicate count (lanes W slot .. W slot + n_rep - 1
+// for slots of W lanes) and its horizon in days.
 struct SlotInfo {
     int32_t t0, n_rep, horizon, pad;
 };
@@ -80,6 +80,7 @@ struct DevState {
     // replicate tiles: the herds whose every (herd, replicate) chain gets a
     // wavefront of its own, and the units that hold only such herds
     int32_t tile_nodes;         // positions of one replicate tile (a power of two, 32 .. 512)
+    int32_t slot_lanes;         // slot handles: replicate lanes of one slot (16, 32 or 64)
     uint32_t few_chains;        // at most this many live chains of a wavefront are walked one after another
     double group_min_attempts;  // a workgroup walks one chain while it expects this many attempts
     int32_t n_heavy;

@@ -14,9 +14,11 @@ the next step. Networks run on their own streams and overlap on the device.
 
 Admission is bounded by an HBM budget: the budget is split between the
 networks in proportion to the lane-days their requests are expected to need,
-and each network gets as many slots (64 replicate lanes each, with their own
-state, parameters and records) as its share holds. A request waits in its
-network's FIFO queue until a slot is free.
+and each network gets as many slots (slot_lanes replicate lanes each, with
+their own state, parameters and records) as its share holds. A request of
+n replicates takes ceil(n / slot_lanes) slots, each running a contiguous part
+of its replicates; narrow slots waste fewer idle lanes on small requests. A
+request waits in its network's FIFO queue until enough slots are free.
 
 Every result is bit-identical to the same request run alone (sim_create with
 the same network, parameters and replicate ids, run for its horizon): a slot
@@ -72,16 +74,19 @@ class Stats:
                     lane_occupancy=round(self.busy_lanes, 3))
 
 
-def plan_slots(networks, hbm_budget, demand, max_slots=256):
+def plan_slots(networks, hbm_budget, demand, max_slots=None, slot_lanes=64):
     """Slots per network from an HBM byte budget split in proportion to
-    `demand` (expected lane-days per network); at least one slot each."""
+    `demand` (expected lane-days per network); at least one column of 64
+    lanes each, whole columns only."""
+    per_col = 64 // slot_lanes
+    max_slots = 256 * per_col if max_slots is None else max_slots
     per, base = [], []
     for net in networks:
-        one = SlotHandle.workspace_bytes(net, 1)
-        two = SlotHandle.workspace_bytes(net, 2)
+        one = SlotHandle.workspace_bytes(net, per_col, slot_lanes)
+        two = SlotHandle.workspace_bytes(net, 2 * per_col, slot_lanes)
         if one == 0 or two == 0:
             raise ValueError("network rejected by the slot handle")
-        per.append(two - one)
+        per.append((two - one) / per_col)
         base.append(one - (two - one))
     w = np.asarray(demand, float)
     w = w / w.sum()
@@ -89,31 +94,33 @@ def plan_slots(networks, hbm_budget, demand, max_slots=256):
     for j, net in enumerate(networks):
         n = int((hbm_budget * w[j] - base[j]) // per[j])
         # lane indices stay below 2^31: positions (nodes plus padding and the
-        # units of the largest herds) times 64 lanes per slot
-        cap = (2 ** 31 - 1) // (64 * (net.n_nodes + 512))
-        out.append(int(min(max(n, 1), max_slots, cap)))
-    return out, [b + n * p for b, n, p in zip(base, out, per)]
+        # units of the largest herds) times the lanes of all slots
+        cap = (2 ** 31 - 1) // (slot_lanes * (net.n_nodes + 512))
+        n = int(min(max(n, per_col), max_slots, cap))
+        out.append(max(per_col, n // per_col * per_col))
+    return out, [int(b + n * p) for b, n, p in zip(base, out, per)]
 
 
 class Server:
     """Slot handles for the given networks, one stream each."""
 
-    def __init__(self, networks, slots, *, max_ahead=4, device=0):
+    def __init__(self, networks, slots, *, max_ahead=4, device=0, slot_lanes=64):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("the server needs a GPU")
         self.torch = torch
         self.networks = networks
         self.max_ahead = max_ahead
+        self.W = int(slot_lanes)
         self.streams = [torch.cuda.Stream(device=device) for _ in networks]  # default priority
         self.handles = []
         for net, n, st in zip(networks, slots, self.streams):
             with torch.cuda.stream(st):
-                self.handles.append(SlotHandle(net, n, stream=st.cuda_stream, device=device))
+                self.handles.append(SlotHandle(net, n, stream=st.cuda_stream, device=device, slot_lanes=self.W))
         # pinned download buffers, one pair per slot (a slot fetches only after
         # its previous fetch was collected)
-        self.bufs = [[(torch.empty(net.n_days * 64, dtype=torch.int32, pin_memory=True),
-                       torch.empty(net.n_days * 64, dtype=torch.int64, pin_memory=True)) for _ in range(n)]
+        self.bufs = [[(torch.empty(net.n_days * self.W, dtype=torch.int32, pin_memory=True),
+                       torch.empty(net.n_days * self.W, dtype=torch.int64, pin_memory=True)) for _ in range(n)]
                      for net, n in zip(networks, slots)]
 
     def close(self):
@@ -126,22 +133,27 @@ class Server:
         by arrival). With realtime, a request enters its queue once the wall
         clock passes its arrival time; otherwise all are queued at once.
         Returns (results in completion order, Stats)."""
-        J = len(self.handles)
+        J, W = len(self.handles), self.W
         for q in requests:
             if not 1 <= q["n_rep"] <= 64:
                 raise ValueError(f"request {q['rid']}: n_rep must be in [1, 64]")
             if not 1 <= q["horizon"] <= self.networks[q["net"]].n_days:
                 raise ValueError(f"request {q['rid']}: horizon beyond its network")
+            if -(-q["n_rep"] // W) > self.handles[q["net"]].n_slots:
+                raise ValueError(f"request {q['rid']}: more replicates than its network's slots hold")
         queues = [deque() for _ in range(J)]
         free = [deque(range(h.n_slots)) for h in self.handles]
-        running = [dict() for _ in range(J)]     # slot -> (request, admitted)
-        fetching = [dict() for _ in range(J)]    # slot -> (request, admitted)
+        running = [dict() for _ in range(J)]     # slot -> (request, part, admitted)
+        fetching = [dict() for _ in range(J)]    # slot -> (request, part, admitted)
+        parts = {}                               # request id -> {part: (prevalence, transitions, error)}
         stats = Stats(steps=[0] * J, slots=[h.n_slots for h in self.handles])
         results = []
         lanes_used = lanes_total = 0
         order = deque(sorted(requests, key=lambda q: q["arrival"]))
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0
+        errors = {}
+
         def landed(j, slot):
             """Whether the download of slot has landed; a request's own error
             is kept with its result."""
@@ -152,15 +164,24 @@ class Server:
                 return True
             return ok
 
-        errors = {}
-
         def collect(j, slot):
-            q, adm = fetching[j].pop(slot)
+            """A part's records are on the host; the request is done once all
+            its parts are."""
+            q, part, adm = fetching[j].pop(slot)
             H, R = q["horizon"], q["n_rep"]
+            n = min(W, R - part * W)
             pv, tr = self.bufs[j][slot]
-            res = Result(q["rid"], j, R, H, q["arrival"] if realtime else 0.0, adm, now(),
-                         pv[:H * R].numpy().reshape(H, R).copy(), tr[:H * R].numpy().reshape(H, R).copy(),
+            got = parts.setdefault(q["rid"], {})
+            got[part] = (pv[:H * n].numpy().reshape(H, n).copy(), tr[:H * n].numpy().reshape(H, n).copy(),
                          errors.pop((j, slot), None))
+            if len(got) < -(-R // W):
+                return
+            del parts[q["rid"]]
+            ordered = [got[k] for k in range(len(got))]
+            err = next((e for _, _, e in ordered if e), None)
+            res = Result(q["rid"], j, R, H, q["arrival"] if realtime else 0.0, adm, now(),
+                         np.concatenate([a for a, _, _ in ordered], axis=1),
+                         np.concatenate([b for _, b, _ in ordered], axis=1), err)
             results.append(res)
             stats.completed += 1
             stats.node_days += float(self.networks[j].n_nodes) * H * R
@@ -178,17 +199,22 @@ class Server:
                     if landed(j, slot):
                         collect(j, slot)
                         progressed = True
-                # admit queued requests into free slots (a slot still being
-                # downloaded is free: the download is ordered before its reuse)
-                while queues[j] and free[j]:
+                # admit queued requests (first come first served) while their
+                # parts find free slots (a slot still being downloaded is free:
+                # the download is ordered before its reuse)
+                while queues[j] and len(free[j]) >= -(-queues[j][0]["n_rep"] // W):
                     q = queues[j].popleft()
-                    slot = free[j].popleft()
-                    h.start(slot, q["horizon"], q["coef"], q["alpha"], q["beta"], q["replicate_id"])
-                    running[j][slot] = (q, now())
+                    adm = now()
+                    for part in range(-(-q["n_rep"] // W)):
+                        slot = free[j].popleft()
+                        sl = slice(part * W, min(q["n_rep"], (part + 1) * W))
+                        h.start(slot, q["horizon"], q["coef"][sl], q["alpha"][sl], q["beta"][sl],
+                                q["replicate_id"][sl])
+                        running[j][slot] = (q, part, adm)
                     progressed = True
                 if running[j] and h.in_flight() < self.max_ahead:
-                    lanes_used += sum(q["n_rep"] for q, _ in running[j].values())
-                    lanes_total += 64 * h.n_slots
+                    lanes_used += sum(min(W, q["n_rep"] - part * W) for q, part, _ in running[j].values())
+                    lanes_total += W * h.n_slots
                     finished = h.step()
                     stats.steps[j] += 1
                     if on_step is not None:
@@ -198,10 +224,10 @@ class Server:
                         while slot in fetching[j]:
                             if landed(j, slot):
                                 collect(j, slot)
-                        q, adm = running[j].pop(slot)
+                        q, part, adm = running[j].pop(slot)
                         pv, tr = self.bufs[j][slot]
                         h.fetch(slot, pv, tr)
-                        fetching[j][slot] = (q, adm)
+                        fetching[j][slot] = (q, part, adm)
                         free[j].append(slot)
                     progressed = True
             if not progressed:

@@ -51,7 +51,7 @@ class sim_device_opts(C.Structure):
                 ("events_mode", C.c_int32), ("block", C.c_int32), ("launch", C.c_int32),
                 ("group_herds", C.c_int32), ("small_level", C.c_int32),
                 ("tile_nodes", C.c_int32), ("heavy_herds", C.c_int32), ("few_chains", C.c_int32),
-                ("group_min_attempts", C.c_int32)]
+                ("group_min_attempts", C.c_int32), ("slot_lanes", C.c_int32)]
 # device options a handle takes (every setting gives the same results)
 OPTION_NAMES = ("events_mode", "launch", "group_herds", "small_level", "tile_nodes", "heavy_herds",
                 "few_chains", "group_min_attempts")
@@ -82,7 +82,7 @@ SIGNATURES = {
                                    C.POINTER(C.c_void_p)]),
     "sim_workspace_bytes_batch": (C.c_size_t, [C.POINTER(C.POINTER(sim_problem)), C.c_int32,
                                                C.POINTER(sim_device_opts)]),
-    "sim_slots_workspace_bytes": (C.c_size_t, [C.POINTER(sim_problem), C.c_int32]),
+    "sim_slots_workspace_bytes": (C.c_size_t, [C.POINTER(sim_problem), C.c_int32, C.POINTER(sim_device_opts)]),
     "sim_slots_create": (C.c_int, [C.POINTER(sim_problem), C.c_int32, C.POINTER(sim_device_opts),
                                    C.POINTER(C.c_void_p)]),
     "sim_slot_start": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, _f64p, _f64p, _f64p, _u32p]),
@@ -336,26 +336,29 @@ def _ptr(x, t):
 
 
 class SlotHandle:
-    """One resident network with n_slots slots of up to 64 replicates; each
-    slot runs its own request from its own day 0 and one step() advances every
-    running slot by a day in shared launches (include/episim.h, slot handles)."""
+    """One resident network with n_slots slots of slot_lanes (16, 32 or 64)
+    replicate lanes; each slot runs its own request from its own day 0 and
+    one step() advances every running slot by a day in shared launches
+    (include/episim.h, slot handles)."""
 
-    def __init__(self, network, n_slots, *, stream=None, torch_workspace=True, device=0):
+    def __init__(self, network, n_slots, *, stream=None, torch_workspace=True, device=0, slot_lanes=64):
         self.p = network
         self.n_slots, self.Nc, self.Nt, self.D = int(n_slots), network.n_comp, network.n_trans, network.n_days
         self.Nn = network.n_nodes
+        self.slot_lanes = int(slot_lanes)
         self._h = C.c_void_p()
         self._ws = None
         self._keep = {}
         torch = _torch_cuda()
         st, keep = _marshal(network)
         opts = sim_device_opts()
+        opts.slot_lanes = self.slot_lanes
         if torch is not None:
             torch.cuda.set_device(device)
             if stream is None:
                 stream = torch.cuda.current_stream().cuda_stream
             if torch_workspace:
-                nbytes = int(lib().sim_slots_workspace_bytes(C.byref(st), self.n_slots))
+                nbytes = int(lib().sim_slots_workspace_bytes(C.byref(st), self.n_slots, C.byref(opts)))
                 if nbytes == 0:
                     raise SimError(SIM_EINVAL, "network rejected (sim_slots_workspace_bytes returned 0)")
                 self._ws = torch.empty(nbytes, dtype=torch.uint8, device=f"cuda:{device}")
@@ -368,9 +371,11 @@ class SlotHandle:
             raise SimError(rc, lib().sim_last_error(None).decode())
 
     @staticmethod
-    def workspace_bytes(network, n_slots):
+    def workspace_bytes(network, n_slots, slot_lanes=64):
         st, keep = _marshal(network)
-        return int(lib().sim_slots_workspace_bytes(C.byref(st), int(n_slots)))
+        opts = sim_device_opts()
+        opts.slot_lanes = int(slot_lanes)
+        return int(lib().sim_slots_workspace_bytes(C.byref(st), int(n_slots), C.byref(opts)))
 
     def _check(self, rc):
         if rc != SIM_OK:

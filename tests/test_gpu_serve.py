@@ -156,3 +156,62 @@ def test_server_results_equal_alone():
         assert np.array_equal(r.prevalence, ref["prevalence"]), r.rid
         assert np.array_equal(r.transitions, ref["transitions"]), r.rid
         assert r.latency >= 0
+
+
+@pytest.mark.parametrize("W", [16, 32])
+def test_narrow_slots_at_different_days_equal_alone(W):
+    # slots of W lanes share a wavefront column while each runs its own
+    # request from its own day: every lane takes its day from its slot
+    net = synth.sise3_network(n_nodes=1500, n_days=70, seed=25, u=3.0, age_days=(10, 30), shifted_moves=0.3)
+    n_slots = 128 // W
+    reqs = [request(10 + k, 1 + (5 * k) % W, 20 + (9 * k) % 45, 40 + k) for k in range(n_slots + 2)]
+    starts = {k: (3 * k if k < n_slots else None) for k in range(len(reqs))}
+    got, where, step = {}, {}, 0
+    with P.SlotHandle(net, n_slots, slot_lanes=W) as H:
+        pending = list(range(len(reqs)))
+        while len(got) < len(reqs):
+            for k in list(pending):
+                free = [sl for sl in range(n_slots) if sl not in where.values()]
+                if free and (starts[k] is None or starts[k] <= step):
+                    q = reqs[k]
+                    H.start(free[0], q["horizon"], q["coef"], q["alpha"], q["beta"], q["replicate_id"])
+                    where[k] = free[0]
+                    pending.remove(k)
+            for sl in H.step():
+                k = next(k for k, v in where.items() if v == sl)
+                q = reqs[k]
+                pv = np.zeros((q["horizon"], q["n_rep"]), np.int32)
+                tr = np.zeros((q["horizon"], q["n_rep"]), np.int64)
+                to = np.zeros((q["horizon"], q["n_rep"], net.n_comp), np.int64)
+                H.fetch(sl, pv, tr, to)
+                while not H.query(sl):
+                    pass
+                u, v = H.state(sl, q["n_rep"])
+                got[k] = dict(prevalence=pv, transitions=tr, totals=to, u=u, v=v)
+                del where[k]
+            step += 1
+    for k, q in enumerate(reqs):
+        ref = alone(net, q)
+        for key, val in got[k].items():
+            assert np.array_equal(val, ref[key]), (W, k, key)
+    say(f"[serve] {len(reqs)} requests in slots of {W} lanes == alone")
+
+
+def test_server_with_narrow_slots_equals_alone():
+    nets = [synth.sise3_network(n_nodes=700, n_days=60, seed=26, age_days=(10, 30)),
+            synth.sise3_network(n_nodes=2000, n_days=80, seed=27, age_days=(10, 30))]
+    reqs = synth.serving_requests(n_requests=12, rate=400.0, n_networks=2, horizon=(20, 60), seed=8)
+    srv = Server(nets, slots=[8, 4], max_ahead=3, slot_lanes=16)
+    try:
+        results, stats = srv.serve(reqs)
+    finally:
+        srv.close()
+    say(f"[serve] narrow slots: {stats.summary(results)}")
+    assert sorted(r.rid for r in results) == list(range(12))
+    by_id = {q["rid"]: q for q in reqs}
+    for r in results:
+        q = by_id[r.rid]
+        ref = alone(nets[q["net"]], q)
+        assert r.error is None
+        assert np.array_equal(r.prevalence, ref["prevalence"]), r.rid
+        assert np.array_equal(r.transitions, ref["transitions"]), r.rid
