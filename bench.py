@@ -281,9 +281,11 @@ def serving_leg(P, synth, torch, rate, seconds, budget_gb, slot_lanes=16):
         srv.close()
     out = stats.summary(results)
     work = np.mean([nets[q["net"]].n_nodes * q["horizon"] * q["n_rep"] for q in reqs])
+    # the offered load in replicate-node-days per second, against which
+    # node_days_per_s (what the day kernels got through) is the bound
     out.update(offered_rate=rate, arrival_seconds=seconds, hbm_budget_gb=budget_gb, slot_lanes=slot_lanes,
                slot_bytes_gb=[round(b / 2 ** 30, 2) for b in nbytes],
-               mean_request_node_days=float(work),
+               mean_request_node_days=float(work), offered_node_days_per_s=float(work) * rate,
                errors=sum(r.error is not None for r in results))
     return out
 

@@ -1604,8 +1604,9 @@ __device__ __forceinline__ SlotLane slot_lane(const DevState &s, int32_t d, int3
     return q;
 }
 
-// With SLOTS (a slot handle), lane r belongs to slot r / slot_lanes, which runs
-// its own request from its own day 0: every lane takes its day, its phases
+// With SLOTS (a slot handle), grid row y runs the column s.run_cols[y] and
+// lane r belongs to slot r / slot_lanes, which runs its own request from its
+// own day 0: every lane takes its day, its phases
 // and its error word from its slot, and a failed slot stops without stopping
 // the others.
 template <class Rules, bool SLOTS>
@@ -1618,9 +1619,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Rules::k
     if constexpr (!SLOTS) {
         if (!block_ok(s.status)) return;
     }
+    // the column of 64 replicate lanes (a slot handle launches only the
+    // columns that run this step)
+    const int32_t col = SLOTS ? s.run_cols[blockIdx.y] : (int32_t)blockIdx.y;
     if (blockIdx.x >= nx) {
         const int64_t hb = blockIdx.x - nx;
-        const int32_t rh = (int32_t)blockIdx.y * 64 + (int32_t)(hb % kHeavyBlocks) * kWaves + wave;
+        const int32_t rh = col * 64 + (int32_t)(hb % kHeavyBlocks) * kWaves + wave;
         if constexpr (SLOTS) {
             const SlotLane q = slot_lane(s, d, rh);
             heavy_chain<Rules>(m, s, ev, hb, rh, q.day, q.prologue, q.ssa, q.on, q.status);
@@ -1630,7 +1634,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Rules::k
         return;
     }
     const int64_t pos0 = (int64_t)blockIdx.x * s.tile_nodes;
-    const int32_t r = (int32_t)blockIdx.y * 64 + lane;
+    const int32_t r = col * 64 + lane;
     bool on = r < s.R, pro = prologue != 0, walk = ssa != 0;
     int32_t day = d;
     unsigned long long *status = s.status;
@@ -1670,13 +1674,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Rules::k
     if constexpr (SLOTS) {
         // each slot of the column at its own day (flush_tile's barriers publish the SSA results)
         for (int32_t g = 0; g < 64 / s.slot_lanes; ++g) {
-            const int32_t r0 = (int32_t)blockIdx.y * 64 + g * s.slot_lanes;
+            const int32_t r0 = col * 64 + g * s.slot_lanes;
             const SlotLane q = slot_lane(s, d, r0);  // the same in every thread
             if (q.ssa)
                 private_tasks<NC>(m, s, ev, q.day, blockIdx.x, nx, r0, s.slot_lanes, r0 + q.n_live, q.status);
         }
     } else {
-        if (ssa) private_tasks<NC>(m, s, ev, d, blockIdx.x, nx, (int32_t)blockIdx.y * 64, 64, s.R, s.status);
+        if (ssa) private_tasks<NC>(m, s, ev, d, blockIdx.x, nx, col * 64, 64, s.R, s.status);
     }
 }
 
@@ -2038,16 +2042,18 @@ __global__ __launch_bounds__(kEvBlock) void k_event_day(Model m, DevState s, Dev
     event_day_levels<NC>(m, s, ev, a, d, sh);
 }
 
-// Slot handles: level k of each slot's own day, one grid row per slot. With
+// Slot handles: level k of each slot's own day, one grid row per slot of
+// s.run_slots (the slots with a day of events this step). With
 // k_end > k + 1 the grid is one workgroup per slot and runs the levels
 // k .. k_end-1 with a workgroup barrier between them.
 template <int NC>
 __global__ __launch_bounds__(kEvBlock) void k_slot_events(Model m, DevState s, DevEvents ev, int32_t step,
                                                           int32_t k, int32_t k_end) {
-    const SlotInfo si = s.slots[blockIdx.y];
+    const int32_t slot = s.run_slots[blockIdx.y];
+    const SlotInfo si = s.slots[slot];
     const int32_t d = step - si.t0;
     if (si.t0 < 0 || d < 0 || d >= si.horizon) return;  // uniform over the workgroup
-    unsigned long long *status = s.status + blockIdx.y;
+    unsigned long long *status = s.status + slot;
     if (!block_ok(status)) return;
     const int32_t W = s.slot_lanes;
     const int32_t lv0 = ev.lvl_ptr[d], lv_day_end = ev.lvl_ptr[d + 1];
@@ -2057,7 +2063,7 @@ __global__ __launch_bounds__(kEvBlock) void k_slot_events(Model m, DevState s, D
         const int64_t count = (end - begin) * W;
         for (int64_t t = (int64_t)blockIdx.x * kEvBlock + threadIdx.x; t < count; t += stride) {
             const int32_t rr = (int32_t)(t % W);
-            if (rr < si.n_rep) event_task<NC>(m, s, ev, begin + t / W, (int32_t)blockIdx.y * W + rr, d, status);
+            if (rr < si.n_rep) event_task<NC>(m, s, ev, begin + t / W, slot * W + rr, d, status);
         }
         if (k_end > k + 1) {
             __syncthreads();
@@ -2282,9 +2288,9 @@ int launch_day(const Model &m, const DevState &s, const DevEvents &ev, int32_t d
     int32_t dd = d, pro = prologue, sa = ssa;
     void *args[] = {&mm, &ss, &ee, &dd, &pro, &sa};
     if (layout == LAYOUT_TILE) {
+        if (s.slots) return hipErrorInvalidValue;  // a slot handle's day runs through launch_slot_day
         const unsigned nx = (unsigned)((s.Np + s.tile_nodes - 1) / s.tile_nodes + (int64_t)s.n_heavy * kHeavyBlocks);
-        return (int)hipLaunchKernel(s.slots ? t.tile_slots : t.tile, dim3(nx, (unsigned)(s.RL / 64)), dim3(kBlock), args, 0,
-                                    (hipStream_t)stream);
+        return (int)hipLaunchKernel(t.tile, dim3(nx, (unsigned)(s.RL / 64)), dim3(kBlock), args, 0, (hipStream_t)stream);
     }
     const unsigned grid = (unsigned)((s.L + kBlock - 1) / kBlock);
     return (int)hipLaunchKernel(t.day, dim3(grid), dim3(kBlock), args, 0, (hipStream_t)stream);
@@ -2345,9 +2351,24 @@ int launch_persistent(const Model &m, const DevState &s, const DevEvents &ev, in
                                            (hipStream_t)stream);
 }
 
+int launch_slot_day(const Model &m, const DevState &s, const DevEvents &ev, int32_t step, int32_t n_cols,
+                    void *stream) {
+    if (s.L == 0 || n_cols <= 0) return hipSuccess;
+    if (!s.slots || n_cols > s.RL / 64) return hipErrorInvalidValue;
+    const Table t = pick(m);
+    Model mm = m;
+    DevState ss = s;
+    DevEvents ee = ev;
+    int32_t dd = step, pro = 1, sa = 1;
+    void *args[] = {&mm, &ss, &ee, &dd, &pro, &sa};
+    const unsigned nx = (unsigned)((s.Np + s.tile_nodes - 1) / s.tile_nodes + (int64_t)s.n_heavy * kHeavyBlocks);
+    return (int)hipLaunchKernel(t.tile_slots, dim3(nx, (unsigned)n_cols), dim3(kBlock), args, 0, (hipStream_t)stream);
+}
+
 int launch_slot_events(const Model &m, const DevState &s, const DevEvents &ev, int32_t step, int32_t k,
-                       int32_t k_end, int64_t max_count, void *stream) {
-    if (k_end <= k || max_count <= 0) return hipSuccess;
+                       int32_t k_end, int64_t max_count, int32_t n_run, void *stream) {
+    if (k_end <= k || max_count <= 0 || n_run <= 0) return hipSuccess;
+    if (n_run > s.RL / s.slot_lanes) return hipErrorInvalidValue;
     const Table t = pick(m);
     const int64_t want = k_end > k + 1 ? 1 : (max_count + kEvBlock - 1) / kEvBlock;
     const unsigned gx = (unsigned)std::min<int64_t>(want, 4096);
@@ -2356,8 +2377,7 @@ int launch_slot_events(const Model &m, const DevState &s, const DevEvents &ev, i
     DevEvents ee = ev;
     int32_t a = step, b = k, c = k_end;
     void *args[] = {&mm, &ss, &ee, &a, &b, &c};
-    return (int)hipLaunchKernel(t.slot_events, dim3(gx, (unsigned)(s.RL / s.slot_lanes)), dim3(kEvBlock), args, 0,
-                                (hipStream_t)stream);
+    return (int)hipLaunchKernel(t.slot_events, dim3(gx, (unsigned)n_run), dim3(kEvBlock), args, 0, (hipStream_t)stream);
 }
 
 int launch_event_day(const Model &m, const DevState &s, const DevEvents &ev, int32_t d, const EventDayArgs &a,

@@ -372,7 +372,7 @@ int64_t order_nodes(const sim_problem *p, int layout, int64_t tile, int64_t heav
 struct Layout {
     size_t u, phi, node_id, inst, inst_off, seed, coef, alpha, beta, repid, status, ev_g, ev_gm, ev_node,
         ev_dest, ev_n, ev_meta, ev_smap, task_off, priv_off, priv_ev_off, day_slot_off, slot_pos, unit_stage_off, unit_stage, stage, slot_key, lvl_ev_off, ev_slot_src, ev_slot_dst, lvl_off, lvl_ptr, prevalence, transitions, totals, max_fired, snap_u, snap_v, rec_slot, slots,
-        u0, v0, heavy_pos, unit_heavy, unit_group, pos_region, regional, goal_ref, goal_part, total;
+        u0, v0, run, heavy_pos, unit_heavy, unit_group, pos_region, regional, goal_ref, goal_part, total;
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -439,6 +439,8 @@ Layout layout_for(int64_t Np, int64_t n_nodes, int64_t n_inst, int64_t Nc, int64
     l.unit_group = take(n_units);
     l.u0 = take(n_slots ? sizeof(int32_t) * Nc * Np : 0);
     l.v0 = take(n_slots ? sizeof(double) * Np : 0);
+    // slot handles: the step's running slots, then its running columns
+    l.run = take(n_slots ? sizeof(int32_t) * (n_slots + RL / 64) : 0);
     l.total = off;
     return l;
 }
@@ -805,6 +807,12 @@ struct sim_handle {
     std::deque<hipEvent_t> in_flight;  // one event per enqueued step, oldest first
     char *stage = nullptr;              // pinned: per slot, parameters then the error word
     size_t stage_stride = 0;
+    // pinned ring of the steps' run lists (running slots, then running
+    // columns): entry step % kRunRing is rewritten once the upload recorded
+    // in run_up[step % kRunRing] has completed
+    static constexpr int kRunRing = 8;
+    int32_t *run_host = nullptr;
+    hipEvent_t run_up[kRunRing] = {};
 };
 
 namespace {
@@ -890,6 +898,10 @@ int create_slots(sim_handle *h, const sim_problem *p, sim_handle **out) {
     if (!rc && h->L > 0) rc = check_device(hipMemset(h->st.phi, 0, sizeof(double) * h->L), &err, "clear phi");
     h->stage_stride = stage_bytes(h->Nt);
     if (!rc) rc = check_device(hipHostMalloc((void **)&h->stage, h->stage_stride * h->n_slots, hipHostMallocDefault), &err, "pinned staging");
+    const size_t run_len = (size_t)h->n_slots + h->RL / 64;
+    if (!rc) rc = check_device(hipHostMalloc((void **)&h->run_host, sizeof(int32_t) * run_len * sim_handle::kRunRing, hipHostMallocDefault), &err, "pinned run lists");
+    for (int k = 0; k < sim_handle::kRunRing; ++k)
+        if (!rc) rc = check_device(hipEventCreateWithFlags(&h->run_up[k], hipEventDisableTiming), &err, "event");
     h->slots.assign(h->n_slots, sim_handle::Slot{});
     for (auto &sl : h->slots) {
         if (!rc) rc = check_device(hipEventCreateWithFlags(&sl.staged, hipEventDisableTiming), &err, "event");
@@ -1045,6 +1057,8 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
     s.snap_v = at<double>(h->ws, l.snap_v);
     s.rec_slot = at<int32_t>(h->ws, l.rec_slot);
     s.slots = h->n_slots ? at<SlotInfo>(h->ws, l.slots) : nullptr;
+    s.run_slots = h->n_slots ? at<int32_t>(h->ws, l.run) : nullptr;
+    s.run_cols = h->n_slots ? at<int32_t>(h->ws, l.run) + h->n_slots : nullptr;
     s.tile_nodes = (int32_t)pk.tile;
     s.slot_lanes = pk.slot_lanes;
     h->slot_lanes = pk.slot_lanes;
@@ -1504,6 +1518,9 @@ void sim_destroy(sim_handle *h) {
         if (sl.fetched) (void)hipEventDestroy(sl.fetched);
     }
     if (h->stage) (void)hipHostFree(h->stage);
+    for (hipEvent_t e : h->run_up)
+        if (e) (void)hipEventDestroy(e);
+    if (h->run_host) (void)hipHostFree(h->run_host);
     if (h->own_ws && h->ws) (void)hipFree(h->ws);
     delete h;
 }
@@ -1593,16 +1610,33 @@ int sim_slots_step(sim_handle *h, int32_t *finished, int32_t *n_finished) {
     }
     if (!any) return SIM_OK;
     std::vector<int64_t> size(k_max, 0);  // largest (task, lane) count of level k over the slots
-    for (const auto &sl : h->slots) {
+    // the run lists of this step: slots with a day of events, then columns
+    // with a running slot (every running slot has its day's phi update, its
+    // SSA or both), into the next entry of the pinned ring
+    const int32_t n_cols_all = h->RL / 64, per_col = 64 / h->slot_lanes;
+    const size_t run_len = (size_t)h->n_slots + n_cols_all;
+    const int ring = T % sim_handle::kRunRing;
+    int rc = check_device(hipEventSynchronize(h->run_up[ring]), &h->err, "run list upload");
+    if (rc) return rc;
+    int32_t *run = h->run_host + run_len * ring, *cols = run + h->n_slots;
+    int32_t n_run = 0, n_cols = 0;
+    for (int32_t j = 0; j < h->n_slots; ++j) {
+        const auto &sl = h->slots[j];
         if (sl.state != SLOT_RUNNING) continue;
+        if (n_cols == 0 || cols[n_cols - 1] != j / per_col) cols[n_cols++] = j / per_col;
         const int32_t d = T - sl.t0;
         if (d >= sl.horizon) continue;
+        run[n_run++] = j;
         for (int32_t k = 0; k < h->lvl_ptr[d + 1] - h->lvl_ptr[d]; ++k) {
             const int32_t lv = h->lvl_ptr[d] + k;
             size[k] = std::max(size[k], (h->lvl_off[lv + 1] - h->lvl_off[lv]) * h->slot_lanes);  // tasks x lanes
         }
     }
-    hipError_t e = timed(h, SIM_K_DAY, [&] { return launch_day(h->model, h->st, h->ev, T, 1, 1, LAYOUT_TILE, h->stream); });
+    rc = check_device(hipMemcpyAsync(const_cast<int32_t *>(h->st.run_slots), run, sizeof(int32_t) * run_len,
+                                     hipMemcpyHostToDevice, h->stream), &h->err, "run list upload");
+    if (!rc) rc = check_device(hipEventRecord(h->run_up[ring], h->stream), &h->err, "event");
+    if (rc) return rc;
+    hipError_t e = timed(h, SIM_K_DAY, [&] { return launch_slot_day(h->model, h->st, h->ev, T, n_cols, h->stream); });
     if (e != hipSuccess) return h->err = fmt("day kernel: %s", hipGetErrorString(e)), SIM_EDEVICE;
     // big levels get a launch of their own; runs of small ones one workgroup per slot
     int32_t k = 0;
@@ -1612,14 +1646,14 @@ int sim_slots_step(sim_handle *h, int32_t *finished, int32_t *n_finished) {
             while (stop < k_max && size[stop] <= kSlotSmallLevel) ++stop;
         const int32_t a = k;
         e = timed(h, SIM_K_EVENTS, [&] {
-            return launch_slot_events(h->model, h->st, h->ev, T, a, stop, size[a], h->stream);
+            return launch_slot_events(h->model, h->st, h->ev, T, a, stop, size[a], n_run, h->stream);
         });
         if (e != hipSuccess) return h->err = fmt("event kernel: %s", hipGetErrorString(e)), SIM_EDEVICE;
         k = stop;
     }
     hipEvent_t done = take_event(h);
     if (!done) return h->err = "event", SIM_EDEVICE;
-    int rc = check_device(hipEventRecord(done, h->stream), &h->err, "event");
+    rc = check_device(hipEventRecord(done, h->stream), &h->err, "event");
     if (rc) return rc;
     h->in_flight.push_back(done);
     h->step = T + 1;

@@ -75,8 +75,13 @@ struct DevState {
     const double *alpha;        // [sets]
     const double *beta;         // [sets][4]
     const uint32_t *repid;      // [sets] second Philox key word
-    unsigned long long *status; // first infeasible event, or STATUS_OK ([RL / 64] in a slot handle)
-    SlotInfo *slots;            // [RL / 64] slot table of a slot handle, null otherwise
+    unsigned long long *status; // first infeasible event, or STATUS_OK ([RL / slot_lanes] in a slot handle)
+    SlotInfo *slots;            // [RL / slot_lanes] slot table of a slot handle, null otherwise
+    // slot handles, rewritten before every step: the slots with a day of events
+    // to run and the 64-lane columns with a lane that runs, each ascending; the
+    // step's launches cover only these (grid y = their count)
+    const int32_t *run_slots;   // [RL / slot_lanes]
+    const int32_t *run_cols;    // [RL / 64]
     // replicate tiles: the herds whose every (herd, replicate) chain gets a
     // wavefront of its own, and the units that hold only such herds
     int32_t tile_nodes;         // positions of one replicate tile (a power of two, 32 .. 512)
@@ -166,8 +171,12 @@ constexpr int64_t kDaySlotCap = 768;
 constexpr int64_t kDayLevelCap = 64;
 int launch_event_day(const Model &m, const DevState &s, const DevEvents &ev, int32_t d, const EventDayArgs &a,
                      void *stream);
+// A slot handle's step: the day kernel over the n_cols columns of s.run_cols,
+// and levels k .. k_end - 1 of the days of the n_run slots of s.run_slots.
+int launch_slot_day(const Model &m, const DevState &s, const DevEvents &ev, int32_t step, int32_t n_cols,
+                    void *stream);
 int launch_slot_events(const Model &m, const DevState &s, const DevEvents &ev, int32_t step, int32_t k,
-                       int32_t k_end, int64_t max_count, void *stream);
+                       int32_t k_end, int64_t max_count, int32_t n_run, void *stream);
 int launch_goal(const DevState &s, int32_t nc, int64_t s0, int32_t N, const int64_t *ref, int32_t d_begin,
                 int32_t n_days, double *part, void *stream);
 // The day terms part[0 .. n) and part[n .. 2n) added in day order into out[0]

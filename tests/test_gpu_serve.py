@@ -215,3 +215,36 @@ def test_server_with_narrow_slots_equals_alone():
         assert r.error is None
         assert np.array_equal(r.prevalence, ref["prevalence"]), r.rid
         assert np.array_equal(r.transitions, ref["transitions"]), r.rid
+
+
+def test_scattered_slots_with_idle_columns_equal_alone():
+    # a step launches only the columns that hold a running slot and the slots
+    # that have a day of events: running slots far apart, columns idle in
+    # between, starts at different steps and the host many steps ahead of the
+    # device (the run lists' pinned ring wraps)
+    net = synth.sise3_network(n_nodes=1200, n_days=60, seed=28, age_days=(10, 30), shifted_moves=0.2)
+    W, n_slots = 16, 32
+    plan = [(1, 0, request(50, 16, 40, 61)), (14, 2, request(51, 5, 55, 62)), (15, 2, request(52, 11, 30, 63)),
+            (29, 7, request(53, 16, 50, 64)), (30, 7, request(54, 3, 21, 65))]
+    got, step = {}, 0
+    with P.SlotHandle(net, n_slots, slot_lanes=W) as H:
+        while len(got) < len(plan):
+            for slot, t0, q in plan:
+                if t0 == step:
+                    H.start(slot, q["horizon"], q["coef"], q["alpha"], q["beta"], q["replicate_id"])
+            for sl in H.step():
+                slot, t0, q = next(x for x in plan if x[0] == sl)
+                pv = np.zeros((q["horizon"], q["n_rep"]), np.int32)
+                tr = np.zeros((q["horizon"], q["n_rep"]), np.int64)
+                to = np.zeros((q["horizon"], q["n_rep"], net.n_comp), np.int64)
+                H.fetch(sl, pv, tr, to)
+                while not H.query(sl):
+                    pass
+                u, v = H.state(sl, q["n_rep"])
+                got[sl] = dict(prevalence=pv, transitions=tr, totals=to, u=u, v=v)
+            step += 1
+    for slot, t0, q in plan:
+        ref = alone(net, q)
+        for key, val in got[slot].items():
+            assert np.array_equal(val, ref[key]), (slot, key)
+    say(f"[serve] {len(plan)} requests in scattered slots == alone")
