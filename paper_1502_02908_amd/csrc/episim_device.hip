@@ -1649,6 +1649,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Rules::k
     }
     __shared__ double sh_coef[Rules::NT][64], sh_alpha[64], sh_beta[4][64];
     __shared__ uint32_t sh_k0[64], sh_k1[64];
+    __shared__ int32_t sh_next;  // the next position of the tile that no wavefront has taken
+    if (threadIdx.x == 0) sh_next = kWaves;
     if (wave == 0 && on) {
         const int32_t inst = s.inst[pos0];  // every position of a tile belongs to one instance
         const int64_t set = (int64_t)inst * s.R + r;
@@ -1663,10 +1665,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Rules::k
     __syncthreads();
     const TileParams tp{sh_coef, sh_alpha, sh_beta, sh_k0, sh_k1};
     Tally<NC> t{};
-    for (int j = wave; j < s.tile_nodes; j += kWaves) {
+    // positions are taken one at a time as wavefronts come free: a herd with
+    // a long chain holds up only its own wavefront, the others take the
+    // remaining positions (nodes are independent within the day, and the
+    // tallies are integer sums and maxima, so the order changes no result)
+    for (int j = wave; j < s.tile_nodes;) {
         const int64_t pos = pos0 + j;
         if (pos >= s.Np) break;
         day_wave<Rules>(m, s, pos * s.RL + r, day, pro, walk, t, s.RL, status, &tp, NoHooks{}, -1, false, on);
+        int32_t next = 0;
+        if (lane == 0) next = atomicAdd(&sh_next, 1);
+        j = __shfl(next, 0);
     }
     // instances are padded to whole tiles: one instance per workgroup
     flush_tile<NC>(m, s, t, on ? s.inst[pos0] * s.R + r : -1, pro ? day - 1 : -1, walk ? day : -1,
