@@ -140,12 +140,12 @@ typedef struct sim_device_opts {
                               negative = none, at most 16 */
     int32_t small_level;   /* per-day launches: event levels of at most this many (event, replicate) tasks
                               run several per launch in one workgroup: 0 = default (512) */
-    int32_t tile_nodes;    /* replicate tiles (R > 1): node positions per tile of 64 replicate lanes, i.e. four
-                              wavefronts walk tile_nodes / 4 nodes each: 0 = default (128), else a power of two in
+    int32_t tile_nodes;    /* replicate tiles (R > 1): node positions per tile of 64 replicate lanes, which the
+                              tile's four wavefronts take one at a time: 0 = default (128), else a power of two in
                               [32, 512] */
     int32_t heavy_herds;   /* replicate tiles with per-day launches: the largest herds per instance (at most one per
                               64 nodes) whose every (herd, replicate) chain gets a wavefront of its own: 0 = default
-                              (32), negative = none, at most 256 */
+                              (64), negative = none, at most 256 */
     int32_t few_chains;    /* at most this many live chains of a wavefront, one of them still expecting many
                               attempts, are walked one after another by the whole wavefront: 0 = default (4),
                               negative = never, at most 64 */

@@ -1615,15 +1615,25 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Rules::k
     constexpr int NC = Rules::NC;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t nx = s.Np / s.tile_nodes;
-    if (s.n_heavy && blockIdx.x < nx && s.unit_heavy[blockIdx.x]) return;  // uniform over the workgroup
+    // Dispatch order (workgroups start in linear order): the tiles of every
+    // column first, then the heavy-herd chains, largest herd first with all
+    // its columns, so that the short chains of the smaller heavy herds fill
+    // the compute units that the last tiles leave free. bx is the tile (or
+    // nx + heavy block) and by the grid row of the workgroup.
+    const int64_t lin = (int64_t)blockIdx.x + (int64_t)gridDim.x * blockIdx.y;
+    const int64_t n_tiles = nx * gridDim.y;
+    const bool heavy = lin >= n_tiles;
+    const int64_t bx = heavy ? nx + (lin - n_tiles) / gridDim.y : lin % nx;
+    const int64_t by = heavy ? (lin - n_tiles) % gridDim.y : lin / nx;
+    if (s.n_heavy && bx < nx && s.unit_heavy[bx]) return;  // uniform over the workgroup
     if constexpr (!SLOTS) {
         if (!block_ok(s.status)) return;
     }
     // the column of 64 replicate lanes (a slot handle launches only the
     // columns that run this step)
-    const int32_t col = SLOTS ? s.run_cols[blockIdx.y] : (int32_t)blockIdx.y;
-    if (blockIdx.x >= nx) {
-        const int64_t hb = blockIdx.x - nx;
+    const int32_t col = SLOTS ? s.run_cols[by] : (int32_t)by;
+    if (heavy) {
+        const int64_t hb = bx - nx;
         const int32_t rh = col * 64 + (int32_t)(hb % kHeavyBlocks) * kWaves + wave;
         if constexpr (SLOTS) {
             const SlotLane q = slot_lane(s, d, rh);
@@ -1633,7 +1643,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Rules::k
         }
         return;
     }
-    const int64_t pos0 = (int64_t)blockIdx.x * s.tile_nodes;
+    const int64_t pos0 = bx * s.tile_nodes;
     const int32_t r = col * 64 + lane;
     bool on = r < s.R, pro = prologue != 0, walk = ssa != 0;
     int32_t day = d;
@@ -1686,10 +1696,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Rules::k
             const int32_t r0 = col * 64 + g * s.slot_lanes;
             const SlotLane q = slot_lane(s, d, r0);  // the same in every thread
             if (q.ssa)
-                private_tasks<NC>(m, s, ev, q.day, blockIdx.x, nx, r0, s.slot_lanes, r0 + q.n_live, q.status);
+                private_tasks<NC>(m, s, ev, q.day, bx, nx, r0, s.slot_lanes, r0 + q.n_live, q.status);
         }
     } else {
-        if (ssa) private_tasks<NC>(m, s, ev, d, blockIdx.x, nx, col * 64, 64, s.R, s.status);
+        if (ssa) private_tasks<NC>(m, s, ev, d, bx, nx, col * 64, 64, s.R, s.status);
     }
 }
 

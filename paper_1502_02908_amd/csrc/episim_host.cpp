@@ -275,7 +275,7 @@ constexpr int64_t kSoloHerds = 128;
 // kHeavyHerds, and one per 64 nodes) get units of their own whose every
 // (herd, replicate) chain is walked by a wavefront of its own; they are placed
 // first, the remaining positions of their units stay empty.
-constexpr int64_t kHeavyHerds = 32;
+constexpr int64_t kHeavyHerds = 64;
 // With one lane per node and per-day launches, the largest herds of a large
 // instance (kGroupHerds unless the options say otherwise) get a workgroup
 // each: the herd sits at the unit's first position and its chain is walked by

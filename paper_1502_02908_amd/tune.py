@@ -22,10 +22,10 @@ one lane per node (one trajectory per instance):
   group_min_attempts how many attempts a chain must still expect in the day for
                      the workgroup to walk it (0: default 4096);
 replicate tiles (several replicates per instance):
-  tile_nodes         nodes per tile of 64 replicate lanes (0: default 128), i.e.
-                     tile_nodes / 4 nodes per wavefront;
+  tile_nodes         nodes per tile of 64 replicate lanes (0: default 128), taken
+                     one at a time by the tile's four wavefronts;
   heavy_herds        how many of the largest herds get a wavefront per (herd,
-                     replicate) chain (0: default 32, negative: none).
+                     replicate) chain (0: default 64, negative: none).
 """
 from __future__ import annotations
 
@@ -53,8 +53,8 @@ TILE_CANDIDATES = (
     dict(tile_nodes=64),
     dict(tile_nodes=256),
     dict(heavy_herds=-1),
-    dict(heavy_herds=16),
-    dict(heavy_herds=64),
+    dict(heavy_herds=32),
+    dict(heavy_herds=128),
     dict(few_chains=1),
     dict(few_chains=-1),
     dict(small_level=4096),

@@ -58,7 +58,7 @@ def test_tile_candidates_agree_and_fastest_is_chosen():
 
 
 @pytest.mark.parametrize("kw", [dict(tile_nodes=32), dict(tile_nodes=512), dict(heavy_herds=-1),
-                                dict(heavy_herds=64, few_chains=-1), dict(few_chains=16)])
+                                dict(heavy_herds=32, few_chains=-1), dict(few_chains=16)])
 def test_tile_options_match_the_oracle(kw):
     base = synth.sise3_network(n_nodes=2500, n_days=40, seed=37, u=5.0, age_days=(10, 30))
     coef, alpha, beta = synth.prior_draws(70, seed=38)
