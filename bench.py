@@ -74,6 +74,34 @@ def counter_traffic(kernel, workload):
     return int(v) if v else None
 
 
+def counter_occupancy(tag):
+    """Occupancy and VALU use of a day kernel from the committed rocprofv3 SQ
+    counter summary (the run named tag), or None if there is none or the
+    kernel source changed since the counters were taken. SQ_WAVE_CYCLES and
+    SQ_ACTIVE_INST_VALU count in units of 4 clocks over the device,
+    GRBM_GUI_ACTIVE the busy clocks of each of the 8 XCDs."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "sq_counters_day_kernels.txt")
+    src = os.path.join(ROOT, "paper_1502_02908_amd", "csrc", "episim_device.hip")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    now = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if f"source_sha256: {now}" not in text:
+        return None
+    for line in text.splitlines():
+        if line.startswith(f"  {tag} ") and ":" in line:
+            v = {k: float(x) for k, x in (kv.split("=") for kv in line.split(":", 1)[1].split())}
+            waves = 4 * v["SQ_WAVE_CYCLES"] / (v["GRBM_GUI_ACTIVE"] / 8) / 1024
+            per_wave = v["SQ_ACTIVE_INST_VALU"] / v["SQ_WAVE_CYCLES"]
+            return dict(resident_waves_per_simd=round(waves, 3),
+                        valu_issue_share_per_simd=round(waves * per_wave, 3),
+                        active_lanes=round(v["SQ_THREAD_CYCLES_VALU"] / (64 * v["SQ_ACTIVE_INST_VALU"]), 3),
+                        wait_share=round(v["SQ_WAIT_ANY"] / v["SQ_WAVE_CYCLES"], 3),
+                        source="profiles/sq_counters_day_kernels.txt")
+    return None
+
+
 # Clock of the MI355X compute units (2.4 GHz peak engine clock) and its VALU
 # width: 256 compute units x 4 SIMDs x 16 lanes issue one lane-operation per
 # cycle each (binary64 add/mul and int32 operations alike), 39.3e12 per
@@ -182,6 +210,11 @@ def batched_leg(P, synth, torch, steps, plain_sample, tune=True):
                              unit="T lane-ops/s", frac=round(ops_per_launch / avg_s / VALU_PEAK_OPS, 4),
                              per_unit=f"{OPS_PER_ATTEMPT} lane-ops per SSA attempt, attempts <= transitions + "
                                       f"node-days"))
+    if R == 256 and base.n_days == 730 and base.n_nodes == 37000:
+        roofline["traffic"] = counter_traffic("k_day_tile", "batched-256x730")
+        roofline["occupancy"] = counter_occupancy("sq_batched")
+    roofline["binding"] = ("issue and latency of the chains' dependent binary64 arithmetic at the resident waves "
+                           "the kernel's 168 VGPRs allow (3 per SIMD), not HBM")
     plain = []
     pick = np.linspace(0, R - 1, plain_sample).astype(int)
     for r in pick:
@@ -510,6 +543,9 @@ def main():
                     frac=round(chain_ms / step_ms, 4), probe=probe["probe"])
     roofline["binding"] = ("serial SSA chain of the day's largest herd (critical_path.frac of the step), "
                            "not HBM")
+    roofline["occupancy"] = counter_occupancy({"sise3-37k": "sq_37k", "sise3-1m": "sq_1m",
+                                               "sise3-37k-u10": "sq_u10", "synthetic-1k": "sq_synthetic"}
+                                              .get(args.workload, ""))
     # SSA-heavy workloads: VALU lane-operations of the attempts against the VALU peak
     alu = None
     if args.workload in ("synthetic-1k", "sise3-37k-u10"):
