@@ -154,7 +154,8 @@ def tuned(p, start_day, window, enabled):
         return {}, None
     from paper_1502_02908_amd.tune import autotune
     t0 = time.perf_counter()
-    t = autotune(p, start_day=start_day, window=window)
+    t = autotune(p, start_day=start_day, window=window,
+                 log=lambda line: print(f"[bench] tuner {line}", file=sys.stderr, flush=True))
     summary = t.summary()
     summary["seconds"] = round(time.perf_counter() - t0, 1)
     print(f"[bench] tuner: {t.best} ({summary['seconds']} s)", file=sys.stderr, flush=True)
@@ -210,7 +211,7 @@ def batched_leg(P, synth, torch, steps, plain_sample, tune=True):
                              unit="T lane-ops/s", frac=round(ops_per_launch / avg_s / VALU_PEAK_OPS, 4),
                              per_unit=f"{OPS_PER_ATTEMPT} lane-ops per SSA attempt, attempts <= transitions + "
                                       f"node-days"))
-    if R == 256 and base.n_days == 730 and base.n_nodes == 37000:
+    if R == 256 and base.n_days == 730 and base.n_nodes == 37000 and not best:
         roofline["traffic"] = counter_traffic("k_day_tile", "batched-256x730")
         roofline["occupancy"] = counter_occupancy("sq_batched")
     roofline["binding"] = ("issue and latency of the chains' dependent binary64 arithmetic at the resident waves "
@@ -412,6 +413,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-replicates leg")
     ap.add_argument("--no-tune", action="store_true", help="default device options instead of the tuner's")
+    ap.add_argument("--options", default="", metavar="JSON",
+                    help="device options of the plain leg, e.g. '{\"tile_nodes\": 4}' (no tuner)")
     ap.add_argument("--instances", action="store_true", help="add the 64-uneven-instances leg (slow to generate)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--serving-rate", type=float, default=20.0, help="request arrivals per second")
@@ -460,8 +463,11 @@ def main():
     p = wl["make"](synth)
     launch = P.LAUNCH_PERSISTENT if args.launch == "persistent" else P.LAUNCH_KERNELS
     print(f"[bench] {wl['desc']}: {p.n_events} events, launch={args.launch}", file=sys.stderr, flush=True)
-    best, tuning = tuned(p, p.n_days // 2, min(30, p.n_days - p.n_days // 2),
-                         not args.no_tune and args.launch == "kernels")
+    if args.options:
+        best, tuning = json.loads(args.options), None
+    else:
+        best, tuning = tuned(p, p.n_days // 2, min(30, p.n_days - p.n_days // 2),
+                             not args.no_tune and args.launch == "kernels")
     opts = dict(launch=launch)
     opts.update(best)
     sim = P.Simulator(p, **opts)
@@ -520,7 +526,9 @@ def main():
         unit_desc = f"{per_nd // 2} B per node (read) per launch"
     avg_s = dom_ms / 1e3 / dom_n
     achieved = bytes_per_launch / avg_s / 1e9
-    traffic = counter_traffic("k_day", args.workload) if dom == "day" else None
+    # committed counters hold for the default options (or, for occupancy, the
+    # options named in the run's tag)
+    traffic = counter_traffic("k_day", args.workload) if dom == "day" and not best else None
     roofline = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 5), traffic=traffic,
                     kernel=dom, avg_launch_us=round(avg_s * 1e6, 3), launches_per_step=dom_n // steps_timed,
@@ -543,9 +551,11 @@ def main():
                     frac=round(chain_ms / step_ms, 4), probe=probe["probe"])
     roofline["binding"] = ("serial SSA chain of the day's largest herd (critical_path.frac of the step), "
                            "not HBM")
-    roofline["occupancy"] = counter_occupancy({"sise3-37k": "sq_37k", "sise3-1m": "sq_1m",
-                                               "sise3-37k-u10": "sq_u10", "synthetic-1k": "sq_synthetic"}
-                                              .get(args.workload, ""))
+    tag = {"sise3-37k": "sq_37k", "sise3-1m": "sq_1m", "sise3-37k-u10": "sq_u10",
+           "synthetic-1k": "sq_synthetic"}.get(args.workload, "")
+    if tag and best:
+        tag += "_" + "_".join(f"{k}{v}" for k, v in sorted(best.items()))
+    roofline["occupancy"] = counter_occupancy(tag) if tag else None
     # SSA-heavy workloads: VALU lane-operations of the attempts against the VALU peak
     alu = None
     if args.workload in ("synthetic-1k", "sise3-37k-u10"):

@@ -142,7 +142,9 @@ typedef struct sim_device_opts {
                               run several per launch in one workgroup: 0 = default (512) */
     int32_t tile_nodes;    /* replicate tiles (R > 1): node positions per tile of 64 replicate lanes, which the
                               tile's four wavefronts take one at a time: 0 = default (128), else a power of two in
-                              [32, 512] */
+                              [4, 512]. With one replicate (R = 1) a nonzero value selects tiles as well: each
+                              wavefront then walks one node's chain at a time with all its lanes (for networks
+                              of few nodes with long chains); 0 keeps one lane per node */
     int32_t heavy_herds;   /* replicate tiles with per-day launches: the largest herds per instance (at most one per
                               64 nodes) whose every (herd, replicate) chain gets a wavefront of its own: 0 = default
                               (64), negative = none, at most 256 */

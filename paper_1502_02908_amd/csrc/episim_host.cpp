@@ -252,11 +252,16 @@ int same_model(const sim_problem *a, const sim_problem *b, std::string *err) {
     return SIM_OK;
 }
 
-int choose_layout(int32_t R) { return R == 1 ? LAYOUT_LANES : LAYOUT_TILE; }
+// One lane per node for a single replicate, unless tile_nodes asks for tiles:
+// then each wavefront of a tile walks one node's chains with all its lanes
+// (networks of few nodes with long chains).
+int choose_layout(int32_t R, int32_t tile_nodes) { return R == 1 && tile_nodes <= 0 ? LAYOUT_LANES : LAYOUT_TILE; }
 
-// Lanes per position: one, or the replicate count rounded up to whole
-// wavefronts (replicate lanes r >= R idle).
-int32_t lane_stride(int32_t R) { return R == 1 ? 1 : (int32_t)(((int64_t)R + 63) / 64 * 64); }
+// Lanes per position: one, or in tiles the replicate count rounded up to
+// whole wavefronts (replicate lanes r >= R idle).
+int32_t lane_stride(int32_t R, int layout) {
+    return layout == LAYOUT_LANES ? 1 : (int32_t)(((int64_t)R + 63) / 64 * 64);
+}
 
 // Nodes of one unit of work and the padding granule of an instance.
 int64_t unit_nodes(int layout, int64_t tile) { return layout == LAYOUT_TILE ? tile : 64; }
@@ -508,8 +513,8 @@ int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, P
     pk->Nc = p0->n_comp;
     pk->Nt = p0->n_trans;
     pk->n_record = p0->n_record;
-    pk->layout = n_slots > 0 ? LAYOUT_TILE : choose_layout(pk->R);
-    pk->RL = lane_stride(pk->R);
+    pk->layout = n_slots > 0 ? LAYOUT_TILE : choose_layout(pk->R, o ? o->tile_nodes : 0);
+    pk->RL = lane_stride(pk->R, pk->layout);
     const int32_t R = pk->R;
     // positions
     std::vector<std::vector<int32_t>> pos_node(n);
@@ -519,7 +524,9 @@ int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, P
     for (int32_t k = 0; k < n; ++k) {
         pk->inst_off[k] = (int32_t)pk->n_nodes;
         pk->inst_pos0[k] = (int32_t)pk->Np;
-        const int64_t heavy = (pk->layout == LAYOUT_TILE && launch == SIM_LAUNCH_KERNELS && heavy_herds >= 0)
+        // (with one replicate a tile's wavefront already walks one herd with all its lanes)
+        const int64_t heavy = (pk->layout == LAYOUT_TILE && launch == SIM_LAUNCH_KERNELS && heavy_herds >= 0 &&
+                               pk->R > 1)
                                   ? std::min<int64_t>(heavy_herds > 0 ? heavy_herds : kHeavyHerds, ps[k]->n_nodes / 64)
                                   : 0;
         const int64_t group = (pk->layout == LAYOUT_LANES && launch == SIM_LAUNCH_KERNELS &&
@@ -921,8 +928,8 @@ int check_opts(const sim_device_opts &o, std::string *err) {
     if (o.block != 0 && o.block != 256) return *err = "block must be 0 or 256", SIM_EINVAL;
     if (o.group_herds > kMaxGroupHerds) return *err = "group_herds must be at most 16", SIM_EINVAL;
     if (o.small_level < 0) return *err = "small_level must not be negative", SIM_EINVAL;
-    if (o.tile_nodes != 0 && (o.tile_nodes < 32 || o.tile_nodes > 512 || (o.tile_nodes & (o.tile_nodes - 1))))
-        return *err = "tile_nodes must be 0 or a power of two in [32, 512]", SIM_EINVAL;
+    if (o.tile_nodes != 0 && (o.tile_nodes < 4 || o.tile_nodes > 512 || (o.tile_nodes & (o.tile_nodes - 1))))
+        return *err = "tile_nodes must be 0 or a power of two in [4, 512]", SIM_EINVAL;
     if (o.heavy_herds > kMaxHeavyHerds) return *err = "heavy_herds must be at most 256", SIM_EINVAL;
     if (o.few_chains > 64) return *err = "few_chains must be at most 64", SIM_EINVAL;
     if (o.group_min_attempts < 0) return *err = "group_min_attempts must not be negative", SIM_EINVAL;

@@ -21,6 +21,8 @@ one lane per node (one trajectory per instance):
                      whole workgroup for their chains (0: default 4, negative: none);
   group_min_attempts how many attempts a chain must still expect in the day for
                      the workgroup to walk it (0: default 4096);
+  tile_nodes         nonzero: tiles of this many nodes instead, each wavefront
+                     walking one node's chain with all its lanes;
 replicate tiles (several replicates per instance):
   tile_nodes         nodes per tile of 64 replicate lanes (0: default 128), taken
                      one at a time by the tile's four wavefronts;
@@ -47,6 +49,8 @@ LANE_CANDIDATES = (
     dict(few_chains=1),
     dict(few_chains=8),
     dict(launch=LAUNCH_PERSISTENT),
+    dict(tile_nodes=4),
+    dict(tile_nodes=16),
 )
 TILE_CANDIDATES = (
     dict(),
@@ -90,13 +94,14 @@ def _sync_time(sim, n_days):
     return time.perf_counter() - t0
 
 
-def autotune(p, *, start_day=None, window=None, candidates=None, margin=0.03) -> Tuning:
+def autotune(p, *, start_day=None, window=None, candidates=None, margin=0.03, log=None) -> Tuning:
     """Time each candidate's settings over days [start_day, start_day + window)
     of problem p (a farmnet.Problem, or a list of instances packed in one
     handle) from the state the default settings reach at start_day; return the
     fastest (the first candidate, the defaults, unless another beats it by
     more than `margin`). Raises if two candidates end the window in different
-    states (they must not)."""
+    states (they must not). log, if given, is called with a line per
+    candidate as it is timed."""
     if candidates is None:
         candidates = candidates_for(p)
     D = (p[0] if isinstance(p, (list, tuple)) else p).n_days
@@ -121,6 +126,8 @@ def autotune(p, *, start_day=None, window=None, candidates=None, margin=0.03) ->
             u, v, d_end = sim.get_state()
         table.append((dict(cand), 1e3 * dt / win))
         ends.append((u, v.view(np.int64), d_end))
+        if log is not None:
+            log(f"candidate {len(table)}/{len(candidates)} {cand}: {1e3 * dt / win:.4f} ms per day")
     ref = ends[0]
     for (cand, _), (u, v, d_end) in zip(table, ends):
         if d_end != ref[2] or not np.array_equal(u, ref[0]) or not np.array_equal(v, ref[1]):

@@ -266,9 +266,9 @@ def test_device_options_validated_before_device():
     assert S.workspace_bytes(p) > 0
     assert S.workspace_bytes(p, group_herds=17) == 0
     assert S.workspace_bytes(p, small_level=-1) == 0
-    for bad in (16, 48, 1024):
+    for bad in (2, 12, 48, 1024):
         assert S.workspace_bytes(p, tile_nodes=bad) == 0
-    for good in (32, 64, 256, 512):
+    for good in (4, 16, 32, 64, 256, 512):
         assert S.workspace_bytes(p, tile_nodes=good) > 0
     assert S.workspace_bytes(p, heavy_herds=257) == 0 and S.workspace_bytes(p, heavy_herds=256) > 0
     assert S.workspace_bytes(p, few_chains=65) == 0 and S.workspace_bytes(p, few_chains=-1) > 0

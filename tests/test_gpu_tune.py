@@ -72,7 +72,8 @@ def test_tile_options_match_the_oracle(kw):
     assert_parity(g, O.run(p, threads=8))
 
 
-@pytest.mark.parametrize("kw", [dict(group_min_attempts=256), dict(few_chains=-1), dict(few_chains=64)])
+@pytest.mark.parametrize("kw", [dict(group_min_attempts=256), dict(few_chains=-1), dict(few_chains=64),
+                                dict(tile_nodes=4), dict(tile_nodes=16)])
 def test_lane_options_match_the_oracle(kw):
     p = synth.sise3_network(n_nodes=9000, n_days=40, seed=39, u=10.0, age_days=(20, 60))
     p.record_days = np.array([39], np.int32)
@@ -81,3 +82,19 @@ def test_lane_options_match_the_oracle(kw):
         g = sim.trajectory()
         g["u"], g["v"], _ = sim.get_state()
     assert_parity(g, O.run(p, threads=8))
+
+
+@pytest.mark.parametrize("tile", [4, 32])
+def test_one_replicate_tiles_on_the_synthetic_model(tile):
+    # Sec. 4.2's SSA-heavy model (S <-> I at rate 1, no events): with one
+    # replicate in tiles every wavefront walks one node's long chain with all
+    # its lanes; records and state against the oracle
+    p = synth.flip_model(n_nodes=200, n_days=12)
+    p.record_days = np.array([5, 11], np.int32)
+    with P.Simulator(p, tile_nodes=tile) as sim:
+        sim.run(0)
+        g = sim.trajectory()
+        g["u"], g["v"], _ = sim.get_state()
+    o = O.run(p, threads=8)
+    assert o["transitions"].sum() > 10 ** 6
+    assert_parity(g, o)
