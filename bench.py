@@ -324,6 +324,45 @@ def serving_leg(P, synth, torch, rate, seconds, budget_gb, slot_lanes=16):
     return out
 
 
+def slot_capacity(P, synth, torch, slot_lanes=16, warm=200, steps=60, budget_gb=96.0):
+    """Throughput of the slot step with every slot of a serving network busy
+    and all slots at one day (from day `warm` on), one network at a time:
+    the device-side bound of the serving leg, and how much of a step's wall
+    time the host leaves the device idle."""
+    import numpy as np
+    from paper_1502_02908_amd.serve import plan_slots
+    nets = synth.serving_networks()
+    slots, _ = plan_slots(nets, budget_gb * 2 ** 30, [net.n_nodes for net in nets], slot_lanes=slot_lanes)
+    out = []
+    for net, n in zip(nets, slots):
+        st = torch.cuda.Stream()  # default priority
+        h = P.SlotHandle(net, n, stream=st.cuda_stream, slot_lanes=slot_lanes)
+        coef, alpha, beta = synth.prior_draws(slot_lanes, seed=9)
+        for k in range(h.n_slots):
+            h.start(k, net.n_days, coef, alpha, beta, np.arange(slot_lanes, dtype=np.uint32) + np.uint32(k * slot_lanes))
+
+        def run(m):
+            for _ in range(m):
+                h.step()
+                while h.in_flight() > 4:
+                    time.sleep(0.0002)
+            st.synchronize()
+        run(warm)
+        h.kernel_times(-1)
+        h.kernel_times(1)
+        t0 = time.perf_counter()
+        run(steps)
+        wall = time.perf_counter() - t0
+        kt = h.kernel_times(0)
+        h.close()
+        busy = sum(a for a, b in kt.values() if b) / 1e3
+        out.append(dict(nodes=net.n_nodes, slots=n, lanes=n * slot_lanes, ms_per_step=round(wall / steps * 1e3, 3),
+                        node_days_per_s=n * slot_lanes * net.n_nodes * steps / wall,
+                        device_busy=round(busy / wall, 3)))
+        print(f"[bench] slot capacity: {out[-1]}", file=sys.stderr, flush=True)
+    return dict(slot_lanes=slot_lanes, from_day=warm, steps=steps, networks=out)
+
+
 def plan_stats(P, synth, workload):
     """Levels per day of the dependency pass (host side of sim_create) and
     the events of each level, as a histogram over the days."""
@@ -423,6 +462,8 @@ def main():
     ap.add_argument("--serving-slot-lanes", type=int, default=16, choices=[16, 32, 64],
                     help="replicate lanes per slot of the serving handles")
     ap.add_argument("--plain-sample", type=int, default=6)
+    ap.add_argument("--slot-capacity", action="store_true",
+                    help="only the slot step's throughput with every slot of each serving network busy")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--plan-stats", action="store_true",
                     help="only print the dependency pass's levels per day and events per level (host only)")
@@ -458,6 +499,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps(dict(calibration="copy", bytes_read=n * 4, bytes_written=n * 4, launches=3)))
+        return
+    if args.slot_capacity:
+        print(json.dumps(dict(slot_capacity=slot_capacity(P, synth, torch, args.serving_slot_lanes))))
         return
     wl = WORKLOADS[args.workload]
     p = wl["make"](synth)
