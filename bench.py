@@ -459,7 +459,7 @@ def main():
     ap.add_argument("--serving-rate", type=float, default=20.0, help="request arrivals per second")
     ap.add_argument("--serving-seconds", type=float, default=8.0, help="seconds of arrivals")
     ap.add_argument("--serving-budget-gb", type=float, default=96.0, help="HBM budget for the slots")
-    ap.add_argument("--serving-slot-lanes", type=int, default=16, choices=[16, 32, 64],
+    ap.add_argument("--serving-slot-lanes", type=int, default=16, choices=[8, 16, 32, 64],
                     help="replicate lanes per slot of the serving handles")
     ap.add_argument("--plain-sample", type=int, default=6)
     ap.add_argument("--slot-capacity", action="store_true",

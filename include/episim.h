@@ -153,7 +153,7 @@ typedef struct sim_device_opts {
                               negative = never, at most 64 */
     int32_t group_min_attempts; /* one lane per node with per-day launches: a workgroup walks one herd's chain
                               while it still expects this many attempts in the day: 0 = default (4096) */
-    int32_t slot_lanes;    /* slot handles: replicate lanes per slot, 16, 32 or 64 (0 = 64); n_slots times
+    int32_t slot_lanes;    /* slot handles: replicate lanes per slot, 8, 16, 32 or 64 (0 = 64); n_slots times
                               slot_lanes must be a multiple of 64 */
 } sim_device_opts;
 

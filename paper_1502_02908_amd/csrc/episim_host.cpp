@@ -933,8 +933,8 @@ int check_opts(const sim_device_opts &o, std::string *err) {
     if (o.heavy_herds > kMaxHeavyHerds) return *err = "heavy_herds must be at most 256", SIM_EINVAL;
     if (o.few_chains > 64) return *err = "few_chains must be at most 64", SIM_EINVAL;
     if (o.group_min_attempts < 0) return *err = "group_min_attempts must not be negative", SIM_EINVAL;
-    if (o.slot_lanes != 0 && o.slot_lanes != 16 && o.slot_lanes != 32 && o.slot_lanes != 64)
-        return *err = "slot_lanes must be 0, 16, 32 or 64", SIM_EINVAL;
+    if (o.slot_lanes != 0 && o.slot_lanes != 8 && o.slot_lanes != 16 && o.slot_lanes != 32 && o.slot_lanes != 64)
+        return *err = "slot_lanes must be 0, 8, 16, 32 or 64", SIM_EINVAL;
     return SIM_OK;
 }
 

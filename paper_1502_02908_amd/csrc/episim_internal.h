@@ -85,7 +85,7 @@ struct DevState {
     // replicate tiles: the herds whose every (herd, replicate) chain gets a
     // wavefront of its own, and the units that hold only such herds
     int32_t tile_nodes;         // positions of one replicate tile (a power of two, 32 .. 512)
-    int32_t slot_lanes;         // slot handles: replicate lanes of one slot (16, 32 or 64)
+    int32_t slot_lanes;         // slot handles: replicate lanes of one slot (8, 16, 32 or 64)
     uint32_t few_chains;        // at most this many live chains of a wavefront are walked one after another
     double group_min_attempts;  // a workgroup walks one chain while it expects this many attempts
     int32_t n_heavy;

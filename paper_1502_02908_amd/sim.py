@@ -336,7 +336,7 @@ def _ptr(x, t):
 
 
 class SlotHandle:
-    """One resident network with n_slots slots of slot_lanes (16, 32 or 64)
+    """One resident network with n_slots slots of slot_lanes (8, 16, 32 or 64)
     replicate lanes; each slot runs its own request from its own day 0 and
     one step() advances every running slot by a day in shared launches
     (include/episim.h, slot handles)."""

@@ -158,7 +158,7 @@ def test_server_results_equal_alone():
         assert r.latency >= 0
 
 
-@pytest.mark.parametrize("W", [16, 32])
+@pytest.mark.parametrize("W", [8, 16, 32])
 def test_narrow_slots_at_different_days_equal_alone(W):
     # slots of W lanes share a wavefront column while each runs its own
     # request from its own day: every lane takes its day from its slot
