@@ -1525,12 +1525,13 @@ __global__ __launch_bounds__(kBlock) void k_day(Model m, DevState s, DevEvents e
     }
 }
 
-// Replicate tiles (replicate lanes in groups of 64): workgroup (x, y) takes
-// positions [x * tile_nodes, (x + 1) * tile_nodes) and replicate lanes
-// [64 y, 64 y + 64); wavefront w walks the positions w, w + 4, ... so a lane
-// always holds the same replicate and its counts add up in registers.
-// In a slot handle, column y is slot y: d is the handle's step, the slot's own
-// day is d - t0, and the slot's lanes past its replicate count are idle.
+// Replicate tiles (replicate lanes in columns of 64): a tile workgroup takes
+// positions [x * tile_nodes, (x + 1) * tile_nodes) and the replicate lanes
+// [64 y, 64 y + 64) of column y; its wavefronts take the positions one at a
+// time, and a lane always holds the same replicate, so its counts add up in
+// registers. In a slot handle the columns are those of the step's run list,
+// each holding 64 / slot_lanes slots: d is the handle's step, a slot's own
+// day is d - t0, and its lanes past its replicate count are idle.
 //
 // Past the regular tiles, workgroups of four wavefronts take the heavy herds:
 // each wavefront one (herd, replicate) chain, walked with the whole wavefront

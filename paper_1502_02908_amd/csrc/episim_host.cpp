@@ -480,8 +480,9 @@ struct Packed {
     std::vector<int32_t> rec_slot;
 };
 
-// n_slots > 0 builds a slot handle of one network: n_slots columns of 64
-// replicate lanes, parameters supplied later slot by slot.
+// n_slots > 0 builds a slot handle of one network: n_slots slots of
+// slot_lanes replicate lanes (64 / slot_lanes to a column of 64), parameters
+// supplied later slot by slot.
 int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, Packed *pk, std::string *err,
                  int32_t n_slots = 0, const sim_device_opts *o = nullptr) {
     const int32_t launch = o ? o->launch : SIM_LAUNCH_KERNELS, group_herds = o ? o->group_herds : 0;

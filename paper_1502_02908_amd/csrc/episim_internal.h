@@ -56,8 +56,8 @@ struct SlotInfo {
 // A handle holds n_inst instances (networks) of one model, each run with the
 // same number R of replicates; "set" = inst * R + r indexes everything that
 // belongs to one trajectory (parameters, replicate id, records). A slot
-// handle holds one network and RL / 64 slots with R = RL sets; each slot runs
-// its own request at its own day.
+// handle holds one network and RL / slot_lanes slots with R = RL sets; each
+// slot runs its own request at its own day.
 struct DevState {
     int32_t *u;                 // [nc][L]
     double *phi;                // [L]
