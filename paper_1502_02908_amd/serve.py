@@ -78,6 +78,16 @@ class Stats:
                     lane_occupancy=round(self.busy_lanes, 3), column_occupancy=round(self.column_lanes, 3))
 
 
+def pick_slot(free, running, per_col):
+    """The free slot (from the set `free`) in the column of 64 lanes that
+    already runs the most slots of `running`, then the lowest column and slot:
+    the parts of small requests share columns, so a step launches fewer."""
+    busy = {}
+    for sl in running:
+        busy[sl // per_col] = busy.get(sl // per_col, 0) + 1
+    return min(free, key=lambda sl: (-busy.get(sl // per_col, 0), sl))
+
+
 def plan_slots(networks, hbm_budget, demand, max_slots=None, slot_lanes=64):
     """Slots per network from an HBM byte budget split in proportion to
     `demand` (expected lane-days per network); at least one column of 64
@@ -156,12 +166,7 @@ class Server:
         lanes_used = lanes_total = col_lanes = 0
 
         def take_slot(j):
-            """A free slot of network j in the column that runs the most
-            slots (then the lowest column and slot)."""
-            busy = {}
-            for sl in running[j]:
-                busy[sl // per_col] = busy.get(sl // per_col, 0) + 1
-            best = min(free[j], key=lambda sl: (-busy.get(sl // per_col, 0), sl))
+            best = pick_slot(free[j], running[j], per_col)
             free[j].discard(best)
             return best
         order = deque(sorted(requests, key=lambda q: q["arrival"]))

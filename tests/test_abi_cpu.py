@@ -291,3 +291,21 @@ def test_tuner_rejects_bad_windows_before_device():
                dict(start_day=5, window=p.n_days)):
         with pytest.raises(ValueError):
             autotune(p, **kw)
+
+
+def test_request_parts_go_to_the_busiest_column():
+    from paper_1502_02908_amd.serve import pick_slot
+    # 16-lane slots: four to a column of 64 lanes
+    assert pick_slot({0, 1, 2, 3, 4, 5, 6, 7}, [], 4) == 0
+    # slot 5 runs: its column (4-7) fills first
+    assert pick_slot({0, 1, 2, 3, 4, 6, 7}, [5], 4) == 4
+    # two columns busy: the one with more running slots wins, then the lowest
+    assert pick_slot({1, 2, 3, 6, 7, 9}, [0, 4, 5, 8], 4) == 6
+    assert pick_slot({1, 6, 9}, [0, 4, 8], 4) == 1
+    # a request's parts in a row fill one column before opening another
+    free, running = set(range(8)), []
+    for _ in range(3):
+        sl = pick_slot(free, running, 4)
+        free.discard(sl)
+        running.append(sl)
+    assert sorted(running) == [0, 1, 2]
