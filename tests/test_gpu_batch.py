@@ -56,12 +56,14 @@ def instances(R=1, n_days=50):
     return out
 
 
-@pytest.mark.parametrize("R,launch", [(1, P.LAUNCH_KERNELS), (1, P.LAUNCH_PERSISTENT), (64, P.LAUNCH_KERNELS),
-                                      (3, P.LAUNCH_KERNELS)])
-def test_packed_instances_match_oracle(R, launch):
+@pytest.mark.parametrize("R,launch,tile", [(1, P.LAUNCH_KERNELS, 0), (1, P.LAUNCH_PERSISTENT, 0),
+                                           (64, P.LAUNCH_KERNELS, 0), (3, P.LAUNCH_KERNELS, 0),
+                                           (1, P.LAUNCH_KERNELS, 8)])
+def test_packed_instances_match_oracle(R, launch, tile):
+    # tile > 0 with R = 1: one-replicate tiles, a wavefront per node
     probs = instances(R)
-    say(f"[batch] pack of {len(probs)} instances R={R} launch={launch}")
-    with P.Simulator(probs, launch=launch) as sim:
+    say(f"[batch] pack of {len(probs)} instances R={R} launch={launch} tile_nodes={tile}")
+    with P.Simulator(probs, launch=launch, tile_nodes=tile) as sim:
         sim.run(0)
         traj = sim.trajectory()
         u, v, day = sim.get_state()
