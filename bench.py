@@ -120,14 +120,22 @@ VALU_PEAK_OPS = 256 * 4 * 16 * CLOCK_GHZ * 1e9
 OPS_PER_ATTEMPT = 98 + 10 + 50 + 10 + 2 + 1 + 12 + 2 + 11
 
 
-def chain_probe(P, synth, torch, half=1000, days=40):
-    """Time per attempt of one long chain walked by a wavefront (the serial
-    critical path of a plain step): the synthetic model of Sec. 4.2 with a
-    single node of S = I = half (lambda = 2 half per day, no events), its day
-    kernel's duration less that of a node with no transitions, over the
-    attempts of a day (transitions + 1)."""
+def chain_probe(P, synth, torch, half=1000, days=40, n_nodes=1):
+    """Time per attempt of one long chain (the serial critical path of a
+    plain step): the synthetic model of Sec. 4.2 with one node of S = I =
+    half (lambda = 2 half per day, no events) among n_nodes - 1 empty ones,
+    its day kernel's duration less that of the same network with no
+    animals, over the attempts of a day (transitions + 1). With one node the
+    chain is walked by a wavefront; from 8192 nodes on, the largest herd has
+    a workgroup as on the farm networks (the block walk fed by a second
+    wavefront, and the workgroup walk while the chain expects 4096 attempts
+    or more)."""
+    import numpy as np
+
     def day_us(S0):
-        p = synth.flip_model(n_nodes=1, S0=S0, I0=S0, n_days=days)
+        p = synth.flip_model(n_nodes=n_nodes, S0=0, I0=0, n_days=days)
+        p.u0 = np.ascontiguousarray(p.u0)
+        p.u0[0] = [S0, S0]
         with P.Simulator(p) as sim:
             sim.run(0)
             sim.sync()
@@ -142,9 +150,10 @@ def chain_probe(P, synth, torch, half=1000, days=40):
     t_big, per_day = day_us(half)
     t_empty, _ = day_us(0)
     us = (t_big - t_empty) / (per_day + 1.0)
+    where = "one node" if n_nodes == 1 else f"one node of {n_nodes}"
     return dict(us_per_attempt=us, cycles_per_attempt=us * 1e3 * CLOCK_GHZ, attempts_per_day=per_day + 1.0,
                 day_kernel_us=t_big, empty_day_kernel_us=t_empty,
-                probe=f"one node of the synthetic S<->I model with S = I = {half}, {days} days")
+                probe=f"{where} of the synthetic S<->I model with S = I = {half}, {days} days")
 
 
 def tuned(p, start_day, window, enabled):
@@ -581,18 +590,30 @@ def main():
                         for k, v in kt.items() if v[1]}
     sim.close()
 
-    # the serial critical path: each day's longest SSA chain, walked attempt
-    # after attempt, at the per-attempt time of a single long chain
-    probe = chain_probe(P, synth, torch)
-    chain_ms = float((most + 1).sum()) * probe["us_per_attempt"] / 1e3
+    # the serial critical path: each day's longest SSA chain at the
+    # per-attempt time of a long chain walked as the day kernel walks the
+    # largest herd (from 8192 nodes with one lane per node: its own workgroup,
+    # the workgroup walk for chains of 4096 expected attempts or more)
+    hub_layout = p.n_nodes >= 8192 and p.n_rep == 1 and not best.get("tile_nodes")
+    if hub_layout:
+        short = chain_probe(P, synth, torch, half=1000, n_nodes=8192)
+        long_ = chain_probe(P, synth, torch, half=10000, days=20, n_nodes=8192)
+        per_day_us = np.where(most + 1 >= 4096, long_["us_per_attempt"], short["us_per_attempt"]) * (most + 1)
+        probes = [short, long_]
+    else:
+        one = chain_probe(P, synth, torch)
+        per_day_us = one["us_per_attempt"] * (most + 1)
+        probes = [one]
+    chain_ms = float(per_day_us.sum()) / 1e3
     step_ms = total / args.steps * 1e3
     critical = dict(longest_chain_attempts_per_step=int((most + 1).sum()),
                     longest_chain_per_day=dict(max=int(most.max()), median=float(np.median(most)),
                                                p99=float(np.percentile(most, 99))),
-                    us_per_attempt=round(probe["us_per_attempt"], 5),
-                    cycles_per_attempt=round(probe["cycles_per_attempt"], 1),
+                    us_per_attempt=[round(q["us_per_attempt"], 5) for q in probes],
+                    cycles_per_attempt=[round(q["cycles_per_attempt"], 1) for q in probes],
                     chain_ms_per_step=round(chain_ms, 3), step_ms=round(step_ms, 3),
-                    frac=round(chain_ms / step_ms, 4), probe=probe["probe"])
+                    frac=round(chain_ms / step_ms, 4), probe=[q["probe"] for q in probes],
+                    rule="longest chains of 4096 attempts or more at the second probe's rate" if hub_layout else "")
     roofline["binding"] = ("serial SSA chain of the day's largest herd (critical_path.frac of the step), "
                            "not HBM")
     tag = {"sise3-37k": "sq_37k", "sise3-1m": "sq_1m", "sise3-37k-u10": "sq_u10",
