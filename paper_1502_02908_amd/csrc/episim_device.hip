@@ -1056,6 +1056,9 @@ __device__ void group_chain(const Model &m, typename Rules::State &c, bool live,
         }
         __syncthreads();
         if (!sh_go) return;  // the same in every thread
+        // the day's critical chain: its wavefronts issue ahead of the other
+        // waves on their SIMDs while it is walked
+        __builtin_amdgcn_s_setprio(3);
         typename Rules::State u;
 #pragma unroll
         for (int k = 0; k < NT; ++k) {
@@ -1073,6 +1076,7 @@ __device__ void group_chain(const Model &m, typename Rules::State &c, bool live,
                                              min_attempts))
             pairs_walk_block<Rules::kPairs, true>(m, u, kb, sh_key[0], day, sh_key[1], sh_key[2], status,
                                                   (int32_t)sh_key[3]);
+        __builtin_amdgcn_s_setprio(0);
         if (threadIdx.x == 0) c = u;
     }
 }
