@@ -30,8 +30,10 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <exception>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/episim.h"
@@ -52,73 +54,162 @@ std::string fmt(const char *f, ...) {
     return buf;
 }
 
+// An allocator that leaves new elements of trivial types uninitialised: the
+// large per-event and per-task arrays of the build are written in full by the
+// threaded passes, which then also take the first touch of their pages.
+template <class T>
+struct NoInit : std::allocator<T> {
+    template <class U>
+    struct rebind {
+        using other = NoInit<U>;
+    };
+    NoInit() noexcept = default;
+    template <class U>
+    NoInit(const NoInit<U> &) noexcept {}
+    template <class U>
+    void construct(U *p) noexcept {
+        ::new ((void *)p) U;
+    }
+    template <class U, class... A>
+    void construct(U *p, A &&...a) {
+        ::new ((void *)p) U(std::forward<A>(a)...);
+    }
+};
+template <class T>
+using big_vec = std::vector<T, NoInit<T>>;
+
 bool is_sampler(int kind) { return kind == SIM_EXIT || kind == SIM_INTERNAL || kind == SIM_EXTERNAL; }
+
+// Host threads for a build pass over many events: one below about a million
+// events, else as many as the machine has, at most 16.
+int host_threads(int64_t n) {
+    if (n < (int64_t(1) << 20)) return 1;
+    const unsigned hw = std::thread::hardware_concurrency();
+    return (int)std::min(std::max(hw, 1u), 16u);
+}
+
+// Cuts of [0, n) into at most T ranges of whole days and similar size
+// (day[] sorted); cut[0] = 0 and cut.back() = n.
+std::vector<int64_t> day_cuts(int64_t n, const int32_t *day, int T) {
+    std::vector<int64_t> cut{0};
+    for (int c = 1; c < T; ++c) {
+        int64_t at = n * c / T;
+        if (at <= cut.back()) continue;
+        at = std::upper_bound(day + at, day + n, day[at - 1]) - day;
+        if (at > cut.back() && at < n) cut.push_back(at);
+    }
+    cut.push_back(n);
+    return cut;
+}
+
+// f(range, begin, end) for each range of cut, one thread a range; the first
+// exception thrown (an allocation failure) is raised again in the caller.
+template <class F>
+void run_ranges(const std::vector<int64_t> &cut, F &&f) {
+    const int C = (int)cut.size() - 1;
+    if (C <= 1) {
+        if (C == 1) f(0, cut[0], cut[1]);
+        return;
+    }
+    std::vector<std::exception_ptr> fail(C);
+    auto guarded = [&](int c) {
+        try {
+            f(c, cut[c], cut[c + 1]);
+        } catch (...) {
+            fail[c] = std::current_exception();
+        }
+    };
+    std::vector<std::thread> th;
+    th.reserve(C - 1);
+    for (int c = 1; c < C; ++c) th.emplace_back(guarded, c);
+    guarded(0);
+    for (auto &t : th) t.join();
+    for (auto &x : fail)
+        if (x) std::rethrow_exception(x);
+}
 
 // Task and level of every event within its day; events must already be
 // sorted by day. Tasks are numbered in order of their first event. Records
 // the number of levels of each day in day_levels (resized to n_days).
+// Days are independent, so ranges of whole days are planned on their own
+// threads, each numbering its tasks from 0, and the numbers are then offset.
 void plan_levels(int64_t n, const int32_t *day, const int32_t *kind, const int32_t *node,
                  const int32_t *dest, int32_t n_nodes, int32_t *level, int32_t *task,
                  std::vector<int32_t> *day_levels, int32_t n_days) {
     // per node, valid for the day stored in stamp (nothing is cleared between
     // days): the last level at which it was touched at all / drawn from, and
     // the task of single-node events still open at it with the values of
-    // those two before the task began
-    std::vector<int32_t> stamp(n_nodes, -1), last_any(n_nodes, 0), last_draw(n_nodes, 0), open(n_nodes, -1),
-        base_any(n_nodes, 0), base_draw(n_nodes, 0);
-    std::vector<char> open_draws(n_nodes, 0);
-    std::vector<int32_t> task_level;
-    if (day_levels) day_levels->assign(n_days > 0 ? n_days : 0, 0);
-    auto touch = [&](int32_t x, int32_t d) {
-        if (stamp[x] != d) {
-            stamp[x] = d;
-            last_any[x] = 0;
-            last_draw[x] = 0;
-            open[x] = -1;
-        }
+    // those two before the task began; one cache line holds a node's state
+    struct alignas(32) NodePlan {
+        int32_t stamp, last_any, last_draw, open, base_any, base_draw, open_draws, unused;
     };
-    for (int64_t e = 0; e < n; ++e) {
-        const int32_t d = day[e];
-        const int32_t src = node[e];
-        touch(src, d);
-        if (kind[e] != SIM_EXTERNAL) {
-            // enter, exit, internal: one node; joins the node's open task
-            const bool draws = is_sampler(kind[e]);
-            int32_t t = open[src];
-            if (t < 0) {
-                t = (int32_t)task_level.size();
-                base_any[src] = last_any[src];
-                base_draw[src] = last_draw[src];
-                task_level.push_back(1 + (draws ? base_any[src] : base_draw[src]));
-                open[src] = t;
-                open_draws[src] = draws;
-            } else if (draws && !open_draws[src]) {
-                // a draw after additions only: the task must now follow every
-                // earlier event at the node (nothing else has used its level)
-                task_level[t] = std::max(task_level[t], 1 + base_any[src]);
-                open_draws[src] = 1;
+    if (day_levels) day_levels->assign(n_days > 0 ? n_days : 0, 0);
+    // each thread's node state takes 32 bytes a node: at most 1 GiB in all
+    const int64_t cap = std::max<int64_t>(1, (int64_t(1) << 30) / ((int64_t)sizeof(NodePlan) * std::max(n_nodes, 1)));
+    const std::vector<int64_t> cut = day_cuts(n, day, (int)std::min<int64_t>(host_threads(n), cap));
+    const int C = (int)cut.size() - 1;
+    std::vector<std::vector<int32_t>> task_level(std::max(C, 0));
+    run_ranges(cut, [&](int c, int64_t b, int64_t end) {
+        std::vector<NodePlan> st(n_nodes, NodePlan{-1, 0, 0, -1, 0, 0, 0, 0});
+        std::vector<int32_t> &tl = task_level[c];
+        auto touch = [&](int32_t x, int32_t d) -> NodePlan & {
+            NodePlan &q = st[x];
+            if (q.stamp != d) {
+                q.stamp = d;
+                q.last_any = 0;
+                q.last_draw = 0;
+                q.open = -1;
             }
-            task[e] = t;
-            last_any[src] = std::max(base_any[src], task_level[t]);
-            last_draw[src] = open_draws[src] ? task_level[t] : base_draw[src];
-            continue;
+            return q;
+        };
+        for (int64_t e = b; e < end; ++e) {
+            const int32_t d = day[e];
+            NodePlan &s = touch(node[e], d);
+            if (kind[e] != SIM_EXTERNAL) {
+                // enter, exit, internal: one node; joins the node's open task
+                const bool draws = is_sampler(kind[e]);
+                int32_t t = s.open;
+                if (t < 0) {
+                    t = (int32_t)tl.size();
+                    s.base_any = s.last_any;
+                    s.base_draw = s.last_draw;
+                    tl.push_back(1 + (draws ? s.base_any : s.base_draw));
+                    s.open = t;
+                    s.open_draws = draws;
+                } else if (draws && !s.open_draws) {
+                    // a draw after additions only: the task must now follow every
+                    // earlier event at the node (nothing else has used its level)
+                    tl[t] = std::max(tl[t], 1 + s.base_any);
+                    s.open_draws = 1;
+                }
+                task[e] = t;
+                s.last_any = std::max(s.base_any, tl[t]);
+                s.last_draw = s.open_draws ? tl[t] : s.base_draw;
+                continue;
+            }
+            // external transfer: draws at src, adds at dest; a task of its own
+            NodePlan &r = touch(dest[e], d);
+            s.open = -1;
+            r.open = -1;
+            const int32_t L = std::max(s.last_any + 1, r.last_draw + 1);
+            task[e] = (int32_t)tl.size();
+            tl.push_back(L);
+            s.last_any = std::max(s.last_any, L);
+            s.last_draw = L;
+            r.last_any = std::max(r.last_any, L);
         }
-        // external transfer: draws at src, adds at dest; a task of its own
-        const int32_t dst = dest[e];
-        touch(dst, d);
-        open[src] = -1;
-        open[dst] = -1;
-        const int32_t L = std::max(last_any[src] + 1, last_draw[dst] + 1);
-        task[e] = (int32_t)task_level.size();
-        task_level.push_back(L);
-        last_any[src] = std::max(last_any[src], L);
-        last_draw[src] = L;
-        last_any[dst] = std::max(last_any[dst], L);
-    }
-    for (int64_t e = 0; e < n; ++e) {
-        level[e] = task_level[task[e]];
-        if (day_levels) (*day_levels)[day[e]] = std::max((*day_levels)[day[e]], level[e]);
-    }
+    });
+    std::vector<int32_t> off(C + 1, 0);
+    for (int c = 0; c < C; ++c) off[c + 1] = off[c] + (int32_t)task_level[c].size();
+    // a day lies in one range, so each range writes its own days' counts
+    run_ranges(cut, [&](int c, int64_t b, int64_t end) {
+        const std::vector<int32_t> &tl = task_level[c];
+        for (int64_t e = b; e < end; ++e) {
+            level[e] = tl[task[e]];
+            task[e] += off[c];
+            if (day_levels) (*day_levels)[day[e]] = std::max((*day_levels)[day[e]], level[e]);
+        }
+    });
 }
 
 int check_device(hipError_t e, std::string *err, const char *what) {
@@ -461,8 +552,8 @@ struct Packed {
     std::vector<double> coef, alpha, beta;
     std::vector<int32_t> lane_of;  // [n_nodes] position of each concatenated node
     // merged events in execution order and their levels
-    std::vector<int32_t> eg, egm, enode, edest, en, ev_inst, ev_local;
-    std::vector<uint32_t> emeta, esmap;
+    big_vec<int32_t> eg, egm, enode, edest, en, ev_inst, ev_local, ev_day;
+    big_vec<uint32_t> emeta, esmap;
     std::vector<int32_t> lvl_ptr;
     std::vector<int64_t> lvl_off;   // task offsets of each level
     std::vector<int32_t> task_off;  // event offsets of each task
@@ -577,28 +668,47 @@ int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, P
         std::memcpy(&pk->beta[(size_t)k * R * 4], p->beta, sizeof(double) * R * 4);
         for (int32_t r = 0; r < R; ++r) pk->repid[(size_t)k * R + r] = p->replicate_id ? p->replicate_id[r] : (uint32_t)r;
     }
-    // merged event list: day by day, instance by instance, list order
+    // merged event list: day by day, instance by instance, list order;
+    // ranges of whole days are merged on their own threads
     const int64_t E = pk->n_events;
-    std::vector<int32_t> mday(E), mkind(E), mnode(E), mdest(E), minst(E), mlocal(E);
+    big_vec<int32_t> mday(E), mkind(E), mnode(E), mdest(E), minst(E), mlocal(E);
     {
-        std::vector<int64_t> cur(n, 0);
-        int64_t m = 0;
-        for (int32_t d = 0; d < pk->D; ++d)
+        // first event of instance k on day d (at[d * n + k]) and of day d in
+        // the merged list (m_at[d])
+        const int32_t D = pk->D;
+        std::vector<int64_t> at((size_t)(D + 1) * n), m_at(D + 1, 0);
+        for (int32_t d = 0; d <= D; ++d)
             for (int32_t k = 0; k < n; ++k) {
-                const sim_problem *p = ps[k];
-                while (cur[k] < p->n_events && p->ev_day[cur[k]] == d) {
-                    const int64_t e = cur[k]++;
-                    mday[m] = d;
-                    mkind[m] = p->ev_kind[e];
-                    mnode[m] = pk->lane_of[pk->inst_off[k] + p->ev_node[e]];
-                    mdest[m] = p->ev_kind[e] == SIM_EXTERNAL ? pk->lane_of[pk->inst_off[k] + p->ev_dest[e]] : -1;
-                    minst[m] = k;
-                    mlocal[m] = (int32_t)e;
-                    ++m;
-                }
+                const int32_t *ed = ps[k]->ev_day;
+                at[(size_t)d * n + k] = std::lower_bound(ed, ed + ps[k]->n_events, d) - ed;
+                m_at[d] += at[(size_t)d * n + k];
             }
+        std::vector<int64_t> dcut{0};
+        const int T = host_threads(E);
+        for (int c = 1; c < T; ++c) {
+            const int64_t d = std::lower_bound(m_at.begin(), m_at.end(), E * c / T) - m_at.begin();
+            if (d > dcut.back() && d < D) dcut.push_back(d);
+        }
+        dcut.push_back(D);
+        run_ranges(dcut, [&](int, int64_t d0, int64_t d1) {
+            int64_t m = m_at[d0];
+            for (int64_t d = d0; d < d1; ++d)
+                for (int32_t k = 0; k < n; ++k) {
+                    const sim_problem *p = ps[k];
+                    const int32_t off = pk->inst_off[k];
+                    for (int64_t e = at[(size_t)d * n + k]; e < at[(size_t)(d + 1) * n + k]; ++e, ++m) {
+                        mday[m] = (int32_t)d;
+                        mkind[m] = p->ev_kind[e];
+                        mnode[m] = pk->lane_of[off + p->ev_node[e]];
+                        mdest[m] = p->ev_kind[e] == SIM_EXTERNAL ? pk->lane_of[off + p->ev_dest[e]] : -1;
+                        minst[m] = k;
+                        mlocal[m] = (int32_t)e;
+                    }
+                }
+        });
     }
-    std::vector<int32_t> level(E), task(E), day_levels;
+    big_vec<int32_t> level(E), task(E);
+    std::vector<int32_t> day_levels;
     if (events_mode == SIM_EVENTS_SERIAL) {
         day_levels.assign(pk->D, 0);
         for (int64_t e = 0; e < E; ++e) {
@@ -609,65 +719,92 @@ int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, P
         plan_levels(E, mday.data(), mkind.data(), mnode.data(), mdest.data(), (int32_t)std::max<int64_t>(pk->Np, 1),
                     level.data(), task.data(), &day_levels, pk->D);
     }
-    int64_t n_tasks = 0;
-    for (int64_t e = 0; e < E; ++e) n_tasks = std::max<int64_t>(n_tasks, (int64_t)task[e] + 1);
+    // ranges of whole days for the threaded passes below and the tasks of
+    // each: tasks are numbered in order of their first event, and a day's
+    // first event opens a task
+    const std::vector<int64_t> cut = day_cuts(E, mday.data(), host_threads(E));
+    const int C = (int)cut.size() - 1;
+    std::vector<int64_t> tcut(C + 1, 0);
+    {
+        std::vector<int64_t> top(C, 0);
+        run_ranges(cut, [&](int c, int64_t b, int64_t end) {
+            for (int64_t e = b; e < end; ++e) top[c] = std::max<int64_t>(top[c], (int64_t)task[e] + 1);
+        });
+        for (int c = 0; c < C; ++c) {
+            tcut[c] = cut[c] < E ? task[cut[c]] : 0;
+            tcut[C] = std::max(tcut[C], top[c]);
+        }
+    }
+    const int64_t n_tasks = tcut[C];
     pk->n_tasks = n_tasks;
     // Private tasks: a level-1 run of one node's single-node events touches
     // only that node, and nothing else touches it before the run in list
     // order, so it runs in the node's unit of the day kernel right after the
     // SSA. The levels left are renumbered from 1 (a day whose level 1 held
     // only private tasks loses it).
-    std::vector<char> priv(n_tasks, 0), ext1(pk->D, 0);
-    if (events_mode == SIM_EVENTS_LEVELS) {
-        for (int64_t e = 0; e < E; ++e)
+    big_vec<char> priv(n_tasks);
+    std::vector<char> ext1(pk->D, 0);
+    run_ranges(cut, [&](int c, int64_t b, int64_t end) {
+        std::fill(priv.begin() + tcut[c], priv.begin() + tcut[c + 1], 0);
+        if (events_mode != SIM_EVENTS_LEVELS) return;
+        for (int64_t e = b; e < end; ++e)
             if (level[e] == 1) {
                 if (mkind[e] == SIM_EXTERNAL)
                     ext1[mday[e]] = 1;
                 else
                     priv[task[e]] = 1;
             }
-        for (int64_t e = 0; e < E; ++e)
+        for (int64_t e = b; e < end; ++e)
             if (!priv[task[e]] && !ext1[mday[e]]) level[e] -= 1;
+    });
+    if (events_mode == SIM_EVENTS_LEVELS)
         for (int32_t d = 0; d < pk->D; ++d)
             if (!ext1[d] && day_levels[d] > 0) day_levels[d] -= 1;
-    }
     pk->lvl_ptr.assign(pk->D + 1, 0);
     for (int32_t d = 0; d < pk->D; ++d) pk->lvl_ptr[d + 1] = pk->lvl_ptr[d] + day_levels[d];
     pk->n_levels = pk->lvl_ptr[pk->D];
     // tasks in execution order: level tasks by level, then by first event;
     // then private tasks by day, unit and first event; a task's events stay
-    // together in list order
+    // together in list order. Levels and (day, unit) pairs belong to one day,
+    // so each range counts and places its own tasks.
     const int64_t U = pk->Np / unit_positions(pk->layout, pk->tile);
     pk->n_units = U;
-    std::vector<int64_t> task_glv(n_tasks, 0), task_n(n_tasks, 0), tslot(n_tasks, 0);
-    for (int64_t e = 0; e < E; ++e) {
-        task_glv[task[e]] = priv[task[e]] ? (int64_t)mday[e] * U + mnode[e] / unit_positions(pk->layout, pk->tile)
-                                          : pk->lvl_ptr[mday[e]] + level[e] - 1;
-        task_n[task[e]]++;
-    }
+    big_vec<int64_t> task_glv(n_tasks);
+    big_vec<int32_t> task_n(n_tasks), tslot(n_tasks);
     pk->lvl_off.assign(pk->n_levels + 1, 0);
     pk->priv_off.assign((size_t)pk->D * U + 1, 0);
-    for (int64_t t = 0; t < n_tasks; ++t) {
-        if (priv[t])
-            pk->priv_off[task_glv[t] + 1]++;
-        else
-            pk->lvl_off[task_glv[t] + 1]++;
-    }
+    run_ranges(cut, [&](int c, int64_t b, int64_t end) {
+        std::fill(task_n.begin() + tcut[c], task_n.begin() + tcut[c + 1], 0);
+        for (int64_t e = b; e < end; ++e) {
+            task_glv[task[e]] = priv[task[e]] ? (int64_t)mday[e] * U + mnode[e] / unit_positions(pk->layout, pk->tile)
+                                              : pk->lvl_ptr[mday[e]] + level[e] - 1;
+            task_n[task[e]]++;
+        }
+        for (int64_t t = tcut[c]; t < tcut[c + 1]; ++t) {
+            if (priv[t])
+                pk->priv_off[task_glv[t] + 1]++;
+            else
+                pk->lvl_off[task_glv[t] + 1]++;
+        }
+    });
     for (int64_t i = 0; i < pk->n_levels; ++i) pk->lvl_off[i + 1] += pk->lvl_off[i];
     pk->priv_off[0] = (int32_t)pk->lvl_off[pk->n_levels];
     for (size_t i = 0; i + 1 < pk->priv_off.size(); ++i) pk->priv_off[i + 1] += pk->priv_off[i];
+    pk->task_off.assign(n_tasks + 1, 0);
     {
         std::vector<int64_t> next(pk->lvl_off.begin(), pk->lvl_off.end() - 1);
         std::vector<int64_t> pnext(pk->priv_off.begin(), pk->priv_off.end() - 1);
-        for (int64_t t = 0; t < n_tasks; ++t) tslot[t] = priv[t] ? pnext[task_glv[t]]++ : next[task_glv[t]]++;
+        run_ranges(cut, [&](int c, int64_t, int64_t) {
+            for (int64_t t = tcut[c]; t < tcut[c + 1]; ++t) {
+                tslot[t] = (int32_t)(priv[t] ? pnext[task_glv[t]]++ : next[task_glv[t]]++);
+                pk->task_off[tslot[t] + 1] = task_n[t];
+            }
+        });
     }
-    pk->task_off.assign(n_tasks + 1, 0);
-    for (int64_t t = 0; t < n_tasks; ++t) pk->task_off[tslot[t] + 1] = (int32_t)task_n[t];
     for (int64_t i = 0; i < n_tasks; ++i) pk->task_off[i + 1] += pk->task_off[i];
     pk->priv_ev_off.resize(pk->priv_off.size());
     for (size_t i = 0; i < pk->priv_off.size(); ++i) pk->priv_ev_off[i] = pk->task_off[pk->priv_off[i]];
-    std::vector<int64_t> fill(n_tasks);
-    for (int64_t t = 0; t < n_tasks; ++t) fill[t] = pk->task_off[tslot[t]];
+    big_vec<int64_t> fill(n_tasks);
     pk->eg.resize(E);
     pk->egm.resize(E);
     pk->enode.resize(E);
@@ -675,27 +812,38 @@ int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, P
     pk->en.resize(E);
     pk->emeta.resize(E);
     pk->esmap.resize(E);
-    pk->ev_inst = minst;
-    pk->ev_local = mlocal;
-    for (int64_t e = 0; e < E; ++e) {
-        const sim_problem *p = ps[minst[e]];
-        const int64_t le = mlocal[e];
-        const int64_t pos = fill[task[e]]++;
-        pk->eg[pos] = (int32_t)le;
-        pk->egm[pos] = (int32_t)e;
-        pk->enode[pos] = mnode[e];
-        pk->edest[pos] = mdest[e];
-        pk->en[pos] = p->ev_n[le];
-        pk->emeta[pos] = meta_pack(p->ev_kind[le], column_mask(p, p->ev_select[le]), p->ev_shift[le]);
+    pk->ev_inst = std::move(minst);
+    pk->ev_local = std::move(mlocal);
+    pk->ev_day = std::move(mday);
+    // of the model all instances share: the column mask of each select and
+    // the compartment map of each shift (at shift + 1; 0 is no shift)
+    std::vector<uint32_t> mask_of(p0->n_select), smap_of(p0->n_shift + 1);
+    for (int32_t sel = 0; sel < p0->n_select; ++sel) mask_of[sel] = column_mask(p0, sel);
+    for (int32_t sid = -1; sid < p0->n_shift; ++sid) {
         uint32_t smap = 0;
         for (int c = 0; c < pk->Nc; ++c) {
-            const int32_t sid = p->ev_shift[le];
-            const int to = sid >= 0 ? c + p->N[(size_t)c * p->n_shift + sid] : c;
+            const int to = sid >= 0 ? c + p0->N[(size_t)c * p0->n_shift + sid] : c;
             smap |= (uint32_t)(to & 0xF) << (4 * c);
         }
-        pk->esmap[pos] = smap;
-        if (pos != pk->task_off[tslot[task[e]]]) pk->emeta[pos] |= kMetaCont;
+        smap_of[sid + 1] = smap;
     }
+    // a task lies in one day, so ranges of whole days fill disjoint positions
+    run_ranges(cut, [&](int c, int64_t b, int64_t end) {
+        for (int64_t t = tcut[c]; t < tcut[c + 1]; ++t) fill[t] = pk->task_off[tslot[t]];
+        for (int64_t e = b; e < end; ++e) {
+            const sim_problem *p = ps[pk->ev_inst[e]];
+            const int64_t le = pk->ev_local[e];
+            const int64_t pos = fill[task[e]]++;
+            pk->eg[pos] = (int32_t)le;
+            pk->egm[pos] = (int32_t)e;
+            pk->enode[pos] = mnode[e];
+            pk->edest[pos] = mdest[e];
+            pk->en[pos] = p->ev_n[le];
+            pk->emeta[pos] = meta_pack(p->ev_kind[le], mask_of[p->ev_select[le]], p->ev_shift[le]) |
+                             (pos != pk->task_off[tslot[task[e]]] ? kMetaCont : 0u);
+            pk->esmap[pos] = smap_of[p->ev_shift[le] + 1];
+        }
+    });
     pk->lvl_ev_off.resize(pk->n_levels + 1);
     for (int64_t i = 0; i <= pk->n_levels; ++i) pk->lvl_ev_off[i] = pk->task_off[pk->lvl_off[i]];
     // Days whose level tasks fit one workgroup with one lane per node run in
@@ -776,7 +924,7 @@ struct sim_handle {
     DevEvents ev{};
     std::vector<int32_t> lane_of;   // position of each concatenated node
     std::vector<int32_t> node_id;   // node number within its instance per position (-1: padding)
-    std::vector<int32_t> ev_inst, ev_local, ev_day;  // merged event index -> instance, local index, day
+    big_vec<int32_t> ev_inst, ev_local, ev_day;  // merged event index -> instance, local index, day
     std::vector<int64_t> lvl_off;   // host copy of the level boundaries (task offsets)
     std::vector<int32_t> lvl_ptr;   // [D+1]
     std::vector<int32_t> day_slot_off;  // [D+1]: a day with slots runs its levels in LDS
@@ -977,19 +1125,9 @@ int create(const sim_problem *const *ps, int32_t n, const sim_device_opts *o, si
     h->lvl_ptr = pk.lvl_ptr;
     h->day_slot_off = pk.day_slot_off;
     h->lvl_ev_off = pk.lvl_ev_off;
-    h->ev_inst = pk.ev_inst;
-    h->ev_local = pk.ev_local;
-    h->ev_day.resize(pk.n_events);
-    {
-        int64_t m = 0;
-        std::vector<int64_t> cur(n, 0);
-        for (int32_t d = 0; d < pk.D; ++d)
-            for (int32_t k = 0; k < n; ++k)
-                while (cur[k] < ps[k]->n_events && ps[k]->ev_day[cur[k]] == d) {
-                    h->ev_day[m++] = d;
-                    ++cur[k];
-                }
-    }
+    h->ev_inst = std::move(pk.ev_inst);
+    h->ev_local = std::move(pk.ev_local);
+    h->ev_day = std::move(pk.ev_day);
 
     // --- model constants
     Model &m = h->model;
