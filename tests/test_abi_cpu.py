@@ -194,6 +194,31 @@ def test_levels_on_generated_network():
     assert len(np.unique(task)) < len(task)
 
 
+def test_long_lists_plan_each_day_as_alone():
+    # days are independent in the dependency pass: a list long enough to be
+    # planned in ranges of days on several host threads gets, day by day, the
+    # levels of that day planned alone and its tasks offset by the tasks of
+    # the days before; tasks stay numbered in order of their first event
+    rng = np.random.default_rng(21)
+    n_nodes, n_days = 20000, 37
+    per_day = rng.integers(5000, 60000, n_days)
+    day = np.repeat(np.arange(n_days), per_day)
+    n = len(day)
+    assert n > 1 << 20
+    kind = rng.integers(0, 4, n)
+    node = rng.integers(0, n_nodes, n)
+    dest = np.where(kind == EXTERNAL, rng.integers(0, n_nodes, n), -1)
+    level, task = P.plan_levels(day, kind, node, dest, n_nodes, tasks=True)
+    first = np.unique(task, return_index=True)[1]
+    assert np.array_equal(np.unique(task), np.arange(task.max() + 1)) and (np.diff(first) > 0).all()
+    off = 0
+    for d, (b, e) in enumerate(zip(np.r_[0, np.cumsum(per_day)[:-1]], np.cumsum(per_day))):
+        lv, tk = P.plan_levels(day[b:e], kind[b:e], node[b:e], dest[b:e], n_nodes, tasks=True)
+        assert np.array_equal(level[b:e], lv), d
+        assert np.array_equal(task[b:e], tk + off), d
+        off += tk.max() + 1
+
+
 def test_single_node_runs_form_one_task():
     # node 0: enter, exit, internal, exit -> one task at level 1; a move out of
     # node 0 follows it; the next exit at node 0 starts a new task after the move
