@@ -913,10 +913,49 @@ __device__ __forceinline__ bool block_ok(const unsigned long long *status) {
     return ok != 0;
 }
 
+// block_ok for a kernel that checks once per launch: thread 0 reads the
+// status word right away, alongside the loads the workgroup has already
+// issued, and one barrier publishes it (no earlier reader of the flag to wait
+// for), so the check adds no round trip of its own.
+__device__ __forceinline__ bool block_ok_once(const unsigned long long *status) {
+    __shared__ int ok;
+    if (threadIdx.x == 0) ok = *(volatile const unsigned long long *)status == STATUS_OK;
+    __syncthreads();
+    return ok != 0;
+}
+
+// Wavefront reductions with DPP lane moves, which run in the vector ALU:
+// pairs and quads (quad permutes), rows of 8 and 16 lanes (half-row and row
+// mirrors), then row 0 into row 1 and row 2 into row 3 (broadcast of lane 15),
+// then rows 0-1 into rows 2-3 (broadcast of lane 31); lane 63 ends with the
+// whole wavefront, read back as a uniform value. Every lane must be active.
+// (A shuffle butterfly would wait on an LDS crossbar round trip per step.)
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ int32_t dpp_move(int32_t v) {
+    // lanes of rows outside ROWS read 0
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xf, false);
+}
+
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ long long dpp_move64(long long v) {
+    const uint32_t lo = (uint32_t)dpp_move<CTRL, ROWS>((int32_t)(uint32_t)v);
+    const uint32_t hi = (uint32_t)dpp_move<CTRL, ROWS>((int32_t)(uint32_t)((unsigned long long)v >> 32));
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+constexpr int kDppXor1 = 0xb1, kDppXor2 = 0x4e, kDppHalfMirror = 0x141, kDppMirror = 0x140,
+              kDppBcast15 = 0x142, kDppBcast31 = 0x143;
+
 __device__ __forceinline__ long long wave_sum(long long v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v += dpp_move64<kDppXor1>(v);
+    v += dpp_move64<kDppXor2>(v);
+    v += dpp_move64<kDppHalfMirror>(v);
+    v += dpp_move64<kDppMirror>(v);
+    v += dpp_move64<kDppBcast15, 0xa>(v);
+    v += dpp_move64<kDppBcast31, 0xc>(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)v, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)((unsigned long long)v >> 32), 63);
+    return (long long)(((unsigned long long)hi << 32) | lo);
 }
 
 // Per-lane contributions to the daily records of one phase.
@@ -927,10 +966,15 @@ struct Tally {
     int32_t most;  // most SSA transitions of one lane's chain (the day's straggler)
 };
 
+// (for values >= 0: rows outside a broadcast's mask read 0)
 __device__ __forceinline__ int32_t wave_max(int32_t v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
-    return v;
+    v = max(v, dpp_move<kDppXor1>(v));
+    v = max(v, dpp_move<kDppXor2>(v));
+    v = max(v, dpp_move<kDppHalfMirror>(v));
+    v = max(v, dpp_move<kDppMirror>(v));
+    v = max(v, dpp_move<kDppBcast15, 0xa>(v));
+    v = max(v, dpp_move<kDppBcast31, 0xc>(v));
+    return __builtin_amdgcn_readlane(v, 63);
 }
 
 // Sum tallies over the workgroup and add them to the records of one set
@@ -1449,7 +1493,7 @@ template <int NC>
 struct EventDayShared {
     int32_t u[kDaySlotCap * NC];
     uint32_t k0[kDaySlotCap], k1[kDaySlotCap];
-    int32_t set[kDaySlotCap];
+    int32_t set[kDaySlotCap], pos[kDaySlotCap];
     int32_t n[kDayEventCap], g[kDayEventCap];
     uint32_t meta[kDayEventCap], smap[kDayEventCap];
     int16_t ss[kDayEventCap], sd[kDayEventCap];
@@ -1481,7 +1525,7 @@ __global__ __launch_bounds__(kBlock) void k_day(Model m, DevState s, DevEvents e
     const bool staged = ssa && ev.unit_stage_off;
     const int32_t st0 = staged ? ev.unit_stage_off[k] : 0;
     const int32_t nst = staged ? ev.unit_stage_off[k + 1] - st0 : 0;
-    if (!block_ok(s.status)) return;
+    if (!block_ok_once(s.status)) return;
     const uint32_t key0 = s.seed[set], key1 = s.repid[set];
     const bool lds = npe <= kBlock;
     const bool has = lds && (int)threadIdx.x < npe;
@@ -1632,7 +1676,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Rules::k
     const int64_t by = heavy ? (lin - n_tiles) % gridDim.y : lin / nx;
     if (s.n_heavy && bx < nx && s.unit_heavy[bx]) return;  // uniform over the workgroup
     if constexpr (!SLOTS) {
-        if (!block_ok(s.status)) return;
+        if (!block_ok_once(s.status)) return;
     }
     // the column of 64 replicate lanes (a slot handle launches only the
     // columns that run this step)
@@ -1907,7 +1951,7 @@ constexpr int kGroupCap = 1024;
 template <int NC>
 __global__ __launch_bounds__(kEvBlock) void k_event_levels(Model m, DevState s, DevEvents ev, int32_t d,
                                                            int32_t lv_begin, int32_t lv_end) {
-    if (!block_ok(s.status)) return;
+    if (!block_ok_once(s.status)) return;
     __shared__ EvDesc sh_desc[kGroupCap];
     __shared__ int32_t sh_multi[kGroupCap];
     const int64_t tb = ev.lvl_off[lv_begin], te = ev.lvl_off[lv_end];
@@ -2020,10 +2064,11 @@ __device__ void event_day_levels(const Model &m, const DevState &s, const DevEve
         sh.k0[i] = ev.slot_key[3 * (s0 + i)];
         sh.k1[i] = ev.slot_key[3 * (s0 + i) + 1];
         sh.set[i] = (int32_t)ev.slot_key[3 * (s0 + i) + 2];
+        sh.pos[i] = ev.slot_pos[s0 + i];
 #pragma unroll
         for (int c = 0; c < NC; ++c) sh.u[i * NC + c] = ev.stage[i * NC + c];
     }
-    if (!block_ok(s.status)) return;  // its barriers also publish the staged fields
+    if (!block_ok_once(s.status)) return;  // its barrier also publishes the staged fields
     // the first draws of every event do not depend on the state: all at once
     for (int i = threadIdx.x; i < ne * (kPreDraws / 2); i += nth) {
         const int j = i / (kPreDraws / 2), b = i % (kPreDraws / 2);
@@ -2051,7 +2096,7 @@ __device__ void event_day_levels(const Model &m, const DevState &s, const DevEve
         __syncthreads();
     }
     for (int i = threadIdx.x; i < ns; i += nth) {
-        const int32_t pos = ev.slot_pos[s0 + i];
+        const int32_t pos = sh.pos[i];
 #pragma unroll
         for (int c = 0; c < NC; ++c)
             if (comp_on<NC>(m, c)) s.u[(int64_t)c * s.L + pos] = sh.u[i * NC + c];
@@ -2078,7 +2123,7 @@ __global__ __launch_bounds__(kEvBlock) void k_slot_events(Model m, DevState s, D
     const int32_t d = step - si.t0;
     if (si.t0 < 0 || d < 0 || d >= si.horizon) return;  // uniform over the workgroup
     unsigned long long *status = s.status + slot;
-    if (!block_ok(status)) return;
+    if (!block_ok_once(status)) return;
     const int32_t W = s.slot_lanes;
     const int32_t lv0 = ev.lvl_ptr[d], lv_day_end = ev.lvl_ptr[d + 1];
     const int64_t stride = (int64_t)gridDim.x * kEvBlock;
