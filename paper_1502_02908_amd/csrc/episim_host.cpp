@@ -240,6 +240,36 @@ int check_params(int Nt, int64_t R, const double *coef, const double *alpha, con
 }
 
 // Full validation of one problem statement (the contract in episim.h).
+// The first fault of event e of p in the order of the checks (its message in
+// *msg and nonzero), or 0; mask_of holds the column mask of each select.
+int event_fault(const sim_problem *p, int64_t e, const uint32_t *mask_of, std::string *msg) {
+    const int Nc = p->n_comp;
+    const int32_t d = p->ev_day[e], k = p->ev_kind[e], i = p->ev_node[e], s = p->ev_select[e];
+    const int32_t h = p->ev_shift[e];
+    if (d < 0 || d >= p->n_days) return *msg = fmt("event %lld: day out of range", (long long)e), 1;
+    if (e > 0 && d < p->ev_day[e - 1]) return *msg = fmt("event %lld: days not sorted", (long long)e), 1;
+    if (k < 0 || k > 3) return *msg = fmt("event %lld: unknown kind", (long long)e), 1;
+    if (i < 0 || i >= p->n_nodes) return *msg = fmt("event %lld: node out of range", (long long)e), 1;
+    if (k == SIM_EXTERNAL && (p->ev_dest[e] < 0 || p->ev_dest[e] >= p->n_nodes))
+        return *msg = fmt("event %lld: dest out of range", (long long)e), 1;
+    if (p->ev_n[e] < 0 || p->ev_n[e] > SIM_MAX_EVENT_N)
+        return *msg = fmt("event %lld: n must be in [0, %d]", (long long)e, SIM_MAX_EVENT_N), 1;
+    if (s < 0 || s >= p->n_select) return *msg = fmt("event %lld: select out of range", (long long)e), 1;
+    if (h < -1 || h >= p->n_shift) return *msg = fmt("event %lld: shift out of range", (long long)e), 1;
+    const uint32_t m = mask_of[s];
+    if (k == SIM_ENTER && (m == 0 || (m & (m - 1))))
+        return *msg = fmt("event %lld: ENTER must select exactly one compartment", (long long)e), 1;
+    if (h >= 0 && k != SIM_ENTER && k != SIM_EXIT) {
+        for (int c = 0; c < Nc; ++c) {
+            if (!((m >> c) & 1u)) continue;
+            const int to = c + p->N[(size_t)c * p->n_shift + h];
+            if (to < 0 || to >= Nc)
+                return *msg = fmt("event %lld: shift moves compartment %d out of range", (long long)e, c), 1;
+        }
+    }
+    return 0;
+}
+
 int validate(const sim_problem *p, std::string *err) {
     if (!p) return *err = "problem is NULL", SIM_EINVAL;
     if (p->n_nodes < 0) return *err = "n_nodes < 0", SIM_EINVAL;
@@ -289,30 +319,21 @@ int validate(const sim_problem *p, std::string *err) {
     if (p->n_events > 0 && (!p->ev_day || !p->ev_kind || !p->ev_node || !p->ev_dest || !p->ev_n ||
                             !p->ev_select || !p->ev_shift))
         return *err = "an event array is NULL", SIM_EINVAL;
-    for (int64_t e = 0; e < p->n_events; ++e) {
-        const int32_t d = p->ev_day[e], k = p->ev_kind[e], i = p->ev_node[e], s = p->ev_select[e];
-        const int32_t h = p->ev_shift[e];
-        if (d < 0 || d >= p->n_days) return *err = fmt("event %lld: day out of range", (long long)e), SIM_EINVAL;
-        if (e > 0 && d < p->ev_day[e - 1]) return *err = fmt("event %lld: days not sorted", (long long)e), SIM_EINVAL;
-        if (k < 0 || k > 3) return *err = fmt("event %lld: unknown kind", (long long)e), SIM_EINVAL;
-        if (i < 0 || i >= p->n_nodes) return *err = fmt("event %lld: node out of range", (long long)e), SIM_EINVAL;
-        if (k == SIM_EXTERNAL && (p->ev_dest[e] < 0 || p->ev_dest[e] >= p->n_nodes))
-            return *err = fmt("event %lld: dest out of range", (long long)e), SIM_EINVAL;
-        if (p->ev_n[e] < 0 || p->ev_n[e] > SIM_MAX_EVENT_N)
-            return *err = fmt("event %lld: n must be in [0, %d]", (long long)e, SIM_MAX_EVENT_N), SIM_EINVAL;
-        if (s < 0 || s >= p->n_select) return *err = fmt("event %lld: select out of range", (long long)e), SIM_EINVAL;
-        if (h < -1 || h >= p->n_shift) return *err = fmt("event %lld: shift out of range", (long long)e), SIM_EINVAL;
-        const uint32_t m = column_mask(p, s);
-        if (k == SIM_ENTER && (m == 0 || (m & (m - 1))))
-            return *err = fmt("event %lld: ENTER must select exactly one compartment", (long long)e), SIM_EINVAL;
-        if (h >= 0 && k != SIM_ENTER && k != SIM_EXIT) {
-            for (int c = 0; c < Nc; ++c) {
-                if (!((m >> c) & 1u)) continue;
-                const int to = c + p->N[(size_t)c * p->n_shift + h];
-                if (to < 0 || to >= Nc)
-                    return *err = fmt("event %lld: shift moves compartment %d out of range", (long long)e, c), SIM_EINVAL;
-            }
-        }
+    if (p->n_events > 0) {
+        // ranges of events on host threads; the first range with a fault
+        // holds the first faulting event
+        std::vector<uint32_t> mask_of(p->n_select);
+        for (int32_t sel = 0; sel < p->n_select; ++sel) mask_of[sel] = column_mask(p, sel);
+        const int T = host_threads(p->n_events);
+        std::vector<int64_t> cut(T + 1);
+        for (int c = 0; c <= T; ++c) cut[c] = p->n_events * c / T;
+        std::vector<std::string> fault(T);
+        run_ranges(cut, [&](int c, int64_t b, int64_t end) {
+            for (int64_t e = b; e < end; ++e)
+                if (event_fault(p, e, mask_of.data(), &fault[c])) return;
+        });
+        for (const std::string &f : fault)
+            if (!f.empty()) return *err = f, SIM_EINVAL;
     }
     if (p->n_record < 0 || (p->n_record > 0 && !p->record_days)) return *err = "bad record_days", SIM_EINVAL;
     for (int k = 0; k < p->n_record; ++k) {
@@ -420,16 +441,36 @@ int64_t order_nodes(const sim_problem *p, int layout, int64_t tile, int64_t heav
         for (int64_t c = 0; c < Nc; ++c) now[i] += p->u0[i * Nc + c];
         size[i] = now[i];
     }
-    for (int64_t e = 0; e < p->n_events; ++e) {
-        const int32_t i = p->ev_node[e], k = p->ev_kind[e], n = p->ev_n[e];
-        if (k == SIM_ENTER) now[i] += n;
-        if (k == SIM_EXIT || k == SIM_EXTERNAL) now[i] -= n;
-        if (k == SIM_EXTERNAL) {
-            now[p->ev_dest[e]] += n;
-            size[p->ev_dest[e]] = std::max(size[p->ev_dest[e]], now[p->ev_dest[e]]);
+    // Ranges of events on host threads: each range replays its events from
+    // zero, keeping every node's net change and its highest running change at
+    // the points where the whole replay takes a node's maximum; the ranges
+    // then add up in order (16 bytes a node and range, at most 1 GiB in all).
+    const int64_t cap = std::max<int64_t>(1, (int64_t(1) << 30) / (16 * std::max<int64_t>(Nn, 1)));
+    const int T = (int)std::min<int64_t>(host_threads(p->n_events), cap);
+    std::vector<int64_t> cut(T + 1);
+    for (int c = 0; c <= T; ++c) cut[c] = p->n_events * c / T;
+    std::vector<std::vector<int64_t>> delta(T), peak(T);
+    run_ranges(cut, [&](int c, int64_t b, int64_t end) {
+        std::vector<int64_t> &cum = delta[c], &top = peak[c];
+        cum.assign(Nn, 0);
+        top.assign(Nn, 0);
+        for (int64_t e = b; e < end; ++e) {
+            const int32_t i = p->ev_node[e], k = p->ev_kind[e], n = p->ev_n[e];
+            if (k == SIM_ENTER) cum[i] += n;
+            if (k == SIM_EXIT || k == SIM_EXTERNAL) cum[i] -= n;
+            if (k == SIM_EXTERNAL) {
+                const int32_t j = p->ev_dest[e];
+                cum[j] += n;
+                top[j] = std::max(top[j], cum[j]);
+            }
+            top[i] = std::max(top[i], cum[i]);
         }
-        size[i] = std::max(size[i], now[i]);
-    }
+    });
+    for (int c = 0; c < T; ++c)
+        for (int64_t i = 0; i < Nn; ++i) {
+            size[i] = std::max(size[i], now[i] + peak[c][i]);
+            now[i] += delta[c][i];
+        }
     std::vector<int32_t> rank(Nn);
     for (int64_t i = 0; i < Nn; ++i) rank[i] = (int32_t)i;
     std::stable_sort(rank.begin(), rank.end(), [&](int32_t a, int32_t b) { return size[a] > size[b]; });

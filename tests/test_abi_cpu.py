@@ -95,6 +95,23 @@ def test_shift_landing_outside_compartments_rejected():
     assert rc == S.SIM_EINVAL and "shift" in msg
 
 
+def test_long_event_lists_report_their_first_fault():
+    # validation runs over ranges of events on host threads when the list is
+    # long: the message still names the first faulting event, whichever
+    # range holds it, and a list without faults passes
+    p = synth.sise3_network(n_nodes=20000, n_days=1000, seed=5, age_days=(20, 60), e1_per_node_day=0.06)
+    n = p.n_events
+    assert n > 1 << 20
+    assert S.workspace_bytes(p) > 0
+    late, early = n - 7, n // 3 + 11
+    p.ev_node[late] = p.n_nodes        # node out of range
+    rc, msg = _create_error(p)
+    assert rc == S.SIM_EINVAL and msg == f"event {late}: node out of range", msg
+    p.ev_n[early] = -1                 # an earlier fault, in another range
+    rc, msg = _create_error(p)
+    assert rc == S.SIM_EINVAL and msg.startswith(f"event {early}: n must be in"), msg
+
+
 def test_valid_problem_passes_validation():
     p = _base()
     assert S.workspace_bytes(p) > 0
