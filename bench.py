@@ -120,22 +120,29 @@ VALU_PEAK_OPS = 256 * 4 * 16 * CLOCK_GHZ * 1e9
 OPS_PER_ATTEMPT = 98 + 10 + 50 + 10 + 2 + 1 + 12 + 2 + 11
 
 
-def chain_probe(P, synth, torch, half=1000, days=40, n_nodes=1):
+def chain_probe(P, synth, torch, half=1000, days=40, n_nodes=1, classes=1):
     """Time per attempt of one long chain (the serial critical path of a
     plain step): the synthetic model of Sec. 4.2 with one node of S = I =
     half (lambda = 2 half per day, no events) among n_nodes - 1 empty ones,
     its day kernel's duration less that of the same network with no
-    animals, over the attempts of a day (transitions + 1). With one node the
-    chain is walked by a wavefront; from 8192 nodes on, the largest herd has
-    a workgroup as on the farm networks (the block walk fed by a second
-    wavefront, and the workgroup walk while the chain expects 4096 attempts
-    or more)."""
+    animals, over the attempts of a day (transitions + 1). classes = 3 runs
+    the same dynamics on the SISe3 compartments (S_j = I_j = half / 3 in each
+    class), so the chain walks the six-compartment model as the farm
+    networks' herds do. With one node the chain is walked by a wavefront;
+    from 8192 nodes on, the largest herd has a workgroup as on the farm
+    networks (the block walk fed by a second wavefront, and the workgroup walk
+    while the chain expects 4096 attempts or more)."""
     import numpy as np
 
     def day_us(S0):
-        p = synth.flip_model(n_nodes=n_nodes, S0=0, I0=0, n_days=days)
+        if classes == 3:
+            p = synth.flip_classes(n_nodes=n_nodes, S0=0, I0=0, n_days=days)
+            row = [S0 // 3] * 6
+        else:
+            p = synth.flip_model(n_nodes=n_nodes, S0=0, I0=0, n_days=days)
+            row = [S0, S0]
         p.u0 = np.ascontiguousarray(p.u0)
-        p.u0[0] = [S0, S0]
+        p.u0[0] = row
         with P.Simulator(p) as sim:
             sim.run(0)
             sim.sync()
@@ -151,9 +158,12 @@ def chain_probe(P, synth, torch, half=1000, days=40, n_nodes=1):
     t_empty, _ = day_us(0)
     us = (t_big - t_empty) / (per_day + 1.0)
     where = "one node" if n_nodes == 1 else f"one node of {n_nodes}"
+    model = ("the synthetic S<->I model" if classes == 1 else
+             "the synthetic S<->I dynamics on the six SISe3 compartments")
+    size = f"S = I = {half}" if classes == 1 else f"S_j = I_j = {half // 3}"
     return dict(us_per_attempt=us, cycles_per_attempt=us * 1e3 * CLOCK_GHZ, attempts_per_day=per_day + 1.0,
                 day_kernel_us=t_big, empty_day_kernel_us=t_empty,
-                probe=f"{where} of the synthetic S<->I model with S = I = {half}, {days} days")
+                probe=f"{where} of {model} with {size}, {days} days")
 
 
 def tuned(p, start_day, window, enabled):
@@ -595,13 +605,16 @@ def main():
     # largest herd (from 8192 nodes with one lane per node: its own workgroup,
     # the workgroup walk for chains of 4096 expected attempts or more)
     hub_layout = p.n_nodes >= 8192 and p.n_rep == 1 and not best.get("tile_nodes")
+    # the probe walks the workload's own rules: three S<->I classes on the
+    # six-compartment networks, one on the synthetic model
+    classes = 3 if p.n_comp == 6 else 1
     if hub_layout:
-        short = chain_probe(P, synth, torch, half=1000, n_nodes=8192)
-        long_ = chain_probe(P, synth, torch, half=10000, days=20, n_nodes=8192)
+        short = chain_probe(P, synth, torch, half=1000, n_nodes=8192, classes=classes)
+        long_ = chain_probe(P, synth, torch, half=10000, days=20, n_nodes=8192, classes=classes)
         per_day_us = np.where(most + 1 >= 4096, long_["us_per_attempt"], short["us_per_attempt"]) * (most + 1)
         probes = [short, long_]
     else:
-        one = chain_probe(P, synth, torch)
+        one = chain_probe(P, synth, torch, classes=classes)
         per_day_us = one["us_per_attempt"] * (most + 1)
         probes = [one]
     chain_ms = float(per_day_us.sum()) / 1e3

@@ -418,6 +418,18 @@ def flip_model(n_nodes=400, S0=1000, I0=1000, n_days=2, seed=12):
                    seed=seed, name="flip", **m, **_no_events())
 
 
+def flip_classes(n_nodes=400, S0=333, I0=333, n_days=2, seed=12):
+    """The synthetic model's dynamics on the SISe3 compartments: in each of the
+    three classes S_j -> I_j and I_j -> S_j at rate 1 per individual, S0 and
+    I0 of each per node, no coupling and no events (a chain of the
+    six-compartment model whose length is known in advance)."""
+    m = sise3_model(coef=np.ones(6))
+    m["uses_phi"] = np.zeros(6, np.int32)
+    u0 = np.tile(np.array([[S0, I0] * 3]), (n_nodes, 1))
+    return Problem(n_nodes=n_nodes, n_rep=1, n_days=n_days, u0=u0, v0=np.zeros(n_nodes),
+                   seed=seed, name="flip3", **m, **_no_events())
+
+
 def constant_infection(n_nodes=3, S0=(90, 50, 0), I0=(10, 50, 0), phi0=(0.0, 1.5, 2.0),
                        n_days=400, day0=0, beta=(0.10, 0.12, 0.10, 0.08), alpha=0.7, seed=13):
     """SIS with all rates zero and no events: I/N is constant, so phi follows a
