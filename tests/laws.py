@@ -93,6 +93,25 @@ def check_flip_clock(lib_path=None):
     return pv > P_MIN, pv
 
 
+def check_flip_classes(lib_path=None, R=3000, each=333):
+    """The same dynamics on the six SISe3 compartments (three classes, S_j <->
+    I_j at rate 1 each): every class keeps S_j + I_j, so lambda = 6 * each
+    never changes and a node-day fires Poisson(6 each) transitions; the three
+    pairs of rates must all enter lambda and each draw must move an animal
+    within its own class."""
+    p = synth.flip_classes(n_nodes=1, S0=each, I0=each, n_days=2).with_replicates(R)
+    r = O.run(p, lib_path=lib_path)
+    lam = 6 * each
+    k = r["transitions"].ravel()
+    edges = np.arange(lam - 150, lam + 151, 10)
+    probs = np.diff(np.r_[0.0, stats.poisson.cdf(edges[1:] - 1, lam), 1.0])
+    counts = np.histogram(k, bins=np.r_[-1, edges[1:] - 0.5, 10**9])[0]
+    pv = gof(counts, probs)
+    u = r["u"].reshape(R, 6)
+    kept = (u[:, 0::2] + u[:, 1::2] == 2 * each).all()
+    return pv > P_MIN and kept, pv
+
+
 def check_max_transitions(lib_path=None, n_nodes=20, R=2000, half=100):
     """The longest chain of a day (the most transitions of one node): in the
     synthetic model with S = I = half per node, lambda = 2 half never changes,

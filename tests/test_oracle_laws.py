@@ -23,6 +23,12 @@ def test_flip_model_transitions_are_poisson_2000():
     assert ok, pv
 
 
+def test_three_class_flip_transitions_are_poisson():
+    # the six-compartment chain the critical-path probe times
+    ok, pv = laws.check_flip_classes()
+    assert ok, pv
+
+
 def test_longest_chain_of_a_day():
     ok, pv = laws.check_max_transitions()
     assert ok, pv
