@@ -1993,6 +1993,50 @@ __device__ __forceinline__ void slot_event(const Model &m, const DevState &s, co
                                            unsigned long long *status, const uint64_t *pre) {
     const int kind = (int)(meta & kEvKindMask);
     const uint32_t mask = (meta >> 2) & 0xffu;
+    // A selection of one or two compartments c0 < c1 with its draws computed
+    // ahead (every column of the farm model, every movement of up to six
+    // animals): the running sums of the walk below are 0 before c0, x[c0]
+    // from c0 to c1 and the total from c1 on, so a pick below the count left
+    // in c0 takes from c0 and any other from c1 (the same picks, counts and
+    // write order as the walk over all compartments).
+    const uint32_t rest = mask & (mask - 1u);
+    if (mask != 0u && (rest & (rest - 1u)) == 0u && n <= kPreDraws && (kind != SIM_ENTER || rest == 0u)) {
+        const int c0 = __builtin_ctz(mask);
+        const int c1 = rest ? __builtin_ctz(rest) : c0;
+        if (kind == SIM_ENTER) {
+            __hip_atomic_fetch_add(&xs[c0], n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            return;
+        }
+        const int32_t x0 = xs[c0], x1 = rest ? xs[c1] : 0;
+        const long long tot = (long long)x0 + (long long)x1;
+        if ((long long)n > tot) {
+            atomicMin(status, ((unsigned long long)(uint32_t)ev.gm[e] << 32) | (unsigned long long)(uint32_t)set);
+            return;
+        }
+        if (tot <= 0x7fffffffLL) {
+            int32_t t0 = 0, t1 = 0;
+            uint32_t left0 = (uint32_t)x0;
+#pragma unroll
+            for (int q = 0; q < kPreDraws; ++q) {
+                if (q >= n) break;
+                const uint32_t pick = (uint32_t)__umul64hi(pre[q], (uint64_t)(tot - q));
+                const int in0 = pick < left0 ? 1 : 0;
+                left0 -= (uint32_t)in0;
+                t0 += in0;
+                t1 += 1 - in0;
+            }
+            xs[c0] = x0 - t0;
+            if (rest) xs[c1] = x1 - t1;
+            if (kind == SIM_INTERNAL) {
+                if (t0) xs[shifted(smap, c0)] += t0;
+                if (t1) xs[shifted(smap, c1)] += t1;
+            } else if (kind == SIM_EXTERNAL) {
+                if (t0) __hip_atomic_fetch_add(&xd[shifted(smap, c0)], t0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (t1) __hip_atomic_fetch_add(&xd[shifted(smap, c1)], t1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+            return;
+        }
+    }
     if (kind == SIM_ENTER) {
 #pragma unroll
         for (int c = 0; c < NC; ++c)
