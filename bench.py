@@ -471,6 +471,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-replicates leg")
     ap.add_argument("--no-tune", action="store_true", help="default device options instead of the tuner's")
+    ap.add_argument("--no-chain-probe", action="store_true",
+                    help="leave out the critical-path probe (profiled runs: its launches share the day kernel)")
     ap.add_argument("--options", default="", metavar="JSON",
                     help="device options of the plain leg, e.g. '{\"tile_nodes\": 4}' (no tuner)")
     ap.add_argument("--instances", action="store_true", help="add the 64-uneven-instances leg (slow to generate)")
@@ -606,27 +608,30 @@ def main():
     # the workgroup walk for chains of 4096 expected attempts or more)
     hub_layout = p.n_nodes >= 8192 and p.n_rep == 1 and not best.get("tile_nodes")
     # the probe walks the workload's own rules: three S<->I classes on the
-    # six-compartment networks, one on the synthetic model
+    # six-compartment networks, one on the synthetic model (its launches are
+    # those of the step's own day kernel, so profiled runs leave it out)
     classes = 3 if p.n_comp == 6 else 1
-    if hub_layout:
-        short = chain_probe(P, synth, torch, half=1000, n_nodes=8192, classes=classes)
-        long_ = chain_probe(P, synth, torch, half=10000, days=20, n_nodes=8192, classes=classes)
-        per_day_us = np.where(most + 1 >= 4096, long_["us_per_attempt"], short["us_per_attempt"]) * (most + 1)
-        probes = [short, long_]
-    else:
-        one = chain_probe(P, synth, torch, classes=classes)
-        per_day_us = one["us_per_attempt"] * (most + 1)
-        probes = [one]
-    chain_ms = float(per_day_us.sum()) / 1e3
-    step_ms = total / args.steps * 1e3
-    critical = dict(longest_chain_attempts_per_step=int((most + 1).sum()),
-                    longest_chain_per_day=dict(max=int(most.max()), median=float(np.median(most)),
-                                               p99=float(np.percentile(most, 99))),
-                    us_per_attempt=[round(q["us_per_attempt"], 5) for q in probes],
-                    cycles_per_attempt=[round(q["cycles_per_attempt"], 1) for q in probes],
-                    chain_ms_per_step=round(chain_ms, 3), step_ms=round(step_ms, 3),
-                    frac=round(chain_ms / step_ms, 4), probe=[q["probe"] for q in probes],
-                    rule="longest chains of 4096 attempts or more at the second probe's rate" if hub_layout else "")
+    critical = None
+    if not args.no_chain_probe:
+        if hub_layout:
+            short = chain_probe(P, synth, torch, half=1000, n_nodes=8192, classes=classes)
+            long_ = chain_probe(P, synth, torch, half=10000, days=20, n_nodes=8192, classes=classes)
+            per_day_us = np.where(most + 1 >= 4096, long_["us_per_attempt"], short["us_per_attempt"]) * (most + 1)
+            probes = [short, long_]
+        else:
+            one = chain_probe(P, synth, torch, classes=classes)
+            per_day_us = one["us_per_attempt"] * (most + 1)
+            probes = [one]
+        chain_ms = float(per_day_us.sum()) / 1e3
+        step_ms = total / args.steps * 1e3
+        critical = dict(longest_chain_attempts_per_step=int((most + 1).sum()),
+                        longest_chain_per_day=dict(max=int(most.max()), median=float(np.median(most)),
+                                                   p99=float(np.percentile(most, 99))),
+                        us_per_attempt=[round(q["us_per_attempt"], 5) for q in probes],
+                        cycles_per_attempt=[round(q["cycles_per_attempt"], 1) for q in probes],
+                        chain_ms_per_step=round(chain_ms, 3), step_ms=round(step_ms, 3),
+                        frac=round(chain_ms / step_ms, 4), probe=[q["probe"] for q in probes],
+                        rule="longest chains of 4096 attempts or more at the second probe's rate" if hub_layout else "")
     roofline["binding"] = ("serial SSA chain of the day's largest herd (critical_path.frac of the step), "
                            "not HBM")
     tag = {"sise3-37k": "sq_37k", "sise3-1m": "sq_1m", "sise3-37k-u10": "sq_u10",
