@@ -441,36 +441,51 @@ int64_t order_nodes(const sim_problem *p, int layout, int64_t tile, int64_t heav
         for (int64_t c = 0; c < Nc; ++c) now[i] += p->u0[i * Nc + c];
         size[i] = now[i];
     }
-    // Ranges of events on host threads: each range replays its events from
-    // zero, keeping every node's net change and its highest running change at
-    // the points where the whole replay takes a node's maximum; the ranges
-    // then add up in order (16 bytes a node and range, at most 1 GiB in all).
+    // Long lists: ranges of events on host threads, each replaying its events
+    // from zero and keeping every node's net change and its highest running
+    // change at the points where the whole replay takes a node's maximum;
+    // the ranges then add up in order (16 bytes a node and range, at most
+    // 1 GiB in all). One range replays directly.
     const int64_t cap = std::max<int64_t>(1, (int64_t(1) << 30) / (16 * std::max<int64_t>(Nn, 1)));
     const int T = (int)std::min<int64_t>(host_threads(p->n_events), cap);
     std::vector<int64_t> cut(T + 1);
     for (int c = 0; c <= T; ++c) cut[c] = p->n_events * c / T;
-    std::vector<std::vector<int64_t>> delta(T), peak(T);
-    run_ranges(cut, [&](int c, int64_t b, int64_t end) {
-        std::vector<int64_t> &cum = delta[c], &top = peak[c];
-        cum.assign(Nn, 0);
-        top.assign(Nn, 0);
-        for (int64_t e = b; e < end; ++e) {
+    if (T == 1) {
+        for (int64_t e = 0; e < p->n_events; ++e) {
             const int32_t i = p->ev_node[e], k = p->ev_kind[e], n = p->ev_n[e];
-            if (k == SIM_ENTER) cum[i] += n;
-            if (k == SIM_EXIT || k == SIM_EXTERNAL) cum[i] -= n;
+            if (k == SIM_ENTER) now[i] += n;
+            if (k == SIM_EXIT || k == SIM_EXTERNAL) now[i] -= n;
             if (k == SIM_EXTERNAL) {
                 const int32_t j = p->ev_dest[e];
-                cum[j] += n;
-                top[j] = std::max(top[j], cum[j]);
+                now[j] += n;
+                size[j] = std::max(size[j], now[j]);
             }
-            top[i] = std::max(top[i], cum[i]);
+            size[i] = std::max(size[i], now[i]);
         }
-    });
-    for (int c = 0; c < T; ++c)
-        for (int64_t i = 0; i < Nn; ++i) {
-            size[i] = std::max(size[i], now[i] + peak[c][i]);
-            now[i] += delta[c][i];
-        }
+    } else {
+        std::vector<std::vector<int64_t>> delta(T), peak(T);
+        run_ranges(cut, [&](int c, int64_t b, int64_t end) {
+            std::vector<int64_t> &cum = delta[c], &top = peak[c];
+            cum.assign(Nn, 0);
+            top.assign(Nn, 0);
+            for (int64_t e = b; e < end; ++e) {
+                const int32_t i = p->ev_node[e], k = p->ev_kind[e], n = p->ev_n[e];
+                if (k == SIM_ENTER) cum[i] += n;
+                if (k == SIM_EXIT || k == SIM_EXTERNAL) cum[i] -= n;
+                if (k == SIM_EXTERNAL) {
+                    const int32_t j = p->ev_dest[e];
+                    cum[j] += n;
+                    top[j] = std::max(top[j], cum[j]);
+                }
+                top[i] = std::max(top[i], cum[i]);
+            }
+        });
+        for (int c = 0; c < T; ++c)
+            for (int64_t i = 0; i < Nn; ++i) {
+                size[i] = std::max(size[i], now[i] + peak[c][i]);
+                now[i] += delta[c][i];
+            }
+    }
     std::vector<int32_t> rank(Nn);
     for (int64_t i = 0; i < Nn; ++i) rank[i] = (int32_t)i;
     std::stable_sort(rank.begin(), rank.end(), [&](int32_t a, int32_t b) { return size[a] > size[b]; });
