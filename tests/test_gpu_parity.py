@@ -6,7 +6,7 @@ import os
 import numpy as np
 import pytest
 
-from farmnet import ENTER, EXIT, EXTERNAL, synth
+from farmnet import ENTER, EXIT, EXTERNAL, INTERNAL, synth
 from oracle import oracle as O
 import paper_1502_02908_amd as P
 
@@ -133,6 +133,36 @@ def test_deterministic_events_and_order():
     p = synth.events_only(u0, ev, n_days=2)
     g = gpu_run(p)
     assert g["u"][0].tolist() == [[2, 0], [0, 0], [5, 0]]
+
+
+def test_event_levels_in_lds_take_every_selection_and_size():
+    # events drawn after an addition at their node sit past level 1, so they
+    # run in the day's LDS levels: selections of one, two and all six
+    # compartments, moves of up to twelve animals (past the six draws computed
+    # ahead), shifts on internal and external transfers, and runs of one
+    # node's exit, internal transfer and entry; all against the oracle
+    rng = np.random.default_rng(41)
+    n_nodes = 64
+    u0 = rng.integers(100, 300, size=(n_nodes, 6))
+    plan = [  # external (select, shift, n), exit (select, n), internal n, entry n
+        ((1, 0, 3), (4, 2), 7, 1),
+        ((2, 1, 9), (1, 8), 3, 4),
+        ((4, -1, 12), (2, 11), 1, 20),
+        ((3, -1, 5), (3, 4), 10, 2),
+    ]
+    ev = []
+    for d in range(3):
+        for i in range(0, n_nodes, 2):
+            (sel_e, sh_e, n_e), (sel_x, n_x), n_i, n_en = plan[(i // 2) % 4]
+            src = (i + 1 + 2 * d) % n_nodes
+            ev += [(d, EXTERNAL, src, i, n_e, sel_e, sh_e), (d, EXIT, i, -1, n_x, sel_x, -1),
+                   (d, INTERNAL, i, -1, n_i, 1, 0), (d, ENTER, i, -1, n_en, 0, -1)]
+    p = synth.events_only(u0, ev, n_days=3, model="sise3")
+    E = np.concatenate([p.E, np.ones((6, 1), np.int32)], axis=1)  # select 4: every compartment
+    p.E = np.ascontiguousarray(E, np.int32)
+    g, o = both(p)
+    assert_parity(g, o)
+    assert g["levels"] == (6, 2)  # each day: the external transfers, then the runs
 
 
 def test_infeasible_event_reports_smallest_index():
