@@ -34,6 +34,7 @@
 #include <new>
 #include <string>
 #include <thread>
+#include <utility>
 #include <vector>
 
 #include "../../include/episim.h"
@@ -486,9 +487,12 @@ int64_t order_nodes(const sim_problem *p, int layout, int64_t tile, int64_t heav
                 now[i] += delta[c][i];
             }
     }
+    // largest herd first, equal sizes by node number (a stable sort by size)
+    std::vector<std::pair<int64_t, int32_t>> by_size(Nn);
+    for (int64_t i = 0; i < Nn; ++i) by_size[i] = {-size[i], (int32_t)i};
+    std::sort(by_size.begin(), by_size.end());
     std::vector<int32_t> rank(Nn);
-    for (int64_t i = 0; i < Nn; ++i) rank[i] = (int32_t)i;
-    std::stable_sort(rank.begin(), rank.end(), [&](int32_t a, int32_t b) { return size[a] > size[b]; });
+    for (int64_t i = 0; i < Nn; ++i) rank[i] = by_size[i].second;
     const int64_t G = unit_nodes(layout, tile);
     const int64_t hv = layout == LAYOUT_TILE ? std::min(heavy, Nn) : 0;
     const int64_t hv_span = ((hv + G - 1) / G) * G;
@@ -909,36 +913,55 @@ int build_packed(const sim_problem *const *ps, int32_t n, int32_t events_mode, P
     pk->ev_slot_src.assign(E, -1);
     pk->ev_slot_dst.assign(E, -1);
     if (pk->RL == 1 && events_mode == SIM_EVENTS_LEVELS && n_slots == 0) {
-        std::vector<int32_t> stamp(pk->Np, -1), slot_of(pk->Np, 0);
-        for (int32_t d = 0; d < pk->D; ++d) {
-            const int64_t tb = pk->lvl_off[pk->lvl_ptr[d]], te = pk->lvl_off[pk->lvl_ptr[d + 1]];
-            const size_t start = pk->slot_pos.size();
-            bool ok = te > tb && pk->task_off[te] - pk->task_off[tb] <= kDayEventCap &&
-                      pk->lvl_ptr[d + 1] - pk->lvl_ptr[d] <= kDayLevelCap;
-            auto slot = [&](int32_t pos) {
-                if (stamp[pos] != d) {
-                    stamp[pos] = d;
-                    slot_of[pos] = (int32_t)(pk->slot_pos.size() - start);
-                    pk->slot_pos.push_back(pos);
-                    const int32_t inst = pk->inst[pos];
-                    pk->slot_key.push_back(pk->seed[inst]);
-                    pk->slot_key.push_back(pk->repid[(size_t)inst * pk->R]);
-                    pk->slot_key.push_back((uint32_t)(inst * pk->R));
+        // days are independent: ranges of days on host threads, each with its
+        // own slot lists (slot numbers count from 0 in every day) and its own
+        // node stamps (8 bytes a position and range, at most 1 GiB in all),
+        // joined in day order
+        const int64_t cap = std::max<int64_t>(1, (int64_t(1) << 30) / (8 * std::max<int64_t>(pk->Np, 1)));
+        const int T = (int)std::min<int64_t>(std::min<int64_t>(host_threads(E), cap), std::max(pk->D, 1));
+        std::vector<int64_t> dcut(T + 1);
+        for (int c = 0; c <= T; ++c) dcut[c] = (int64_t)pk->D * c / T;
+        std::vector<std::vector<int32_t>> pos_r(T);
+        std::vector<std::vector<uint32_t>> key_r(T);
+        run_ranges(dcut, [&](int c, int64_t d0, int64_t d1) {
+            std::vector<int32_t> stamp(pk->Np, -1), slot_of(pk->Np, 0);
+            std::vector<int32_t> &sp = pos_r[c];
+            std::vector<uint32_t> &sk = key_r[c];
+            for (int32_t d = (int32_t)d0; d < d1; ++d) {
+                const int64_t tb = pk->lvl_off[pk->lvl_ptr[d]], te = pk->lvl_off[pk->lvl_ptr[d + 1]];
+                const size_t start = sp.size();
+                bool ok = te > tb && pk->task_off[te] - pk->task_off[tb] <= kDayEventCap &&
+                          pk->lvl_ptr[d + 1] - pk->lvl_ptr[d] <= kDayLevelCap;
+                auto slot = [&](int32_t pos) {
+                    if (stamp[pos] != d) {
+                        stamp[pos] = d;
+                        slot_of[pos] = (int32_t)(sp.size() - start);
+                        sp.push_back(pos);
+                        const int32_t inst = pk->inst[pos];
+                        sk.push_back(pk->seed[inst]);
+                        sk.push_back(pk->repid[(size_t)inst * pk->R]);
+                        sk.push_back((uint32_t)(inst * pk->R));
+                    }
+                    return slot_of[pos];
+                };
+                for (int64_t t = tb; ok && t < te; ++t)
+                    for (int64_t e = pk->task_off[t]; e < pk->task_off[t + 1]; ++e) {
+                        pk->ev_slot_src[e] = slot(pk->enode[e]);
+                        if ((pk->emeta[e] & 3u) == (uint32_t)SIM_EXTERNAL) pk->ev_slot_dst[e] = slot(pk->edest[e]);
+                    }
+                if (ok && sp.size() - start > (size_t)kDaySlotCap) ok = false;
+                if (!ok) {
+                    sp.resize(start);
+                    sk.resize(3 * start);
+                    for (int64_t e = pk->task_off[tb]; e < pk->task_off[te]; ++e) pk->ev_slot_src[e] = pk->ev_slot_dst[e] = -1;
                 }
-                return slot_of[pos];
-            };
-            for (int64_t t = tb; ok && t < te; ++t)
-                for (int64_t e = pk->task_off[t]; e < pk->task_off[t + 1]; ++e) {
-                    pk->ev_slot_src[e] = slot(pk->enode[e]);
-                    if ((pk->emeta[e] & 3u) == (uint32_t)SIM_EXTERNAL) pk->ev_slot_dst[e] = slot(pk->edest[e]);
-                }
-            if (ok && pk->slot_pos.size() - start > (size_t)kDaySlotCap) ok = false;
-            if (!ok) {
-                pk->slot_pos.resize(start);
-                pk->slot_key.resize(3 * start);
-                for (int64_t e = pk->task_off[tb]; e < pk->task_off[te]; ++e) pk->ev_slot_src[e] = pk->ev_slot_dst[e] = -1;
+                pk->day_slot_off[d + 1] = (int32_t)(sp.size() - start);  // the day's count for now
             }
-            pk->day_slot_off[d + 1] = (int32_t)pk->slot_pos.size();
+        });
+        for (int32_t d = 0; d < pk->D; ++d) pk->day_slot_off[d + 1] += pk->day_slot_off[d];
+        for (int c = 0; c < T; ++c) {
+            pk->slot_pos.insert(pk->slot_pos.end(), pos_r[c].begin(), pos_r[c].end());
+            pk->slot_key.insert(pk->slot_key.end(), key_r[c].begin(), key_r[c].end());
         }
     }
     // The slots of such a day by unit: the unit's day kernel hands their
